@@ -1,0 +1,198 @@
+"""Seeded synthetic inputs and parameter presets for the Ericksen-Leslie step.
+
+This module holds no arithmetic of the method itself: only a counter-based
+random generator, initial director fields (the seeded tilt and the skyrmion
+tube ansatz), Leslie-viscosity presets and the workload definitions.  Both the
+HIP path and the FP64 oracle take their inputs from here.
+
+Arrays use the external layout field[c][zf][y][x] over fluid layers (x
+fastest); zf = z - 1 when the walls z = 0 and z = nz - 1 are solid.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+# --------------------------------------------------------------------------
+# Counter-based generator: SplitMix64 (Steele, Lea and Flood, OOPSLA 2014),
+# evaluated at counter value `index` of the stream keyed by (seed, stream).
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, stream: int, index: np.ndarray) -> np.ndarray:
+    """64-bit outputs for counters `index` (uint64 array) of stream (seed, stream)."""
+    with np.errstate(over="ignore"):
+        key = np.uint64((seed * 0x632BE59BD9B4E019 + stream * 0x8CB92BA72F3D8DD7) % (1 << 64))
+        z = key + (np.asarray(index, dtype=np.uint64) + np.uint64(1)) * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        return z ^ (z >> np.uint64(31))
+
+
+def uniform01(seed: int, stream: int, count: int) -> np.ndarray:
+    """Doubles in [0, 1) from the top 53 bits of each output."""
+    bits = splitmix64(seed, stream, np.arange(count, dtype=np.uint64))
+    return (bits >> np.uint64(11)).astype(np.float64) * (1.0 / float(1 << 53))
+
+
+# --------------------------------------------------------------------------
+# Leslie viscosities of the paper's material table (lattice units), MBBA-like.
+TABLE1_ALPHA = (0.0373, -0.4496, -0.0203, 0.9318, 0.3084, -0.1617)
+
+
+@dataclass(frozen=True)
+class Material:
+    """Leslie viscosities, BGK tau and the explicit alpha4' of the force."""
+    alpha: tuple
+    tau: float
+    alpha4p: float = 0.0
+
+
+def set_a() -> Material:
+    """Table-1 ratios scaled so that the LBM viscosity carries alpha4 at tau = 0.8:
+    alpha4 = 2 rho c_s^2 (tau - 1/2) = 0.2, hence every alpha is multiplied by 0.2/0.9318."""
+    s = 0.2 / TABLE1_ALPHA[3]
+    return Material(alpha=tuple(a * s for a in TABLE1_ALPHA), tau=0.8, alpha4p=0.0)
+
+
+def set_b() -> Material:
+    """Table-1 viscosities; tau chosen so that 2 rho c_s^2 (tau - 1/2) = alpha4."""
+    return Material(alpha=TABLE1_ALPHA, tau=0.5 + 1.5 * TABLE1_ALPHA[3], alpha4p=0.0)
+
+
+# --------------------------------------------------------------------------
+@dataclass
+class Problem:
+    """Plain description of one channel; the HIP binding and the oracle wrapper
+    each translate it into their own parameter structure."""
+    nx: int
+    ny: int
+    nz: int
+    tau: float = 0.8
+    g: tuple = (0.0, 0.0, 0.0)
+    K: float = 0.0
+    q0: float = 0.0
+    W0: float = 0.0
+    alpha: tuple = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0)
+    alpha4p: float = 0.0
+    fd_ratio: int = 1
+    periodic_z: bool = False
+    renorm_predictor: bool = True
+    coupling: bool = True
+
+    @property
+    def nzf(self) -> int:
+        return self.nz if self.periodic_z else self.nz - 2
+
+    @property
+    def fluid_nodes(self) -> int:
+        return self.nx * self.ny * self.nzf
+
+    def shape(self, ncomp: int):
+        return (ncomp, self.nzf, self.ny, self.nx)
+
+    def with_(self, **kw) -> "Problem":
+        return replace(self, **kw)
+
+
+def channel(nx, ny, nz, material: Material, **kw) -> Problem:
+    return Problem(nx=nx, ny=ny, nz=nz, tau=material.tau, alpha=tuple(material.alpha),
+                   alpha4p=material.alpha4p, **kw)
+
+
+# --------------------------------------------------------------------------
+# Initial director fields.
+
+def director_tilt(prob: Problem, seed: int, amplitude: float = 0.05) -> np.ndarray:
+    """z-hat with a seeded tilt: theta_x, theta_y ~ U(-amplitude, amplitude) rad per
+    fluid node, n = (tan theta_x, tan theta_y, 1)/|.|."""
+    nf = prob.fluid_nodes
+    tx = (2.0 * uniform01(seed, 1, nf) - 1.0) * amplitude
+    ty = (2.0 * uniform01(seed, 2, nf) - 1.0) * amplitude
+    v = np.stack([np.tan(tx), np.tan(ty), np.ones(nf)])
+    v /= np.sqrt((v * v).sum(axis=0))
+    return v.reshape(prob.shape(3))
+
+
+def director_tubes(prob: Problem, centres, radius: float, z_modulated: bool = False) -> np.ndarray:
+    """Skyrmion-tube ansatz around each (xc, yc): polar angle
+    theta(r) = pi (1 - r/R) for r < R (0 outside), azimuth phi + pi/2, uniform in z
+    (or, with z_modulated, theta scaled by sin(pi (z - 1/2)/(nz - 2)) so that it
+    vanishes at the walls).  r is the periodic distance to the nearest centre."""
+    nzf, ny, nx = prob.nzf, prob.ny, prob.nx
+    X, Y = np.meshgrid(np.arange(nx, dtype=np.float64), np.arange(ny, dtype=np.float64))
+    best_r = np.full((ny, nx), np.inf)
+    best_dx = np.zeros((ny, nx))
+    best_dy = np.zeros((ny, nx))
+    for (xc, yc) in centres:
+        dx = (X - xc + nx / 2.0) % nx - nx / 2.0
+        dy = (Y - yc + ny / 2.0) % ny - ny / 2.0
+        r = np.hypot(dx, dy)
+        closer = r < best_r
+        best_r = np.where(closer, r, best_r)
+        best_dx = np.where(closer, dx, best_dx)
+        best_dy = np.where(closer, dy, best_dy)
+    theta2d = np.where(best_r < radius, math.pi * (1.0 - best_r / radius), 0.0)
+    phi = np.arctan2(best_dy, best_dx) + math.pi / 2.0
+    out = np.zeros((3, nzf, ny, nx))
+    for zf in range(nzf):
+        if z_modulated and not prob.periodic_z:
+            z = zf + 1
+            theta = theta2d * math.sin(math.pi * (z - 0.5) / (prob.nz - 2))
+        else:
+            theta = theta2d
+        out[0, zf] = np.sin(theta) * np.cos(phi)
+        out[1, zf] = np.sin(theta) * np.sin(phi)
+        out[2, zf] = np.cos(theta)
+    return out
+
+
+def place_tubes(nx: int, ny: int, count: int, radius: float, seed: int, stream: int = 7,
+                max_tries: int = 2000):
+    """Rejection-place up to `count` centres with periodic separation >= 2R."""
+    u = uniform01(seed, stream, 2 * max_tries)
+    centres = []
+    for k in range(max_tries):
+        if len(centres) == count:
+            break
+        c = (u[2 * k] * nx, u[2 * k + 1] * ny)
+        ok = True
+        for (xc, yc) in centres:
+            dx = (c[0] - xc + nx / 2.0) % nx - nx / 2.0
+            dy = (c[1] - yc + ny / 2.0) % ny - ny / 2.0
+            if math.hypot(dx, dy) < 2.0 * radius:
+                ok = False
+                break
+        if ok:
+            centres.append(c)
+    return centres
+
+
+# --------------------------------------------------------------------------
+# The five workloads (lattice sizes include the two solid wall layers).
+
+def workload_c1(shifted_precision_note: str = "") -> tuple:
+    """Plain FP64 channel 24^3, tau 0.8, g_x = 1e-6, K = 0.01, r = 1, 200 steps,
+    seeded +-0.05 rad tilt (seed 1)."""
+    prob = channel(24, 24, 24, set_a(), g=(1e-6, 0.0, 0.0), K=0.01, fd_ratio=1)
+    return prob, director_tilt(prob, seed=1), 200
+
+
+def workload_c2(gx: float = 1e-6, r: int = 10, K: float = 5e-4) -> tuple:
+    """Precision study channel 128x128x64 (tau 0.8, SET_A), seed 2, 20000 steps.
+    K = 5e-4 keeps the explicit director update stable up to r = 20."""
+    prob = channel(128, 128, 64, set_a(), g=(gx, 0.0, 0.0), K=K, fd_ratio=r)
+    return prob, director_tilt(prob, seed=2), 20000
+
+
+def workload_c3(r: int = 10) -> tuple:
+    """Single skyrmion tube 256x256x48 (SET_B, K = 5e-3, pitch 32), g_x = 5e-6,
+    tube of radius p/2 = 16 at the centre, 100000 steps."""
+    prob = channel(256, 256, 48, set_b(), g=(5e-6, 0.0, 0.0), K=5e-3, q0=2.0 * math.pi / 32.0,
+                   fd_ratio=r)
+    return prob, director_tubes(prob, [(128.0, 128.0)], 16.0), 100000
