@@ -1,0 +1,201 @@
+/*
+ * el.h -- C ABI of libel.so: the per-time-step hot path of the hybrid
+ * lattice-Boltzmann / finite-difference Ericksen-Leslie solver of Amaral,
+ * Sedahmed, Telo da Gama and Coelho, "Efficient single-precision simulations
+ * of nematohydrodynamics" (arXiv 2503.06610), for AMD Instinct MI355X (gfx950).
+ *
+ * Paper passages are cited by section:
+ *   Sec. II A  Hydrodynamic equations  (Leslie stress, N, D, W, Frank energy,
+ *                                       director equation, molecular field)
+ *   Sec. II B  Finite-differences      (coupling force F^LC, central
+ *                                       differences, fluid-only gradients,
+ *                                       predictor-corrector)
+ *   Sec. II C  Lattice Boltzmann       (SRT LBE, equilibrium, D3Q19, moments,
+ *                                       Guo forcing, halfway bounce-back,
+ *                                       shifted distribution and its LBE)
+ *   Sec. II D  Hybrid method           (order of the steps, force held fixed
+ *                                       for dt_FD)
+ *   Sec. III   Results                 (error measure epsilon, per component)
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an int status (EL_OK or a negative code), never
+ *     throws and never aborts.  The message of the last failure on the
+ *     calling thread is returned by el_last_error().
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued asynchronously on it; no entry point synchronises
+ *     the host with the device.
+ *   - All device buffers are allocated and freed by the caller.  The library
+ *     never allocates device memory on the hot path and keeps no state
+ *     between calls apart from the caller-owned el_state.
+ *   - Layout: structure of arrays over FLUID nodes only, x fastest:
+ *       element (c, x, y, zf) of a field with C components lives at
+ *       c*N + x + nx*(y + ny*zf),  N = nx*ny*nzf,
+ *     where zf = z - 1 and nzf = nz - 2 with solid walls at z = 0 and
+ *     z = nz - 1 (halfway bounce-back, wall midway between the last fluid
+ *     and the solid layer), or zf = z and nzf = nz with EL_PERIODIC_Z.
+ *     Solid nodes are not stored: they hold n = z-hat, u = 0 and zero stress
+ *     (infinite homeotropic anchoring and no slip, Sec. II B).
+ *   - The storage type T of q, n, n_pred, dndt, u and F is double for
+ *     EL_F64*, float for EL_F32*; arithmetic is done in T.  Global sums
+ *     (observables, error norms) are always accumulated in double.
+ *   - D3Q19 order is fixed: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 =
+ *     (1,1,0),(-1,-1,0),(1,-1,0),(-1,1,0),(1,0,1),(-1,0,-1),(1,0,-1),
+ *     (-1,0,1),(0,1,1),(0,-1,-1),(0,1,-1),(0,-1,1); the opposite of an odd
+ *     direction i is i + 1.
+ *   - One el_state must not be used concurrently from two streams; distinct
+ *     states are independent (the library is re-entrant).
+ */
+#ifndef EL_H
+#define EL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EL_ABI_VERSION 1
+
+/* status codes */
+enum {
+    EL_OK = 0,
+    EL_EINVAL = -1,     /* bad argument: NULL pointer, sizes, flags */
+    EL_EUNSTABLE = -2,  /* parameters outside the stability bounds (see el_validate) */
+    EL_EDEVICE = -3,    /* a HIP call or kernel launch failed */
+    EL_ENAN = -4,       /* reserved: non-finite values are reported in el_obs.nonfinite */
+    EL_ENOMEM = -5      /* a caller buffer is too small */
+};
+
+/* precision variants: storage and arithmetic type, and whether q stores the
+ * shifted distribution g_i = f_i - w_i (rho0 = 1) of Sec. II C */
+enum { EL_F64 = 0, EL_F64_SHIFTED = 1, EL_F32 = 2, EL_F32_SHIFTED = 3 };
+
+/* flags */
+enum {
+    EL_PERIODIC_Z = 1,            /* no walls: z periodic (analytic test cases) */
+    EL_NO_COUPLING = 2,           /* F^LC held at zero: plain Guo-forced LBM */
+    EL_NO_RENORM_PREDICTOR = 4,   /* do not normalise the Heun predictor */
+    EL_ALLOW_UNSTABLE = 8         /* skip the stability checks of el_validate */
+};
+
+typedef struct {
+    int32_t nx, ny, nz;     /* lattice nodes; nz counts the two solid wall layers */
+    int32_t precision;      /* EL_F64 .. EL_F32_SHIFTED */
+    int32_t fd_ratio;       /* r = dt_FD / dt_LBM >= 1 (Sec. II D) */
+    int32_t flags;          /* EL_PERIODIC_Z | EL_NO_COUPLING | ... */
+    double tau;             /* BGK relaxation time > 1/2; nu = (tau - 1/2)/3 (Sec. II C) */
+    double g[3];            /* body acceleration; the force density is rho*g (Sec. II A) */
+    double K;               /* one-constant Frank elasticity */
+    double q0;              /* cholesteric wave number 2 pi / P */
+    double W0;              /* weak bulk anchoring along z (Sec. III A) */
+    double alpha[6];        /* Leslie viscosities alpha1..alpha6; alpha[3] (alpha4)
+                               is informational: the LBM carries it through tau */
+    double alpha4p;         /* alpha4' added to the finite-difference force (Sec. II B) */
+} el_params;
+
+/* Caller-owned device buffers of one lattice (sizes from el_buffer_bytes). */
+typedef struct {
+    void* q[2];         /* 19*N T each: distributions, ping-pong */
+    void* n;            /* 3*N T: director */
+    void* n_pred;       /* 3*N T: predictor n^P */
+    void* dndt;         /* 3*N T: (d_t n)_old of the predictor-corrector */
+    void* u;            /* 3*N T: velocity incl. F/(2 rho), written by el_moments */
+    void* F;            /* 3*N T: coupling force F^LC, held fixed between FD steps */
+    void* scratch;      /* el_buffer_bytes(p, EL_BUF_SCRATCH) bytes */
+    int32_t parity;     /* q[parity] holds the current distributions */
+    int32_t reserved;
+    int64_t step;       /* LBM steps taken since el_init_lattice */
+} el_state;
+
+enum { EL_BUF_Q = 0, EL_BUF_VEC3 = 1, EL_BUF_SCRATCH = 2 };
+
+/* FP64 observables (Sec. III error measures are in el_error_norms). */
+typedef struct {
+    double mass;            /* sum over fluid nodes of rho */
+    double mom[3];          /* sum over fluid nodes of sum_i e_i q_i */
+    double mom_phys[3];     /* mom + 1/2 sum of the total force rho g + F^LC */
+    double max_u;           /* max |u| */
+    double max_unit_dev;    /* max | |n| - 1 | */
+    double tube_weight;     /* sum of w = max(0, -n_z) */
+    double tube_centroid[2];/* periodic circular mean of (x, y) weighted by w */
+    double tube_cs[4];      /* sums of w cos, w sin of 2 pi x/nx and 2 pi y/ny */
+    int32_t nonfinite;      /* 1 if any q, n, u or F^LC is not finite */
+    int32_t reserved;
+} el_obs;
+
+/* Library version (EL_ABI_VERSION). */
+int el_version(void);
+
+/* Human-readable text of a status code; static storage. */
+const char* el_strerror(int status);
+
+/* Detail of the last failure on the calling thread; static thread-local storage. */
+const char* el_last_error(void);
+
+/* Bytes the caller must allocate: EL_BUF_Q for each of q[0], q[1];
+ * EL_BUF_VEC3 for each of n, n_pred, dndt, u, F; EL_BUF_SCRATCH for scratch.
+ * Returns 0 for invalid parameters. */
+size_t el_buffer_bytes(const el_params* p, int32_t which);
+
+/* Checks the parameters.  EL_EINVAL: sizes (nx, ny >= 3; nz >= 4, or >= 3
+ * with EL_PERIODIC_Z), tau <= 1/2, r < 1, gamma1 = alpha3 - alpha2 <= 0 with
+ * coupling, unknown precision or flags.  EL_EUNSTABLE (unless
+ * EL_ALLOW_UNSTABLE): r * 12 K / gamma1 > 2 (the explicit Heun step on the
+ * compact Laplacian), or a Mach estimate |g| H^2/(8 nu) * sqrt(3) > 0.1. */
+int el_validate(const el_params* p);
+
+/* Initialisation (Sec. II D, first step): q = rest state (0 when shifted,
+ * w_i otherwise), n = n0 at fluid nodes, n_pred = n0, u = 0, dndt = 0,
+ * F^LC computed from n0 with u = 0, parity = 0, step = 0.
+ * n0: device, 3*N T in the layout above, not modified (may alias s->n). */
+int el_init_lattice(const el_params* p, el_state* s, const void* n0, void* stream);
+
+/* Optional warm start: q = equilibrium at rho = 1 and velocity u0 (device,
+ * 3*N T); then u is recomputed from q and F^LC. */
+int el_init_flow(const el_params* p, el_state* s, const void* u0, void* stream);
+
+/* nsteps LBM steps (Sec. II C): per fluid node the moments rho - 1 = sum q,
+ * u = (sum e q + F/2)/rho with F = rho g + F^LC (F^LC held fixed, Sec. II D),
+ * BGK collision toward the (shifted) equilibrium with the Guo source,
+ * streaming, halfway bounce-back at the walls.  q[parity] is read, the other
+ * buffer written, parity flips every step, step += nsteps.  With write_u != 0
+ * u is recomputed after the last step (el_moments). */
+int el_step_lbm(const el_params* p, el_state* s, int32_t nsteps, int32_t write_u, void* stream);
+
+/* Moments of the current q with the current F^LC: u = (sum e q + F/2)/rho. */
+int el_moments(const el_params* p, el_state* s, void* stream);
+
+/* One finite-difference step of dt_FD = r (Sec. II B): the predictor-corrector
+ * on the director equation (Sec. II A) with the current u, the predictor
+ * normalised unless EL_NO_RENORM_PREDICTOR, the corrector always normalised
+ * to |n| = 1; then F^LC = d_b sigma_ab of the Leslie + elastic stress at the
+ * new director (skipped with EL_NO_COUPLING). */
+int el_step_director(const el_params* p, el_state* s, void* stream);
+
+/* Recompute F^LC from the current n and u only. */
+int el_force(const el_params* p, el_state* s, void* stream);
+
+/* The hybrid loop of Sec. II D for T more LBM steps: after every LBM step
+ * whose counter t satisfies t % r == 0, the moments, the predictor-corrector
+ * and the new force.  u is left holding the velocity of the last step. */
+int el_run(const el_params* p, el_state* s, int64_t T, void* stream);
+
+/* FP64 observables of the current state into out (device memory, one el_obs).
+ * Uses the first 128 KiB of s->scratch. */
+int el_observables(const el_params* p, const el_state* s, el_obs* out, void* stream);
+
+/* Error sums of a field a (device, ncomp*N T) against ref (device, ncomp*N
+ * double) over fluid nodes, into out (device, 4 + 2*ncomp doubles):
+ *   out[0] = sum |a - ref|^2, out[1] = sum |ref|^2           (relative L2)
+ *   out[2] = sum_n |a - ref|_2, out[3] = sum_n |ref|_2         (epsilon, Sec. III)
+ *   out[4 + 2c] = sum_n |a_c - ref_c|, out[5 + 2c] = sum_n |ref_c| (per component)
+ * ncomp is 1..3.  work: device scratch of at least 128 KiB (the start of an
+ * el_state's scratch buffer will do; it must not be in use by another call). */
+int el_error_norms(const el_params* p, const void* a, const double* ref, int32_t ncomp, void* work,
+                   double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

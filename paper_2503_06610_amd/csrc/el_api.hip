@@ -1,0 +1,435 @@
+// el_api.hip -- the C ABI of libel.so (declared in include/el.h): argument
+// validation, precision dispatch and the launch sequence of the hybrid step
+// (Sec. II D).  All device memory belongs to the caller.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "el.h"
+#include "el_common.hpp"
+#include "fd_kernels.hpp"
+#include "lbm_kernels.hpp"
+#include "reduce_kernels.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int check_launch(const char* what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(EL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return EL_OK;
+}
+
+constexpr size_t REDUCE_BYTES = (size_t)el::RED_MAX_BLOCKS * 16 * sizeof(double);
+constexpr int BLOCK = 256;
+
+bool is_f64(const el_params* p) { return p->precision == EL_F64 || p->precision == EL_F64_SHIFTED; }
+bool is_shifted(const el_params* p) { return p->precision == EL_F64_SHIFTED || p->precision == EL_F32_SHIFTED; }
+bool periodic_z(const el_params* p) { return (p->flags & EL_PERIODIC_Z) != 0; }
+bool coupling(const el_params* p) { return (p->flags & EL_NO_COUPLING) == 0; }
+
+int nzf_of(const el_params* p) { return periodic_z(p) ? p->nz : p->nz - 2; }
+
+el::Geom geom_of(const el_params* p)
+{
+    el::Geom g;
+    g.nx = p->nx;
+    g.ny = p->ny;
+    g.nzf = nzf_of(p);
+    g.periodic_z = periodic_z(p) ? 1 : 0;
+    g.N = p->nx * p->ny * g.nzf;
+    return g;
+}
+
+int basic_checks(const el_params* p)
+{
+    if (!p) return fail(EL_EINVAL, "params is NULL");
+    if (p->precision < EL_F64 || p->precision > EL_F32_SHIFTED)
+        return fail(EL_EINVAL, "unknown precision %d", p->precision);
+    if (p->flags & ~(EL_PERIODIC_Z | EL_NO_COUPLING | EL_NO_RENORM_PREDICTOR | EL_ALLOW_UNSTABLE))
+        return fail(EL_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->nx < 3 || p->ny < 3 || (periodic_z(p) ? p->nz < 3 : p->nz < 4))
+        return fail(EL_EINVAL, "lattice %dx%dx%d too small", p->nx, p->ny, p->nz);
+    const long long N = (long long)p->nx * p->ny * nzf_of(p);
+    if (N * 19 >= (1LL << 31)) return fail(EL_EINVAL, "lattice of %lld fluid nodes exceeds 32-bit offsets", N);
+    if (!(p->tau > 0.5)) return fail(EL_EINVAL, "tau = %g must exceed 1/2", p->tau);
+    if (p->fd_ratio < 1) return fail(EL_EINVAL, "fd_ratio = %d must be >= 1", p->fd_ratio);
+    const double gamma1 = p->alpha[2] - p->alpha[1];
+    if (!(gamma1 > 0.0)) return fail(EL_EINVAL, "gamma1 = alpha3 - alpha2 = %g must be positive", gamma1);
+    for (double v : {p->tau, p->g[0], p->g[1], p->g[2], p->K, p->q0, p->W0, p->alpha4p, p->alpha[0], p->alpha[1],
+                     p->alpha[2], p->alpha[3], p->alpha[4], p->alpha[5]})
+        if (!std::isfinite(v)) return fail(EL_EINVAL, "non-finite parameter");
+    return EL_OK;
+}
+
+int stability_checks(const el_params* p)
+{
+    if (p->flags & EL_ALLOW_UNSTABLE) return EL_OK;
+    const double gamma1 = p->alpha[2] - p->alpha[1];
+    const double heun = p->fd_ratio * 12.0 * std::fabs(p->K) / gamma1;
+    if (heun > 2.0)
+        return fail(EL_EUNSTABLE, "explicit director step unstable: r*12K/gamma1 = %g > 2", heun);
+    if (!periodic_z(p)) {
+        const double nu = (p->tau - 0.5) / 3.0;
+        const double H = p->nz - 2;
+        const double gmag = std::sqrt(p->g[0] * p->g[0] + p->g[1] * p->g[1] + p->g[2] * p->g[2]);
+        const double mach = gmag * H * H / (8.0 * nu) * std::sqrt(3.0);
+        if (mach > 0.1) return fail(EL_EUNSTABLE, "Poiseuille Mach estimate %g > 0.1", mach);
+    }
+    return EL_OK;
+}
+
+int state_checks(const el_params* p, const el_state* s)
+{
+    if (!s) return fail(EL_EINVAL, "state is NULL");
+    if (!s->q[0] || !s->q[1] || !s->n || !s->n_pred || !s->dndt || !s->u || !s->F || !s->scratch)
+        return fail(EL_EINVAL, "state has a NULL buffer");
+    if (s->parity != 0 && s->parity != 1) return fail(EL_EINVAL, "parity %d", s->parity);
+    (void)p;
+    return EL_OK;
+}
+
+int grid_for(int N) { return (N + BLOCK - 1) / BLOCK; }
+
+// --------------------------------------------------------------------------
+template <typename T>
+el::LbmArgs<T> lbm_args(const el_params* p)
+{
+    el::LbmArgs<T> a;
+    a.g = geom_of(p);
+    a.omega = T(1.0 / p->tau);
+    a.cS = T(1.0 - 0.5 / p->tau);
+    a.gx = T(p->g[0]);
+    a.gy = T(p->g[1]);
+    a.gz = T(p->g[2]);
+    a.coupling = coupling(p) ? 1 : 0;
+    return a;
+}
+
+template <typename T>
+el::FdArgs<T> fd_args(const el_params* p)
+{
+    el::FdArgs<T> a;
+    a.g = geom_of(p);
+    const double g1 = p->alpha[2] - p->alpha[1];
+    const double g2 = p->alpha[2] + p->alpha[1];
+    a.dt = T(p->fd_ratio);
+    a.K = T(p->K);
+    a.Kq0x2 = T(2.0 * p->K * p->q0);
+    a.Kq0 = T(p->K * p->q0);
+    a.W0 = T(p->W0);
+    a.inv_g1 = T(1.0 / g1);
+    a.g2_over_g1 = T(g2 / g1);
+    a.g2 = T(g2);
+    a.a1 = T(p->alpha[0]);
+    a.a2 = T(p->alpha[1]);
+    a.a3 = T(p->alpha[2]);
+    a.a4p = T(p->alpha4p);
+    a.a5 = T(p->alpha[4]);
+    a.a6 = T(p->alpha[5]);
+    a.renorm_predictor = (p->flags & EL_NO_RENORM_PREDICTOR) ? 0 : 1;
+    return a;
+}
+
+template <typename T, bool SHIFT>
+int launch_lbm_steps(const el_params* p, el_state* s, int nsteps, hipStream_t st)
+{
+    const el::LbmArgs<T> a = lbm_args<T>(p);
+    const int grid = grid_for(a.g.N);
+    for (int k = 0; k < nsteps; ++k) {
+        const T* qa = static_cast<const T*>(s->q[s->parity]);
+        T* qb = static_cast<T*>(s->q[1 - s->parity]);
+        hipLaunchKernelGGL((el::k_lbm_push<T, SHIFT>), dim3(grid), dim3(BLOCK), 0, st, qa, qb,
+                           static_cast<const T*>(s->F), a);
+        s->parity = 1 - s->parity;
+        s->step += 1;
+    }
+    return check_launch("k_lbm_push");
+}
+
+template <typename T, bool SHIFT>
+int launch_moments(const el_params* p, el_state* s, hipStream_t st)
+{
+    const el::LbmArgs<T> a = lbm_args<T>(p);
+    hipLaunchKernelGGL((el::k_moments<T, SHIFT>), dim3(grid_for(a.g.N)), dim3(BLOCK), 0, st,
+                       static_cast<const T*>(s->q[s->parity]), static_cast<const T*>(s->F), static_cast<T*>(s->u), a);
+    return check_launch("k_moments");
+}
+
+template <typename T>
+T* sigma_of(el_state* s)
+{
+    return reinterpret_cast<T*>(static_cast<char*>(s->scratch) + REDUCE_BYTES);
+}
+
+template <typename T>
+int launch_force(const el_params* p, el_state* s, hipStream_t st)
+{
+    const el::FdArgs<T> a = fd_args<T>(p);
+    const int grid = grid_for(a.g.N);
+    if (!coupling(p)) {
+        hipLaunchKernelGGL((el::k_fill<T>), dim3(grid_for(3 * a.g.N)), dim3(BLOCK), 0, st, static_cast<T*>(s->F),
+                           T(0), 3 * a.g.N);
+        return check_launch("clear F");
+    }
+    T* sig = sigma_of<T>(s);
+    hipLaunchKernelGGL((el::k_fd_stress<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
+                       static_cast<const T*>(s->u), sig, a);
+    hipLaunchKernelGGL((el::k_fd_divergence<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(sig),
+                       static_cast<T*>(s->F), a);
+    return check_launch("force kernels");
+}
+
+template <typename T>
+int launch_director(const el_params* p, el_state* s, hipStream_t st)
+{
+    const el::FdArgs<T> a = fd_args<T>(p);
+    const int grid = grid_for(a.g.N);
+    hipLaunchKernelGGL((el::k_fd_predictor<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
+                       static_cast<const T*>(s->u), static_cast<T*>(s->n_pred), static_cast<T*>(s->dndt), a);
+    hipLaunchKernelGGL((el::k_fd_corrector<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<T*>(s->n),
+                       static_cast<const T*>(s->n_pred), static_cast<const T*>(s->u),
+                       static_cast<const T*>(s->dndt), a);
+    int rc = check_launch("director kernels");
+    if (rc != EL_OK) return rc;
+    return launch_force<T>(p, s, st);
+}
+
+template <typename T, bool SHIFT>
+int init_impl(const el_params* p, el_state* s, const void* n0, hipStream_t st)
+{
+    const int N = geom_of(p).N;
+    const int grid = grid_for(N);
+    hipLaunchKernelGGL((el::k_rest<T, SHIFT>), dim3(grid), dim3(BLOCK), 0, st, static_cast<T*>(s->q[0]), N);
+    hipLaunchKernelGGL((el::k_fd_init<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(n0),
+                       static_cast<T*>(s->n), static_cast<T*>(s->n_pred), static_cast<T*>(s->dndt),
+                       static_cast<T*>(s->u), static_cast<T*>(s->F), N);
+    int rc = check_launch("init kernels");
+    if (rc != EL_OK) return rc;
+    s->parity = 0;
+    s->step = 0;
+    return launch_force<T>(p, s, st);
+}
+
+template <typename T, bool SHIFT>
+int init_flow_impl(const el_params* p, el_state* s, const void* u0, hipStream_t st)
+{
+    const int N = geom_of(p).N;
+    hipLaunchKernelGGL((el::k_equilibrium<T, SHIFT>), dim3(grid_for(N)), dim3(BLOCK), 0, st,
+                       static_cast<T*>(s->q[s->parity]), static_cast<const T*>(u0), N);
+    int rc = check_launch("k_equilibrium");
+    if (rc != EL_OK) return rc;
+    return launch_moments<T, SHIFT>(p, s, st);
+}
+
+template <typename T>
+int observables_impl(const el_params* p, const el_state* s, el_obs* out, hipStream_t st)
+{
+    el::ObsArgs<T> a;
+    a.g = geom_of(p);
+    a.shifted = is_shifted(p) ? 1 : 0;
+    a.coupling = coupling(p) ? 1 : 0;
+    a.gx = p->g[0];
+    a.gy = p->g[1];
+    a.gz = p->g[2];
+    int blocks = grid_for(a.g.N);
+    if (blocks > el::RED_MAX_BLOCKS) blocks = el::RED_MAX_BLOCKS;
+    double* partial = static_cast<double*>(s->scratch);
+    hipLaunchKernelGGL((el::k_obs_partial<T>), dim3(blocks), dim3(el::RED_THREADS), 0, st,
+                       static_cast<const T*>(s->q[s->parity]), static_cast<const T*>(s->n),
+                       static_cast<const T*>(s->u), static_cast<const T*>(s->F), partial, a);
+    hipLaunchKernelGGL(el::k_obs_final, dim3(1), dim3(el::RED_THREADS), 0, st, static_cast<const double*>(partial),
+                       blocks, out, p->nx, p->ny);
+    return check_launch("observables kernels");
+}
+
+template <typename T>
+int error_impl(const el_params* p, const void* a, const double* ref, int ncomp, void* work, double* out, hipStream_t st)
+{
+    const int N = geom_of(p).N;
+    int blocks = grid_for(N);
+    if (blocks > el::RED_MAX_BLOCKS) blocks = el::RED_MAX_BLOCKS;
+    double* partial = static_cast<double*>(work);
+    hipLaunchKernelGGL((el::k_err_partial<T>), dim3(blocks), dim3(el::RED_THREADS), 0, st, static_cast<const T*>(a),
+                       ref, ncomp, N, partial);
+    hipLaunchKernelGGL(el::k_err_final, dim3(1), dim3(el::RED_THREADS), 0, st, static_cast<const double*>(partial),
+                       blocks, 4 + 2 * ncomp, out);
+    return check_launch("error-norm kernels");
+}
+
+// Precision dispatch: F(T, SHIFT) instantiated for the four variants.
+#define EL_DISPATCH(p, CALL)                                   \
+    switch ((p)->precision) {                                  \
+    case EL_F64: { using T = double; constexpr bool SH = false; return CALL; } \
+    case EL_F64_SHIFTED: { using T = double; constexpr bool SH = true; return CALL; } \
+    case EL_F32: { using T = float; constexpr bool SH = false; return CALL; } \
+    default: { using T = float; constexpr bool SH = true; return CALL; } \
+    }
+
+}  // namespace
+
+// ==========================================================================
+extern "C" {
+
+int el_version(void) { return EL_ABI_VERSION; }
+
+const char* el_strerror(int status)
+{
+    switch (status) {
+    case EL_OK: return "ok";
+    case EL_EINVAL: return "invalid argument";
+    case EL_EUNSTABLE: return "parameters outside the stability bounds";
+    case EL_EDEVICE: return "device error";
+    case EL_ENAN: return "non-finite values";
+    case EL_ENOMEM: return "buffer too small";
+    default: return "unknown status";
+    }
+}
+
+const char* el_last_error(void) { return g_err; }
+
+size_t el_buffer_bytes(const el_params* p, int32_t which)
+{
+    if (basic_checks(p) != EL_OK) return 0;
+    const size_t N = (size_t)geom_of(p).N;
+    const size_t ts = is_f64(p) ? sizeof(double) : sizeof(float);
+    switch (which) {
+    case EL_BUF_Q: return 19 * N * ts;
+    case EL_BUF_VEC3: return 3 * N * ts;
+    case EL_BUF_SCRATCH: return REDUCE_BYTES + 9 * N * ts;
+    default: fail(EL_EINVAL, "unknown buffer kind %d", which); return 0;
+    }
+}
+
+int el_validate(const el_params* p)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    return stability_checks(p);
+}
+
+int el_init_lattice(const el_params* p, el_state* s, const void* n0, void* stream)
+{
+    int rc = el_validate(p);
+    if (rc != EL_OK) return rc;
+    if ((rc = state_checks(p, s)) != EL_OK) return rc;
+    if (!n0) return fail(EL_EINVAL, "n0 is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    EL_DISPATCH(p, (init_impl<T, SH>(p, s, n0, st)))
+}
+
+int el_init_flow(const el_params* p, el_state* s, const void* u0, void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if ((rc = state_checks(p, s)) != EL_OK) return rc;
+    if (!u0) return fail(EL_EINVAL, "u0 is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    EL_DISPATCH(p, (init_flow_impl<T, SH>(p, s, u0, st)))
+}
+
+int el_step_lbm(const el_params* p, el_state* s, int32_t nsteps, int32_t write_u, void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if ((rc = state_checks(p, s)) != EL_OK) return rc;
+    if (nsteps < 0) return fail(EL_EINVAL, "nsteps = %d", nsteps);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    switch (p->precision) {
+    case EL_F64: rc = launch_lbm_steps<double, false>(p, s, nsteps, st); break;
+    case EL_F64_SHIFTED: rc = launch_lbm_steps<double, true>(p, s, nsteps, st); break;
+    case EL_F32: rc = launch_lbm_steps<float, false>(p, s, nsteps, st); break;
+    default: rc = launch_lbm_steps<float, true>(p, s, nsteps, st); break;
+    }
+    if (rc != EL_OK || !write_u) return rc;
+    return el_moments(p, s, stream);
+}
+
+int el_moments(const el_params* p, el_state* s, void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if ((rc = state_checks(p, s)) != EL_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    EL_DISPATCH(p, (launch_moments<T, SH>(p, s, st)))
+}
+
+int el_step_director(const el_params* p, el_state* s, void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if ((rc = state_checks(p, s)) != EL_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (is_f64(p)) return launch_director<double>(p, s, st);
+    return launch_director<float>(p, s, st);
+}
+
+int el_force(const el_params* p, el_state* s, void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if ((rc = state_checks(p, s)) != EL_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (is_f64(p)) return launch_force<double>(p, s, st);
+    return launch_force<float>(p, s, st);
+}
+
+int el_run(const el_params* p, el_state* s, int64_t T, void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if ((rc = state_checks(p, s)) != EL_OK) return rc;
+    if (T < 0) return fail(EL_EINVAL, "T = %lld", (long long)T);
+    const int r = p->fd_ratio;
+    int64_t left = T;
+    while (left > 0) {
+        // LBM steps up to the next multiple of r (or the end)
+        int64_t to_fd = r - (s->step % r);
+        const int n = (int)(left < to_fd ? left : to_fd);
+        if ((rc = el_step_lbm(p, s, n, 0, stream)) != EL_OK) return rc;
+        left -= n;
+        if ((rc = el_moments(p, s, stream)) != EL_OK) return rc;
+        if (s->step % r == 0)
+            if ((rc = el_step_director(p, s, stream)) != EL_OK) return rc;
+    }
+    return EL_OK;
+}
+
+int el_observables(const el_params* p, const el_state* s, el_obs* out, void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if ((rc = state_checks(p, s)) != EL_OK) return rc;
+    if (!out) return fail(EL_EINVAL, "out is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (is_f64(p)) return observables_impl<double>(p, s, out, st);
+    return observables_impl<float>(p, s, out, st);
+}
+
+int el_error_norms(const el_params* p, const void* a, const double* ref, int32_t ncomp, void* work, double* out,
+                   void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if (!a || !ref || !work || !out) return fail(EL_EINVAL, "NULL pointer");
+    if (ncomp < 1 || ncomp > 3) return fail(EL_EINVAL, "ncomp = %d", ncomp);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (is_f64(p)) return error_impl<double>(p, a, ref, ncomp, work, out, st);
+    return error_impl<float>(p, a, ref, ncomp, work, out, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// el_common.hpp -- lattice constants, launch arguments and neighbour helpers
+// shared by the gfx950 kernels of libel.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace el {
+
+// D3Q19 velocity set (Sec. II C): rest, 6 face and 12 edge neighbours in the
+// order fixed by the C ABI; the opposite of an odd direction i is i + 1.
+__host__ __device__ constexpr int EX(int i)
+{
+    constexpr int v[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return v[i];
+}
+__host__ __device__ constexpr int EY(int i)
+{
+    constexpr int v[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return v[i];
+}
+__host__ __device__ constexpr int EZ(int i)
+{
+    constexpr int v[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    return v[i];
+}
+__host__ __device__ constexpr int OPP(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// Weights 1/3, 1/18, 1/36 by squared speed 0, 1, 2.
+template <typename T>
+__host__ __device__ constexpr T WGT(int i)
+{
+    return i == 0 ? T(1) / T(3) : (i <= 6 ? T(1) / T(18) : T(1) / T(36));
+}
+
+// Geometry of one channel: fluid layers only are stored.
+struct Geom {
+    int nx, ny, nzf;   // fluid nodes per axis
+    int periodic_z;    // 1: z wraps, 0: solid walls below zf = 0 and above zf = nzf-1
+    int N;             // nx*ny*nzf
+};
+
+// Neighbour indices of node (x, y, zf) along the three axes; a z neighbour
+// outside [0, nzf) is a solid wall node unless z is periodic.
+struct Nbr {
+    int c;                   // own index
+    int xm, xp, ym, yp, zm, zp;  // linear indices of the six face neighbours (valid when not wall)
+    bool wall_zm, wall_zp;
+};
+
+__device__ inline Nbr make_nbr(const Geom& g, int x, int y, int z)
+{
+    Nbr n;
+    const int row = g.nx, plane = g.nx * g.ny;
+    n.c = x + row * y + plane * z;
+    const int xm = (x == 0) ? g.nx - 1 : x - 1;
+    const int xp = (x == g.nx - 1) ? 0 : x + 1;
+    const int ym = (y == 0) ? g.ny - 1 : y - 1;
+    const int yp = (y == g.ny - 1) ? 0 : y + 1;
+    int zm = z - 1, zp = z + 1;
+    n.wall_zm = false;
+    n.wall_zp = false;
+    if (g.periodic_z) {
+        if (zm < 0) zm = g.nzf - 1;
+        if (zp == g.nzf) zp = 0;
+    } else {
+        n.wall_zm = (zm < 0);
+        n.wall_zp = (zp == g.nzf);
+        if (n.wall_zm) zm = 0;
+        if (n.wall_zp) zp = g.nzf - 1;
+    }
+    const int base = row * y + plane * z;
+    n.xm = xm + base;
+    n.xp = xp + base;
+    n.ym = x + row * ym + plane * z;
+    n.yp = x + row * yp + plane * z;
+    n.zm = x + row * y + plane * zm;
+    n.zp = x + row * y + plane * zp;
+    return n;
+}
+
+}  // namespace el

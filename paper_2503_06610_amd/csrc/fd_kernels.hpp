@@ -1,0 +1,284 @@
+// fd_kernels.hpp -- finite-difference director update (Heun predictor and
+// corrector) and the coupling force F^LC = d_b sigma_ab (Sec. II A, II B).
+//
+// Central differences on the 7-point stencil; x and y periodic; a z neighbour
+// beyond the fluid layers is a solid node with fixed values n = z-hat, u = 0
+// and zero stress (fluid-only gradients, infinite homeotropic anchoring).
+// One thread per fluid node; the stencil values of a node are gathered into
+// registers before any arithmetic.
+#pragma once
+
+#include "el_common.hpp"
+
+namespace el {
+
+template <typename T>
+struct FdArgs {
+    Geom g;
+    T dt;          // dt_FD = r
+    T K, Kq0x2, W0;  // K, 2 K q0, W0
+    T Kq0;         // K q0
+    T inv_g1;      // 1/gamma1
+    T g2_over_g1;  // gamma2/gamma1
+    T g2;          // gamma2
+    T a1, a2, a3, a4p, a5, a6;
+    int renorm_predictor;
+};
+
+// 7-point stencil of a 3-vector field: v[0] centre, v[1 + 2b] = minus side,
+// v[2 + 2b] = plus side along axis b.
+template <typename T>
+struct Stencil3 {
+    T v[7][3];
+};
+
+// kind 0: director (solid value z-hat), kind 1: velocity (solid value 0)
+template <typename T, int KIND>
+__device__ inline void gather3(const T* __restrict__ f, const Nbr& nb, size_t N, Stencil3<T>& s)
+{
+    const int idx[7] = {nb.c, nb.xm, nb.xp, nb.ym, nb.yp, nb.zm, nb.zp};
+#pragma unroll
+    for (int p = 0; p < 7; ++p) {
+        const bool wall = (p == 5 && nb.wall_zm) || (p == 6 && nb.wall_zp);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (wall)
+                s.v[p][c] = (KIND == 0 && c == 2) ? T(1) : T(0);
+            else
+                s.v[p][c] = f[c * N + idx[p]];
+        }
+    }
+}
+
+// G[b][g] = d_b m_g
+template <typename T>
+__device__ inline void grad(const Stencil3<T>& s, T (&G)[3][3])
+{
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) G[b][c] = T(0.5) * (s.v[2 + 2 * b][c] - s.v[1 + 2 * b][c]);
+}
+
+// Molecular field of the one-constant energy f = K/2 (d n)^2 + K q0 n.curl n
+// - W0/2 n_z^2: h = K lap n - 2 K q0 curl n + W0 n_z z-hat, compact Laplacian.
+template <typename T>
+__device__ inline void molecular_field(const Stencil3<T>& m, const T (&G)[3][3], const FdArgs<T>& a, T (&h)[3])
+{
+    const T curl[3] = {G[1][2] - G[2][1], G[2][0] - G[0][2], G[0][1] - G[1][0]};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const T lap = ((m.v[1][c] + m.v[2][c]) + (m.v[3][c] + m.v[4][c]) + (m.v[5][c] + m.v[6][c])) - T(6) * m.v[0][c];
+        h[c] = a.K * lap - a.Kq0x2 * curl[c];
+    }
+    h[2] += a.W0 * m.v[0][2];
+}
+
+// D_am = (d_a u_m + d_m u_a)/2 and W_am = (d_m u_a - d_a u_m)/2 from A[b][a] = d_b u_a.
+template <typename T>
+__device__ inline void flow_tensors(const Stencil3<T>& u, T (&D)[3][3], T (&W)[3][3])
+{
+    T A[3][3];
+    grad(u, A);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            D[i][j] = T(0.5) * (A[i][j] + A[j][i]);
+            W[i][j] = T(0.5) * (A[j][i] - A[i][j]);
+        }
+}
+
+// Director equation (Sec. II A):
+// d_t m_mu = h_mu/gamma1 - (gamma2/gamma1) m_a D_a,mu - u_g d_g m_mu + W_mu,g m_g
+template <typename T>
+__device__ inline void director_rhs(const Stencil3<T>& m, const Stencil3<T>& u, const FdArgs<T>& a, T (&out)[3])
+{
+    T G[3][3], h[3], D[3][3], W[3][3];
+    grad(m, G);
+    molecular_field(m, G, a, h);
+    flow_tensors(u, D, W);
+    const T* mc = m.v[0];
+    const T* uc = u.v[0];
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+        const T align = mc[0] * D[0][mu] + mc[1] * D[1][mu] + mc[2] * D[2][mu];
+        const T adv = uc[0] * G[0][mu] + uc[1] * G[1][mu] + uc[2] * G[2][mu];
+        const T rot = W[mu][0] * mc[0] + W[mu][1] * mc[1] + W[mu][2] * mc[2];
+        out[mu] = h[mu] * a.inv_g1 - a.g2_over_g1 * align - adv + rot;
+    }
+}
+
+template <typename T>
+__device__ inline void normalise(T (&v)[3])
+{
+    const T inv = T(1) / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] *= inv;
+    v[1] *= inv;
+    v[2] *= inv;
+}
+
+__device__ inline void node_coords(const Geom& g, int k, int& x, int& y, int& z)
+{
+    x = k % g.nx;
+    const int t = k / g.nx;
+    y = t % g.ny;
+    z = t / g.ny;
+}
+
+// Predictor: (d_t n)_old = RHS(n); n^P = n + dt (d_t n)_old, normalised when asked.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fd_predictor(const T* __restrict__ n, const T* __restrict__ u,
+                                                     T* __restrict__ nP, T* __restrict__ dndt, FdArgs<T> a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.g.N) return;
+    int x, y, z;
+    node_coords(a.g, k, x, y, z);
+    const Nbr nb = make_nbr(a.g, x, y, z);
+    const size_t N = (size_t)a.g.N;
+    Stencil3<T> m, uu;
+    gather3<T, 0>(n, nb, N, m);
+    gather3<T, 1>(u, nb, N, uu);
+    T r[3];
+    director_rhs(m, uu, a, r);
+    T v[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        dndt[c * N + k] = r[c];
+        v[c] = m.v[0][c] + a.dt * r[c];
+    }
+    if (a.renorm_predictor) normalise(v);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) nP[c * N + k] = v[c];
+}
+
+// Corrector: n <- n + dt/2 [(d_t n)_old + RHS(n^P)], normalised to |n| = 1.
+// n is read only at the own node, so the update is done in place.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fd_corrector(T* __restrict__ n, const T* __restrict__ nP,
+                                                     const T* __restrict__ u, const T* __restrict__ dndt,
+                                                     FdArgs<T> a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.g.N) return;
+    int x, y, z;
+    node_coords(a.g, k, x, y, z);
+    const Nbr nb = make_nbr(a.g, x, y, z);
+    const size_t N = (size_t)a.g.N;
+    Stencil3<T> m, uu;
+    gather3<T, 0>(nP, nb, N, m);
+    gather3<T, 1>(u, nb, N, uu);
+    T r[3];
+    director_rhs(m, uu, a, r);
+    T v[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = n[c * N + k] + T(0.5) * a.dt * (dndt[c * N + k] + r[c]);
+    normalise(v);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) n[c * N + k] = v[c];
+}
+
+// Leslie + elastic stress at one fluid node (Sec. II B):
+// sigma_ab = a1 n_a n_b (n.D.n) + a2 n_b N_a + a3 n_a N_b + a4' D_ab
+//          + a5 n_b (Dn)_a + a6 n_a (Dn)_b - d_a n_g Pi_bg,
+// N = (h - gamma2 D n)/gamma1, Pi_bg = K d_b n_g + K q0 eps_{m b g} n_m.
+template <typename T>
+__device__ inline void stress(const Stencil3<T>& m, const Stencil3<T>& u, const FdArgs<T>& a, T (&sig)[3][3])
+{
+    T G[3][3], h[3], D[3][3], W[3][3];
+    grad(m, G);
+    molecular_field(m, G, a, h);
+    flow_tensors(u, D, W);
+    const T* n = m.v[0];
+    T Dn[3], N[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Dn[i] = D[i][0] * n[0] + D[i][1] * n[1] + D[i][2] * n[2];
+    const T nDn = n[0] * Dn[0] + n[1] * Dn[1] + n[2] * Dn[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) N[i] = (h[i] - a.g2 * Dn[i]) * a.inv_g1;
+    // chiral part of Pi: eps_{m b g} n_m
+    const T ch[3][3] = {{T(0), n[2], -n[1]}, {-n[2], T(0), n[0]}, {n[1], -n[0], T(0)}};
+    T Pi[3][3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Pi[b][c] = a.K * G[b][c] + a.Kq0 * ch[b][c];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const T el = G[i][0] * Pi[j][0] + G[i][1] * Pi[j][1] + G[i][2] * Pi[j][2];
+            sig[i][j] = a.a1 * n[i] * n[j] * nDn + a.a2 * n[j] * N[i] + a.a3 * n[i] * N[j] + a.a4p * D[i][j] +
+                        a.a5 * n[j] * Dn[i] + a.a6 * n[i] * Dn[j] - el;
+        }
+}
+
+// sigma at every fluid node into sig (9 components, index a*3 + b).
+template <typename T>
+__global__ void __launch_bounds__(256) k_fd_stress(const T* __restrict__ n, const T* __restrict__ u,
+                                                  T* __restrict__ sig, FdArgs<T> a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.g.N) return;
+    int x, y, z;
+    node_coords(a.g, k, x, y, z);
+    const Nbr nb = make_nbr(a.g, x, y, z);
+    const size_t N = (size_t)a.g.N;
+    Stencil3<T> m, uu;
+    gather3<T, 0>(n, nb, N, m);
+    gather3<T, 1>(u, nb, N, uu);
+    T s[3][3];
+    stress(m, uu, a, s);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) sig[(i * 3 + j) * N + k] = s[i][j];
+}
+
+// F^LC_a = sum_b [sigma_ab(x + b) - sigma_ab(x - b)]/2, zero stress at walls.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fd_divergence(const T* __restrict__ sig, T* __restrict__ F, FdArgs<T> a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.g.N) return;
+    int x, y, z;
+    node_coords(a.g, k, x, y, z);
+    const Nbr nb = make_nbr(a.g, x, y, z);
+    const size_t N = (size_t)a.g.N;
+    const int plus[3] = {nb.xp, nb.yp, nb.zp};
+    const int minus[3] = {nb.xm, nb.ym, nb.zm};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        T div = T(0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const T* s = sig + (i * 3 + b) * N;
+            const T sp = (b == 2 && nb.wall_zp) ? T(0) : s[plus[b]];
+            const T sm = (b == 2 && nb.wall_zm) ? T(0) : s[minus[b]];
+            div += T(0.5) * (sp - sm);
+        }
+        F[i * N + k] = div;
+    }
+}
+
+// Copies of the initial director and zeroed fields.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fd_init(const T* n0, T* n, T* __restrict__ nP,
+                                                T* __restrict__ dndt, T* __restrict__ u, T* __restrict__ F, int N)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const size_t n3 = (size_t)N;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const T v = n0[c * n3 + k];
+        n[c * n3 + k] = v;
+        nP[c * n3 + k] = v;
+        dndt[c * n3 + k] = T(0);
+        u[c * n3 + k] = T(0);
+        F[c * n3 + k] = T(0);
+    }
+}
+
+}  // namespace el

@@ -1,0 +1,178 @@
+// lbm_kernels.hpp -- fused D3Q19 moments + BGK/Guo collision + push streaming
+// with halfway bounce-back (Sec. II C), on the shifted (g_i = f_i - w_i) or
+// plain distribution, one thread per fluid node.
+//
+// Memory traffic per node and step: 19 reads of q (coalesced, x fastest),
+// 3 reads of F^LC, 19 writes of q to the neighbours' slots.  The kernel is
+// HBM-bound; all arithmetic stays in registers.
+#pragma once
+
+#include "el_common.hpp"
+
+namespace el {
+
+template <typename T>
+struct LbmArgs {
+    Geom g;
+    T omega;     // 1/tau
+    T cS;        // 1 - 1/(2 tau), weight of the Guo source
+    T gx, gy, gz;  // body acceleration (force density rho g)
+    int coupling;  // 0: F^LC is treated as zero and not read
+};
+
+// Density and momentum of one node: rho - 1 = sum q (shifted) or rho = sum f,
+// j = sum e_i q_i with opposite directions paired first, which keeps the
+// differences of nearly equal populations exact in single precision.
+template <typename T, bool SHIFT>
+__device__ inline void node_moments(const T (&q)[19], T& rho, T& drho, T& jx, T& jy, T& jz)
+{
+    T s = q[0];
+    s += (q[1] + q[2]) + (q[3] + q[4]) + (q[5] + q[6]);
+    s += ((q[7] + q[8]) + (q[9] + q[10])) + ((q[11] + q[12]) + (q[13] + q[14]));
+    s += (q[15] + q[16]) + (q[17] + q[18]);
+    if (SHIFT) {
+        drho = s;
+        rho = T(1) + s;
+    } else {
+        rho = s;
+        drho = s - T(1);
+    }
+    jx = (q[1] - q[2]) + (q[7] - q[8]) + (q[9] - q[10]) + (q[11] - q[12]) + (q[13] - q[14]);
+    jy = (q[3] - q[4]) + (q[7] - q[8]) + (q[10] - q[9]) + (q[15] - q[16]) + (q[17] - q[18]);
+    jz = (q[5] - q[6]) + (q[11] - q[12]) + (q[14] - q[13]) + (q[15] - q[16]) + (q[18] - q[17]);
+}
+
+// One LBM step: read q at own node from qa, collide, push to the neighbours
+// in qb.  A population whose destination is a wall node returns to its own
+// node in the opposite direction (wall midway between fluid and solid node).
+template <typename T, bool SHIFT>
+__global__ void __launch_bounds__(256) k_lbm_push(const T* __restrict__ qa, T* __restrict__ qb,
+                                                 const T* __restrict__ Flc, LbmArgs<T> a)
+{
+    const Geom& g = a.g;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= g.N) return;
+    const int x = k % g.nx;
+    const int t = k / g.nx;
+    const int y = t % g.ny;
+    const int z = t / g.ny;
+    const size_t N = (size_t)g.N;
+
+    T q[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) q[i] = __builtin_nontemporal_load(qa + i * N + k);
+
+    T rho, drho, jx, jy, jz;
+    node_moments<T, SHIFT>(q, rho, drho, jx, jy, jz);
+    T Fx = rho * a.gx, Fy = rho * a.gy, Fz = rho * a.gz;
+    if (a.coupling) {
+        Fx += Flc[k];
+        Fy += Flc[N + k];
+        Fz += Flc[2 * N + k];
+    }
+    const T inv_rho = T(1) / rho;
+    const T ux = (jx + T(0.5) * Fx) * inv_rho;
+    const T uy = (jy + T(0.5) * Fy) * inv_rho;
+    const T uz = (jz + T(0.5) * Fz) * inv_rho;
+    const T uu = ux * ux + uy * uy + uz * uz;
+    const T uF = ux * Fx + uy * Fy + uz * Fz;
+
+    // neighbour coordinates
+    const int row = g.nx, plane = g.nx * g.ny;
+    const int xs[3] = {(x == 0) ? g.nx - 1 : x - 1, x, (x == g.nx - 1) ? 0 : x + 1};
+    const int ys[3] = {((y == 0) ? g.ny - 1 : y - 1) * row, y * row, ((y == g.ny - 1) ? 0 : y + 1) * row};
+    int zm = z - 1, zp = z + 1;
+    bool wall_m = false, wall_p = false;
+    if (g.periodic_z) {
+        if (zm < 0) zm = g.nzf - 1;
+        if (zp == g.nzf) zp = 0;
+    } else {
+        wall_m = zm < 0;
+        wall_p = zp == g.nzf;
+    }
+    const int zs[3] = {zm * plane, z * plane, zp * plane};
+
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const T w = WGT<T>(i);
+        const T eu = T(EX(i)) * ux + T(EY(i)) * uy + T(EZ(i)) * uz;
+        const T eF = T(EX(i)) * Fx + T(EY(i)) * Fy + T(EZ(i)) * Fz;
+        T eq;
+        if (SHIFT)
+            eq = w * (rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu) + drho);
+        else
+            eq = w * rho * (T(1) + T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu);
+        const T S = w * (T(3) * (eF - uF) + T(9) * eu * eF);
+        const T post = q[i] + a.omega * (eq - q[i]) + a.cS * S;
+        const bool to_wall = (EZ(i) == 1 && wall_p) || (EZ(i) == -1 && wall_m);
+        if (to_wall) {
+            qb[OPP(i) * N + k] = post;
+        } else {
+            const int d = xs[EX(i) + 1] + ys[EY(i) + 1] + zs[EZ(i) + 1];
+            qb[i * N + d] = post;
+        }
+    }
+}
+
+// Velocity of the current state: u = (sum e q + F/2)/rho, F = rho g + F^LC.
+template <typename T, bool SHIFT>
+__global__ void __launch_bounds__(256) k_moments(const T* __restrict__ q_in, const T* __restrict__ Flc,
+                                                T* __restrict__ u, LbmArgs<T> a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.g.N) return;
+    const size_t N = (size_t)a.g.N;
+    T q[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) q[i] = q_in[i * N + k];
+    T rho, drho, jx, jy, jz;
+    node_moments<T, SHIFT>(q, rho, drho, jx, jy, jz);
+    T Fx = rho * a.gx, Fy = rho * a.gy, Fz = rho * a.gz;
+    if (a.coupling) {
+        Fx += Flc[k];
+        Fy += Flc[N + k];
+        Fz += Flc[2 * N + k];
+    }
+    const T inv_rho = T(1) / rho;
+    u[k] = (jx + T(0.5) * Fx) * inv_rho;
+    u[N + k] = (jy + T(0.5) * Fy) * inv_rho;
+    u[2 * N + k] = (jz + T(0.5) * Fz) * inv_rho;
+}
+
+// Fills n values with v (used instead of a memset so the launch sequence can
+// be captured in a graph).
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill(T* __restrict__ p, T v, int n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
+// Rest state: q = 0 (shifted) or q_i = w_i (plain).
+template <typename T, bool SHIFT>
+__global__ void __launch_bounds__(256) k_rest(T* __restrict__ q, int N)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) q[(size_t)i * N + k] = SHIFT ? T(0) : WGT<T>(i);
+}
+
+// Equilibrium at rho = 1 and velocity u0 (warm start).
+template <typename T, bool SHIFT>
+__global__ void __launch_bounds__(256) k_equilibrium(T* __restrict__ q, const T* __restrict__ u0, int N)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const size_t n = (size_t)N;
+    const T ux = u0[k], uy = u0[n + k], uz = u0[2 * n + k];
+    const T uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const T eu = T(EX(i)) * ux + T(EY(i)) * uy + T(EZ(i)) * uz;
+        const T poly = T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu;
+        q[i * n + k] = SHIFT ? WGT<T>(i) * poly : WGT<T>(i) * (T(1) + poly);
+    }
+}
+
+}  // namespace el

@@ -1,0 +1,251 @@
+"""Thin ctypes binding of libel.so (the C ABI in include/el.h).
+
+Argument marshalling only: every step of the time step runs in the library's
+HIP kernels.  PyTorch provides the device buffers and the stream.  The
+binding refuses to run when libel.so is missing or cannot be loaded; there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libel.so")
+
+EL_OK, EL_EINVAL, EL_EUNSTABLE, EL_EDEVICE, EL_ENAN, EL_ENOMEM = 0, -1, -2, -3, -4, -5
+EL_F64, EL_F64_SHIFTED, EL_F32, EL_F32_SHIFTED = 0, 1, 2, 3
+EL_PERIODIC_Z, EL_NO_COUPLING, EL_NO_RENORM_PREDICTOR, EL_ALLOW_UNSTABLE = 1, 2, 4, 8
+EL_BUF_Q, EL_BUF_VEC3, EL_BUF_SCRATCH = 0, 1, 2
+
+PRECISIONS = {"f64": EL_F64, "f64_shifted": EL_F64_SHIFTED, "f32": EL_F32, "f32_shifted": EL_F32_SHIFTED}
+
+# Every symbol the header declares (checked by the CPU test suite).
+EXPORTED = ("el_version", "el_strerror", "el_last_error", "el_buffer_bytes", "el_validate", "el_init_lattice",
+            "el_init_flow", "el_step_lbm", "el_moments", "el_step_director", "el_force", "el_run",
+            "el_observables", "el_error_norms")
+
+
+class ElError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str):
+        super().__init__(f"{what} failed with status {status}: {detail}")
+        self.status = status
+
+
+class el_params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("precision", C.c_int32), ("fd_ratio", C.c_int32), ("flags", C.c_int32),
+                ("tau", C.c_double), ("g", C.c_double * 3), ("K", C.c_double), ("q0", C.c_double),
+                ("W0", C.c_double), ("alpha", C.c_double * 6), ("alpha4p", C.c_double)]
+
+
+class el_state(C.Structure):
+    _fields_ = [("q", C.c_void_p * 2), ("n", C.c_void_p), ("n_pred", C.c_void_p), ("dndt", C.c_void_p),
+                ("u", C.c_void_p), ("F", C.c_void_p), ("scratch", C.c_void_p), ("parity", C.c_int32),
+                ("reserved", C.c_int32), ("step", C.c_int64)]
+
+
+class el_obs(C.Structure):
+    _fields_ = [("mass", C.c_double), ("mom", C.c_double * 3), ("mom_phys", C.c_double * 3),
+                ("max_u", C.c_double), ("max_unit_dev", C.c_double), ("tube_weight", C.c_double),
+                ("tube_centroid", C.c_double * 2), ("tube_cs", C.c_double * 4), ("nonfinite", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+OBS_DOUBLES = C.sizeof(el_obs) // 8
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libel.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libel.so not found at {path}: build it with paper_2503_06610_amd/build.py")
+    lib = C.CDLL(path)
+    P, S, V = C.POINTER(el_params), C.POINTER(el_state), C.c_void_p
+    sig = {
+        "el_version": (C.c_int, []),
+        "el_strerror": (C.c_char_p, [C.c_int]),
+        "el_last_error": (C.c_char_p, []),
+        "el_buffer_bytes": (C.c_size_t, [P, C.c_int32]),
+        "el_validate": (C.c_int, [P]),
+        "el_init_lattice": (C.c_int, [P, S, V, V]),
+        "el_init_flow": (C.c_int, [P, S, V, V]),
+        "el_step_lbm": (C.c_int, [P, S, C.c_int32, C.c_int32, V]),
+        "el_moments": (C.c_int, [P, S, V]),
+        "el_step_director": (C.c_int, [P, S, V]),
+        "el_force": (C.c_int, [P, S, V]),
+        "el_run": (C.c_int, [P, S, C.c_int64, V]),
+        "el_observables": (C.c_int, [P, S, V, V]),
+        "el_error_norms": (C.c_int, [P, V, V, C.c_int32, V, V, V]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != EL_OK:
+        raise ElError(status, what, load().el_last_error().decode())
+
+
+def make_params(prob, precision: str = "f32_shifted") -> el_params:
+    """el_params from a seeded Problem (paper_2503_06610_amd.inputs)."""
+    p = el_params()
+    p.nx, p.ny, p.nz = prob.nx, prob.ny, prob.nz
+    p.precision = PRECISIONS[precision]
+    p.fd_ratio = int(prob.fd_ratio)
+    flags = 0
+    if prob.periodic_z:
+        flags |= EL_PERIODIC_Z
+    if not prob.coupling:
+        flags |= EL_NO_COUPLING
+    if not prob.renorm_predictor:
+        flags |= EL_NO_RENORM_PREDICTOR
+    p.flags = flags
+    p.tau = float(prob.tau)
+    p.g = (C.c_double * 3)(*prob.g)
+    p.K, p.q0, p.W0 = float(prob.K), float(prob.q0), float(prob.W0)
+    p.alpha = (C.c_double * 6)(*prob.alpha)
+    p.alpha4p = float(prob.alpha4p)
+    return p
+
+
+def validate(params: el_params) -> int:
+    return load().el_validate(C.byref(params))
+
+
+def buffer_bytes(params: el_params, which: int) -> int:
+    return int(load().el_buffer_bytes(C.byref(params), which))
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Lattice:
+    """Device buffers of one channel (torch tensors) and the C-ABI calls on them."""
+
+    def __init__(self, prob, precision: str = "f32_shifted", device: str = "cuda", allow_unstable: bool = False):
+        import torch
+        self.lib = load()
+        self.prob = prob
+        self.precision = precision
+        self.params = make_params(prob, precision)
+        if allow_unstable:
+            self.params.flags |= EL_ALLOW_UNSTABLE
+        _check(self.lib.el_validate(C.byref(self.params)), "el_validate")
+        self.dtype = torch.float64 if precision.startswith("f64") else torch.float32
+        self.N = prob.fluid_nodes
+        dev = torch.device(device)
+        self.q = [torch.empty((19,) + prob.shape(1)[1:], dtype=self.dtype, device=dev) for _ in range(2)]
+        mk = lambda: torch.zeros(prob.shape(3), dtype=self.dtype, device=dev)
+        self.n, self.n_pred, self.dndt, self.u, self.F = mk(), mk(), mk(), mk(), mk()
+        nscratch = buffer_bytes(self.params, EL_BUF_SCRATCH)
+        self.scratch = torch.empty(nscratch, dtype=torch.uint8, device=dev)
+        self.obs_buf = torch.zeros(OBS_DOUBLES, dtype=torch.float64, device=dev)
+        assert self.q[0].numel() * self.q[0].element_size() == buffer_bytes(self.params, EL_BUF_Q)
+        self.state = el_state()
+        self.state.q = (C.c_void_p * 2)(self.q[0].data_ptr(), self.q[1].data_ptr())
+        self.state.n = self.n.data_ptr()
+        self.state.n_pred = self.n_pred.data_ptr()
+        self.state.dndt = self.dndt.data_ptr()
+        self.state.u = self.u.data_ptr()
+        self.state.F = self.F.data_ptr()
+        self.state.scratch = self.scratch.data_ptr()
+        self.state.parity = 0
+        self.state.step = 0
+
+    # -- the C-ABI entry points ---------------------------------------------
+    def init_lattice(self, n0, stream=None):
+        import torch
+        t = torch.as_tensor(np.ascontiguousarray(n0) if isinstance(n0, np.ndarray) else n0)
+        t = t.to(device=self.n.device, dtype=self.dtype).contiguous().reshape(self.prob.shape(3))
+        self._n0 = t  # keep alive until the copy kernel ran
+        _check(self.lib.el_init_lattice(C.byref(self.params), C.byref(self.state), C.c_void_p(t.data_ptr()),
+                                        _stream_ptr(stream)), "el_init_lattice")
+
+    def init_flow(self, u0, stream=None):
+        import torch
+        t = torch.as_tensor(u0).to(device=self.n.device, dtype=self.dtype).contiguous()
+        self._u0 = t
+        _check(self.lib.el_init_flow(C.byref(self.params), C.byref(self.state), C.c_void_p(t.data_ptr()),
+                                     _stream_ptr(stream)), "el_init_flow")
+
+    def step_lbm(self, nsteps: int = 1, write_u: bool = True, stream=None):
+        _check(self.lib.el_step_lbm(C.byref(self.params), C.byref(self.state), int(nsteps), int(bool(write_u)),
+                                    _stream_ptr(stream)), "el_step_lbm")
+
+    def moments(self, stream=None):
+        _check(self.lib.el_moments(C.byref(self.params), C.byref(self.state), _stream_ptr(stream)), "el_moments")
+
+    def step_director(self, stream=None):
+        _check(self.lib.el_step_director(C.byref(self.params), C.byref(self.state), _stream_ptr(stream)),
+               "el_step_director")
+
+    def force(self, stream=None):
+        _check(self.lib.el_force(C.byref(self.params), C.byref(self.state), _stream_ptr(stream)), "el_force")
+
+    def run(self, T: int, stream=None):
+        _check(self.lib.el_run(C.byref(self.params), C.byref(self.state), int(T), _stream_ptr(stream)), "el_run")
+
+    def observables(self, stream=None) -> dict:
+        import torch
+        _check(self.lib.el_observables(C.byref(self.params), C.byref(self.state),
+                                       C.c_void_p(self.obs_buf.data_ptr()), _stream_ptr(stream)), "el_observables")
+        raw = self.obs_buf.cpu().numpy().tobytes()
+        o = el_obs.from_buffer_copy(raw)
+        return {"mass": o.mass, "mom": np.array(o.mom[:]), "mom_phys": np.array(o.mom_phys[:]),
+                "max_u": o.max_u, "max_unit_dev": o.max_unit_dev, "tube_weight": o.tube_weight,
+                "tube_centroid": np.array(o.tube_centroid[:]), "tube_cs": np.array(o.tube_cs[:]),
+                "nonfinite": int(o.nonfinite)}
+
+    def error_norms(self, a, ref, stream=None) -> dict:
+        """Error sums of a device field `a` (this lattice's dtype) against an
+        FP64 reference (numpy or tensor) of the same shape."""
+        import torch
+        at = a.contiguous()
+        ncomp = at.shape[0]
+        rt = torch.as_tensor(ref, dtype=torch.float64).to(at.device).contiguous()
+        out = torch.zeros(10, dtype=torch.float64, device=at.device)
+        _check(self.lib.el_error_norms(C.byref(self.params), C.c_void_p(at.data_ptr()), C.c_void_p(rt.data_ptr()),
+                                       int(ncomp), C.c_void_p(self.scratch.data_ptr()), C.c_void_p(out.data_ptr()),
+                                       _stream_ptr(stream)), "el_error_norms")
+        v = out.cpu().numpy()
+        res = {"rel_l2": float(np.sqrt(v[0] / v[1])) if v[1] > 0 else float(np.sqrt(v[0])),
+               "eps": float(v[2] / v[3]) if v[3] > 0 else float(v[2])}
+        res["eps_comp"] = [float(v[4 + 2 * c] / v[5 + 2 * c]) if v[5 + 2 * c] > 0 else float(v[4 + 2 * c])
+                           for c in range(ncomp)]
+        return res
+
+    # -- field access ----------------------------------------------------------
+    @property
+    def step(self) -> int:
+        return int(self.state.step)
+
+    def q_current(self):
+        return self.q[self.state.parity]
+
+    def get(self, name: str) -> np.ndarray:
+        """Host copy (float64) of a field: q, n, nP, u, F."""
+        import torch
+        torch.cuda.synchronize()
+        t = {"q": self.q_current(), "n": self.n, "nP": self.n_pred, "u": self.u, "F": self.F}[name]
+        return t.detach().to("cpu", torch.float64).numpy()
+
+    def set(self, name: str, arr):
+        """Overwrite a field from host data (tests and warm starts)."""
+        import torch
+        t = {"q": self.q_current(), "n": self.n, "nP": self.n_pred, "u": self.u, "F": self.F}[name]
+        t.copy_(torch.as_tensor(np.ascontiguousarray(arr)).reshape(t.shape).to(t.dtype))

@@ -1,0 +1,125 @@
+"""Host-side checks of the C ABI (no GPU): libel.so loads, exports every
+function include/el.h declares, validates parameters and sizes buffers."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2503_06610_amd import el, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "el.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(el_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_what_binding_expects():
+    assert _declared_functions() == sorted(el.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = el.load()
+    out = subprocess.check_output(["nm", "-D", "--defined-only", el.LIB_PATH], text=True)
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    for name in _declared_functions():
+        assert name in exported, name
+        assert hasattr(lib, name)
+    assert lib.el_version() == 1
+
+
+def test_struct_sizes_match_header():
+    # the header's structs are plain C: compile a probe with gcc and compare
+    src = r'''
+    #include <stdio.h>
+    #include <stddef.h>
+    #include "el.h"
+    int main(void) {
+      printf("%zu %zu %zu %zu %zu %zu\n", sizeof(el_params), sizeof(el_state), sizeof(el_obs),
+             offsetof(el_params, tau), offsetof(el_state, parity), offsetof(el_obs, nonfinite));
+      return 0; }
+    '''
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        cpath = os.path.join(d, "probe.c")
+        open(cpath, "w").write(src)
+        exe = os.path.join(d, "probe")
+        subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), cpath, "-o", exe])
+        vals = [int(v) for v in subprocess.check_output([exe], text=True).split()]
+    assert vals == [C.sizeof(el.el_params), C.sizeof(el.el_state), C.sizeof(el.el_obs),
+                    el.el_params.tau.offset, el.el_state.parity.offset, el.el_obs.nonfinite.offset]
+
+
+def test_validate_accepts_workloads():
+    for prob in (inputs.workload_c1()[0], inputs.workload_c2(r=20)[0], inputs.workload_c3()[0]):
+        for prec in el.PRECISIONS:
+            p = el.make_params(prob, prec)
+            assert el.validate(p) == el.EL_OK, el.load().el_last_error()
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("tau", 0.5, el.EL_EINVAL),
+    ("nx", 2, el.EL_EINVAL),
+    ("nz", 3, el.EL_EINVAL),
+    ("fd_ratio", 0, el.EL_EINVAL),
+    ("precision", 7, el.EL_EINVAL),
+    ("flags", 64, el.EL_EINVAL),
+    ("K", 0.5, el.EL_EUNSTABLE),
+    ("fd_ratio", 2, el.EL_EUNSTABLE),  # C1 with K = 0.01: r*12K/gamma1 = 2.6
+])
+def test_validate_rejects(field, value, code):
+    prob = inputs.workload_c1()[0]
+    p = el.make_params(prob, "f64")
+    setattr(p, field, value)
+    assert el.validate(p) == code
+    assert el.load().el_last_error()
+
+
+def test_validate_rejects_nonpositive_gamma1_and_nan():
+    prob = inputs.workload_c1()[0]
+    p = el.make_params(prob, "f64")
+    p.alpha[1], p.alpha[2] = 0.1, 0.1
+    assert el.validate(p) == el.EL_EINVAL
+    p = el.make_params(prob, "f64")
+    p.g[0] = float("nan")
+    assert el.validate(p) == el.EL_EINVAL
+    p = el.make_params(prob, "f64")
+    p.flags |= el.EL_ALLOW_UNSTABLE
+    p.K = 0.5
+    assert el.validate(p) == el.EL_OK
+
+
+def test_validate_rejects_high_mach_and_overflowing_lattice():
+    prob = inputs.workload_c1()[0].with_(g=(5e-3, 0.0, 0.0))
+    assert el.validate(el.make_params(prob, "f32_shifted")) == el.EL_EUNSTABLE
+    big = inputs.workload_c1()[0].with_(nx=1024, ny=1024, nz=130)
+    assert el.validate(el.make_params(big, "f32")) == el.EL_EINVAL
+
+
+def test_buffer_bytes():
+    prob = inputs.workload_c1()[0]
+    N = prob.fluid_nodes
+    for prec, ts in (("f64", 8), ("f32_shifted", 4)):
+        p = el.make_params(prob, prec)
+        assert el.buffer_bytes(p, el.EL_BUF_Q) == 19 * N * ts
+        assert el.buffer_bytes(p, el.EL_BUF_VEC3) == 3 * N * ts
+        assert el.buffer_bytes(p, el.EL_BUF_SCRATCH) == 131072 + 9 * N * ts
+        assert el.buffer_bytes(p, 99) == 0
+
+
+def test_null_arguments_are_rejected_without_device_work():
+    lib = el.load()
+    prob = inputs.workload_c1()[0]
+    p = el.make_params(prob, "f64")
+    s = el.el_state()
+    assert lib.el_init_lattice(C.byref(p), C.byref(s), None, None) == el.EL_EINVAL
+    assert lib.el_step_lbm(C.byref(p), None, 1, 0, None) == el.EL_EINVAL
+    assert lib.el_step_director(None, C.byref(s), None) == el.EL_EINVAL
+    assert lib.el_observables(C.byref(p), C.byref(s), None, None) == el.EL_EINVAL
+    assert lib.el_error_norms(C.byref(p), None, None, 3, None, None, None) == el.EL_EINVAL
+    assert lib.el_strerror(el.EL_EUNSTABLE)
