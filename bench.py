@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Coupled MLUPS of the hybrid LBM / finite-difference Ericksen-Leslie step on
+one MI355X, FP32-shifted against FP64 on the same grid.
+
+Workload: the precision-study channel, 128 x 128 x 64 nodes (two solid wall
+layers), tau = 0.8, Leslie set A, K = 5e-4, g_x = 1e-6, dt_FD/dt_LBM = r = 10,
+seeded +-0.05 rad director tilt (seed 2).  A step is one LBM step (moments,
+BGK + Guo collision, streaming, bounce-back) plus, every r-th step, the
+moments, the Heun director update and the coupling force.  Inputs are resident
+in HBM before the timed region; MLUPS count fluid nodes.
+
+Prints one JSON line (rank 0, N = 1) with the roofline of the dominant kernel
+(the LBM step, timed with HIP events on the stream it runs on) and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "coupled MLUPS FP32-shifted vs FP64 at <=1e-4 rel-L2 velocity error; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "lbm_push_c2_f32_shifted_traffic.json")
+
+
+def lbm_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("lbm_kernels.hpp", "el_common.hpp"):
+        with open(os.path.join(ROOT, "paper_2503_06610_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def timed_run(prob, n0, precision, steps, warmup):
+    """W untimed steps, then `steps` timed hybrid steps; returns timings and
+    the final fields (host copies)."""
+    import torch
+    from paper_2503_06610_amd import el
+
+    stream = torch.cuda.current_stream()
+    lat = el.Lattice(prob, precision)
+    lat.init_lattice(n0)
+    lat.run(warmup)
+    r = prob.fd_ratio
+    nint = (steps + r - 1) // r + 1
+    lbm_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nint)]
+    fd_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nint)]
+    lbm_counts = []
+    nfd = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    k = 0
+    while done < steps:
+        n = min(r - (lat.step % r), steps - done)
+        lbm_ev[k][0].record(stream)
+        lat.step_lbm(n, write_u=False)
+        lbm_ev[k][1].record(stream)
+        lbm_counts.append(n)
+        done += n
+        if lat.step % r == 0:
+            fd_ev[nfd][0].record(stream)
+            lat.moments()
+            lat.step_director()
+            fd_ev[nfd][1].record(stream)
+            nfd += 1
+        elif done == steps:
+            lat.moments()
+        k += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lbm_ms = sum(lbm_ev[i][0].elapsed_time(lbm_ev[i][1]) for i in range(k))
+    fd_ms = sum(fd_ev[i][0].elapsed_time(fd_ev[i][1]) for i in range(nfd))
+    out = {"wall_s": wall, "lbm_kernel_ms_avg": lbm_ms / sum(lbm_counts), "fd_ms_avg": fd_ms / max(nfd, 1),
+           "n_fd": nfd, "u": lat.get("u"), "n": lat.get("n"), "obs": lat.observables()}
+    return out
+
+
+def cpu_baseline(prob, n0, seconds_hint=20.0):
+    """The FP64 oracle on the host cores for a bounded sample: the full
+    channel for a few FD intervals."""
+    from tests.helpers import oracle_for
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = oracle_for(prob, True, threads=threads)
+    o.init(n0)
+    r = prob.fd_ratio
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        o.run(r)
+        steps += r
+        if time.perf_counter() - t0 > seconds_hint or steps >= 40 * r:
+            break
+    dt = time.perf_counter() - t0
+    o.close()
+    return {"value": prob.fluid_nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle, full {prob.nx}x{prob.ny}x{prob.nz} channel, {steps} coupled steps "
+                      f"(r={r}) from the seeded initial state, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--fd-ratio", type=int, default=10)
+    ap.add_argument("--gx", type=float, default=1e-6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-fp64", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (see DESIGN.md, "
+              "'How the path would shard').", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2503_06610_amd import inputs
+
+    torch.cuda.init()
+    prob, n0, _ = inputs.workload_c2(gx=args.gx, r=args.fd_ratio)
+    nf = prob.fluid_nodes
+    nall = prob.nx * prob.ny * prob.nz
+
+    res32 = timed_run(prob, n0, "f32_shifted", args.steps, args.warmup)
+    mlups = nf * args.steps / res32["wall_s"] / 1e6
+    check = {}
+    if not args.skip_fp64:
+        res64 = timed_run(prob, n0, "f64_shifted", args.steps, args.warmup)
+        mlups64 = nf * args.steps / res64["wall_s"] / 1e6
+        du = res32["u"] - res64["u"]
+        dn = res32["n"] - res64["n"]
+        check = {"fp64_shifted_mlups": round(mlups64, 1), "speedup_fp32s_vs_fp64": round(mlups / mlups64, 3),
+                 "u_rel_l2_vs_fp64": float(np.sqrt((du ** 2).sum() / (res64["u"] ** 2).sum())),
+                 "n_rel_l2_vs_fp64": float(np.sqrt((dn ** 2).sum() / (res64["n"] ** 2).sum())),
+                 "fp64_lbm_kernel_us": round(res64["lbm_kernel_ms_avg"] * 1e3, 3),
+                 "paper_context": "paper: 26.5x FP32 (dt_FD=250) vs FP64 on an RTX 4000 Ada with FP64 at 1/64 "
+                                  "of FP32; MI355X FP64 vector rate is 1/2 of FP32 and the step is HBM-bound"}
+
+    # roofline of the dominant kernel: the LBM step, 41 words per fluid node
+    bytes_per_launch = 41 * 4 * nf
+    lbm_s = res32["lbm_kernel_ms_avg"] * 1e-3
+    achieved = bytes_per_launch / lbm_s / 1e9
+    traffic = None
+    if os.path.exists(PROFILE_TRAFFIC):
+        with open(PROFILE_TRAFFIC) as f:
+            prof = json.load(f)
+        if prof.get("source_hash") == lbm_source_hash() and prof.get("fluid_nodes") == nf:
+            traffic = prof.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_lbm_push<float, shifted>", "bytes_per_launch": bytes_per_launch,
+                "avg_launch_us": round(lbm_s * 1e6, 3)}
+    # whole-step algorithmic bytes s*(41 + 15/r) per fluid-node update
+    step_bytes = 4 * (41 + 15.0 / prob.fd_ratio)
+    step_frac = mlups * 1e6 * step_bytes / (HBM_PEAK_GBS * 1e9)
+
+    line = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(res32["wall_s"] / args.steps * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "precision-study channel 128x128x64 (walls at z=0,63), tau=0.8, Leslie set A, "
+                               f"K=5e-4, g_x={args.gx:g}, r={prob.fd_ratio}, FP32-shifted, seeded tilt",
+                   "nx": prob.nx, "ny": prob.ny, "nz": prob.nz, "fd_ratio": prob.fd_ratio,
+                   "fluid_nodes": nf, "mlups_counting_wall_nodes": round(nall * args.steps / res32["wall_s"] / 1e6, 1),
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "step_roofline": {"bytes_per_update": step_bytes, "frac": round(step_frac, 4),
+                          "fd_step_us": round(res32["fd_ms_avg"] * 1e3, 2)},
+        "precision_check": check,
+        "observables": {"mass": res32["obs"]["mass"], "max_u": res32["obs"]["max_u"],
+                        "max_unit_dev": res32["obs"]["max_unit_dev"], "nonfinite": res32["obs"]["nonfinite"]},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(prob, n0)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
