@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "coupled MLUPS FP32-shifted vs FP64 at <=1e-4 rel-L2 velocity error; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "lbm_push_c2_f32_shifted_traffic.json")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "lbm_step_traffic.json")
 
 
 def lbm_source_hash() -> str:
@@ -114,6 +114,10 @@ def main():
     ap.add_argument("--gx", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
+                    help="c2: 128x128x64 precision-study channel (headline); c3: 256x256x48 tube channel")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (traffic-counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -126,7 +130,23 @@ def main():
     from paper_2503_06610_amd import inputs
 
     torch.cuda.init()
-    prob, n0, _ = inputs.workload_c2(gx=args.gx, r=args.fd_ratio)
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 4, "copies": 5}), flush=True)
+        return
+    if args.workload == "c2":
+        prob, n0, _ = inputs.workload_c2(gx=args.gx, r=args.fd_ratio)
+        workload = ("precision-study channel 128x128x64 (walls at z=0,63), tau=0.8, Leslie set A, "
+                    f"K=5e-4, g_x={args.gx:g}, r={prob.fd_ratio}, FP32-shifted, seeded tilt")
+    else:
+        prob, n0, _ = inputs.workload_c3(r=args.fd_ratio)
+        workload = ("skyrmion-tube channel 256x256x48 (walls at z=0,47), Leslie set B (tau=1.8977), K=5e-3, "
+                    f"q0=2pi/32, tube R=16, g_x=5e-6, r={prob.fd_ratio}, FP32-shifted")
     nf = prob.fluid_nodes
     nall = prob.nx * prob.ny * prob.nz
 
@@ -153,8 +173,9 @@ def main():
     if os.path.exists(PROFILE_TRAFFIC):
         with open(PROFILE_TRAFFIC) as f:
             prof = json.load(f)
-        if prof.get("source_hash") == lbm_source_hash() and prof.get("fluid_nodes") == nf:
-            traffic = prof.get("hbm_bytes_per_launch")
+        entry = prof.get(args.workload, {})
+        if entry.get("source_hash") == lbm_source_hash() and entry.get("fluid_nodes") == nf:
+            traffic = entry.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_lbm_push<float, shifted>", "bytes_per_launch": bytes_per_launch,
@@ -167,8 +188,7 @@ def main():
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(res32["wall_s"] / args.steps * 1e3, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "precision-study channel 128x128x64 (walls at z=0,63), tau=0.8, Leslie set A, "
-                               f"K=5e-4, g_x={args.gx:g}, r={prob.fd_ratio}, FP32-shifted, seeded tilt",
+        "config": {"workload": workload,
                    "nx": prob.nx, "ny": prob.ny, "nz": prob.nz, "fd_ratio": prob.fd_ratio,
                    "fluid_nodes": nf, "mlups_counting_wall_nodes": round(nall * args.steps / res32["wall_s"] / 1e6, 1),
                    "parallelism": "single GPU"},
