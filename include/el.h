@@ -195,6 +195,65 @@ int el_observables(const el_params* p, const el_state* s, el_obs* out, void* str
 int el_error_norms(const el_params* p, const void* a, const double* ref, int32_t ncomp, void* work,
                    double* out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched ensemble: many independent channels of uneven sizes, body forces
+ * and FD/LBM step ratios advanced together.  Each step launches persistent
+ * kernels over a work list of (channel, tile) pairs; a device step counter
+ * decides per channel whether the finite-difference update of Sec. II D is
+ * due ((step + 1) % r == 0), so one captured step replays without the host.
+ * Every channel performs the same arithmetic as the single-lattice calls, in
+ * the same order, so its state is bitwise equal to an el_run of that channel.
+ * ------------------------------------------------------------------------ */
+typedef struct el_batch el_batch;   /* opaque handle owned by the library */
+
+typedef struct {
+    int32_t lbm_block;          /* threads per block = nodes per tile of the LBM kernel (64..1024) */
+    int32_t lbm_blocks_per_cu;  /* persistent grid = compute units * this */
+    int32_t fd_block;           /* the same for the moments and FD kernels */
+    int32_t fd_blocks_per_cu;
+    int32_t tuned;              /* out: 1 if chosen by the autotuner, 2 if taken from its cache */
+    int32_t reserved;
+} el_batch_tuning;
+
+/* Creates a batch over nchan caller-owned lattices.  params[c] and states[c]
+ * describe channel c exactly as for the single-lattice calls (buffers sized
+ * by el_buffer_bytes, already initialised by el_init_lattice); all channels
+ * share the precision.  tuning == NULL runs the autotuner: candidate launch
+ * shapes are timed on `stream` with kernels whose outputs are recomputed
+ * before use (the LBM step into the inactive buffer, the moments, the
+ * predictor, the stress), so the states are not changed; the choice is cached
+ * per (kernel, precision, node-count class, channel-count class, GPU
+ * architecture) for the process; n_pred and dndt, the predictor-corrector's
+ * intermediates, may be overwritten.  Allocates the small device tables of the
+ * handle (hipMalloc, outside the hot path).  EL_EINVAL for a bad channel
+ * (el_last_error names it) or mixed precisions. */
+int el_batch_create(const el_params* params, el_state* states, int32_t nchan, const el_batch_tuning* tuning,
+                    void* stream, el_batch** out);
+
+/* nsteps coupled steps of every channel (Sec. II D per channel).  After
+ * el_batch_capture each step is one hipGraphLaunch of the captured step. */
+int el_batch_step(el_batch* b, int32_t nsteps, void* stream);
+
+/* Captures one batched step into a hipGraph on `stream` (which must not be
+ * capturing already); later el_batch_step calls replay it. */
+int el_batch_capture(el_batch* b, void* stream);
+
+/* u of every channel from its current q and F^LC (el_moments per channel). */
+int el_batch_moments(el_batch* b, void* stream);
+
+/* FP64 observables of every channel into out (device, nchan el_obs). */
+int el_batch_observables(el_batch* b, el_obs* out, void* stream);
+
+/* Writes each channel's parity and step back into states[0..nchan-1]. */
+int el_batch_sync(const el_batch* b, el_state* states, int32_t nchan);
+
+/* The launch shapes in use. */
+int el_batch_get_tuning(const el_batch* b, el_batch_tuning* out);
+
+/* Frees the handle and its device tables (not the channels' buffers);
+ * waits for work on the handle's streams to finish. */
+int el_batch_destroy(el_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

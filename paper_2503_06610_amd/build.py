@@ -10,10 +10,13 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libel.so")
-SOURCES = ["el_api.hip"]
+SOURCES = ["el_api.hip", "batch.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # contract a*b+c only within one expression, so a node update inlined into
+    # different kernels compiles to the same arithmetic
+    "-ffp-contract=on",
     # no packed-FP32 instructions in the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",

@@ -1,22 +1,13 @@
 // el_api.hip -- the C ABI of libel.so (declared in include/el.h): argument
 // validation, precision dispatch and the launch sequence of the hybrid step
 // (Sec. II D).  All device memory belongs to the caller.
-#include <hip/hip_runtime.h>
+#include "host_common.hpp"
 
-#include <cmath>
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
-
-#include "el.h"
-#include "el_common.hpp"
-#include "fd_kernels.hpp"
-#include "lbm_kernels.hpp"
-#include "reduce_kernels.hpp"
+namespace elh {
 
 namespace {
-
 thread_local char g_err[512] = "";
+}
 
 int fail(int code, const char* fmt, ...)
 {
@@ -27,33 +18,7 @@ int fail(int code, const char* fmt, ...)
     return code;
 }
 
-int check_launch(const char* what)
-{
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(EL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
-    return EL_OK;
-}
-
-constexpr size_t REDUCE_BYTES = (size_t)el::RED_MAX_BLOCKS * 16 * sizeof(double);
-constexpr int BLOCK = 256;
-
-bool is_f64(const el_params* p) { return p->precision == EL_F64 || p->precision == EL_F64_SHIFTED; }
-bool is_shifted(const el_params* p) { return p->precision == EL_F64_SHIFTED || p->precision == EL_F32_SHIFTED; }
-bool periodic_z(const el_params* p) { return (p->flags & EL_PERIODIC_Z) != 0; }
-bool coupling(const el_params* p) { return (p->flags & EL_NO_COUPLING) == 0; }
-
-int nzf_of(const el_params* p) { return periodic_z(p) ? p->nz : p->nz - 2; }
-
-el::Geom geom_of(const el_params* p)
-{
-    el::Geom g;
-    g.nx = p->nx;
-    g.ny = p->ny;
-    g.nzf = nzf_of(p);
-    g.periodic_z = periodic_z(p) ? 1 : 0;
-    g.N = p->nx * p->ny * g.nzf;
-    return g;
-}
+const char* last_error() { return g_err; }
 
 int basic_checks(const el_params* p)
 {
@@ -103,48 +68,13 @@ int state_checks(const el_params* p, const el_state* s)
     return EL_OK;
 }
 
-int grid_for(int N) { return (N + BLOCK - 1) / BLOCK; }
+}  // namespace elh
+
+namespace {
+using namespace elh;
+
 
 // --------------------------------------------------------------------------
-template <typename T>
-el::LbmArgs<T> lbm_args(const el_params* p)
-{
-    el::LbmArgs<T> a;
-    a.g = geom_of(p);
-    a.omega = T(1.0 / p->tau);
-    a.cS = T(1.0 - 0.5 / p->tau);
-    a.gx = T(p->g[0]);
-    a.gy = T(p->g[1]);
-    a.gz = T(p->g[2]);
-    a.coupling = coupling(p) ? 1 : 0;
-    return a;
-}
-
-template <typename T>
-el::FdArgs<T> fd_args(const el_params* p)
-{
-    el::FdArgs<T> a;
-    a.g = geom_of(p);
-    const double g1 = p->alpha[2] - p->alpha[1];
-    const double g2 = p->alpha[2] + p->alpha[1];
-    a.dt = T(p->fd_ratio);
-    a.K = T(p->K);
-    a.Kq0x2 = T(2.0 * p->K * p->q0);
-    a.Kq0 = T(p->K * p->q0);
-    a.W0 = T(p->W0);
-    a.inv_g1 = T(1.0 / g1);
-    a.g2_over_g1 = T(g2 / g1);
-    a.g2 = T(g2);
-    a.a1 = T(p->alpha[0]);
-    a.a2 = T(p->alpha[1]);
-    a.a3 = T(p->alpha[2]);
-    a.a4p = T(p->alpha4p);
-    a.a5 = T(p->alpha[4]);
-    a.a6 = T(p->alpha[5]);
-    a.renorm_predictor = (p->flags & EL_NO_RENORM_PREDICTOR) ? 0 : 1;
-    return a;
-}
-
 template <typename T, bool SHIFT>
 int launch_lbm_steps(const el_params* p, el_state* s, int nsteps, hipStream_t st)
 {
@@ -168,12 +98,6 @@ int launch_moments(const el_params* p, el_state* s, hipStream_t st)
     hipLaunchKernelGGL((el::k_moments<T, SHIFT>), dim3(grid_for(a.g.N)), dim3(BLOCK), 0, st,
                        static_cast<const T*>(s->q[s->parity]), static_cast<const T*>(s->F), static_cast<T*>(s->u), a);
     return check_launch("k_moments");
-}
-
-template <typename T>
-T* sigma_of(el_state* s)
-{
-    return reinterpret_cast<T*>(static_cast<char*>(s->scratch) + REDUCE_BYTES);
 }
 
 template <typename T>
@@ -300,7 +224,7 @@ const char* el_strerror(int status)
     }
 }
 
-const char* el_last_error(void) { return g_err; }
+const char* el_last_error(void) { return elh::last_error(); }
 
 size_t el_buffer_bytes(const el_params* p, int32_t which)
 {

@@ -126,13 +126,12 @@ __device__ inline void node_coords(const Geom& g, int k, int& x, int& y, int& z)
     z = t / g.ny;
 }
 
-// Predictor: (d_t n)_old = RHS(n); n^P = n + dt (d_t n)_old, normalised when asked.
+// Predictor at fluid node k: (d_t n)_old = RHS(n); n^P = n + dt (d_t n)_old,
+// normalised when asked.
 template <typename T>
-__global__ void __launch_bounds__(256) k_fd_predictor(const T* __restrict__ n, const T* __restrict__ u,
-                                                     T* __restrict__ nP, T* __restrict__ dndt, FdArgs<T> a)
+__device__ __forceinline__ void predictor_node(const T* __restrict__ n, const T* __restrict__ u, T* __restrict__ nP,
+                                               T* __restrict__ dndt, const FdArgs<T>& a, int k)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.g.N) return;
     int x, y, z;
     node_coords(a.g, k, x, y, z);
     const Nbr nb = make_nbr(a.g, x, y, z);
@@ -153,15 +152,12 @@ __global__ void __launch_bounds__(256) k_fd_predictor(const T* __restrict__ n, c
     for (int c = 0; c < 3; ++c) nP[c * N + k] = v[c];
 }
 
-// Corrector: n <- n + dt/2 [(d_t n)_old + RHS(n^P)], normalised to |n| = 1.
-// n is read only at the own node, so the update is done in place.
+// Corrector at fluid node k: n <- n + dt/2 [(d_t n)_old + RHS(n^P)], normalised
+// to |n| = 1.  n is read only at the own node, so the update is done in place.
 template <typename T>
-__global__ void __launch_bounds__(256) k_fd_corrector(T* __restrict__ n, const T* __restrict__ nP,
-                                                     const T* __restrict__ u, const T* __restrict__ dndt,
-                                                     FdArgs<T> a)
+__device__ __forceinline__ void corrector_node(T* __restrict__ n, const T* __restrict__ nP, const T* __restrict__ u,
+                                               const T* __restrict__ dndt, const FdArgs<T>& a, int k)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.g.N) return;
     int x, y, z;
     node_coords(a.g, k, x, y, z);
     const Nbr nb = make_nbr(a.g, x, y, z);
@@ -177,6 +173,25 @@ __global__ void __launch_bounds__(256) k_fd_corrector(T* __restrict__ n, const T
     normalise(v);
 #pragma unroll
     for (int c = 0; c < 3; ++c) n[c * N + k] = v[c];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fd_predictor(const T* __restrict__ n, const T* __restrict__ u,
+                                                     T* __restrict__ nP, T* __restrict__ dndt, FdArgs<T> a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.g.N) return;
+    predictor_node(n, u, nP, dndt, a, k);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fd_corrector(T* __restrict__ n, const T* __restrict__ nP,
+                                                     const T* __restrict__ u, const T* __restrict__ dndt,
+                                                     FdArgs<T> a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.g.N) return;
+    corrector_node(n, nP, u, dndt, a, k);
 }
 
 // Leslie + elastic stress at one fluid node (Sec. II B):
@@ -214,13 +229,11 @@ __device__ inline void stress(const Stencil3<T>& m, const Stencil3<T>& u, const 
         }
 }
 
-// sigma at every fluid node into sig (9 components, index a*3 + b).
+// sigma at fluid node k into sig (9 components, index a*3 + b).
 template <typename T>
-__global__ void __launch_bounds__(256) k_fd_stress(const T* __restrict__ n, const T* __restrict__ u,
-                                                  T* __restrict__ sig, FdArgs<T> a)
+__device__ __forceinline__ void stress_node(const T* __restrict__ n, const T* __restrict__ u, T* __restrict__ sig,
+                                            const FdArgs<T>& a, int k)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.g.N) return;
     int x, y, z;
     node_coords(a.g, k, x, y, z);
     const Nbr nb = make_nbr(a.g, x, y, z);
@@ -236,12 +249,12 @@ __global__ void __launch_bounds__(256) k_fd_stress(const T* __restrict__ n, cons
         for (int j = 0; j < 3; ++j) sig[(i * 3 + j) * N + k] = s[i][j];
 }
 
-// F^LC_a = sum_b [sigma_ab(x + b) - sigma_ab(x - b)]/2, zero stress at walls.
+// F^LC_a = sum_b [sigma_ab(x + b) - sigma_ab(x - b)]/2 at fluid node k, zero
+// stress at walls.
 template <typename T>
-__global__ void __launch_bounds__(256) k_fd_divergence(const T* __restrict__ sig, T* __restrict__ F, FdArgs<T> a)
+__device__ __forceinline__ void divergence_node(const T* __restrict__ sig, T* __restrict__ F, const FdArgs<T>& a,
+                                                int k)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.g.N) return;
     int x, y, z;
     node_coords(a.g, k, x, y, z);
     const Nbr nb = make_nbr(a.g, x, y, z);
@@ -260,6 +273,23 @@ __global__ void __launch_bounds__(256) k_fd_divergence(const T* __restrict__ sig
         }
         F[i * N + k] = div;
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fd_stress(const T* __restrict__ n, const T* __restrict__ u,
+                                                  T* __restrict__ sig, FdArgs<T> a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.g.N) return;
+    stress_node(n, u, sig, a, k);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fd_divergence(const T* __restrict__ sig, T* __restrict__ F, FdArgs<T> a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.g.N) return;
+    divergence_node(sig, F, a, k);
 }
 
 // Copies of the initial director and zeroed fields.

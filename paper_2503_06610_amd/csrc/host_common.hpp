@@ -1,0 +1,103 @@
+// host_common.hpp -- host-side helpers shared by the translation units of
+// libel.so: error reporting, parameter checks and kernel-argument packing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+
+#include "el.h"
+#include "el_common.hpp"
+#include "fd_kernels.hpp"
+#include "lbm_kernels.hpp"
+#include "reduce_kernels.hpp"
+
+namespace elh {
+
+// Records the detail of a failure for el_last_error() and returns code.
+int fail(int code, const char* fmt, ...);
+
+// The detail recorded by the last fail() on this thread.
+const char* last_error();
+
+inline int check_launch(const char* what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(EL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return EL_OK;
+}
+
+constexpr size_t REDUCE_BYTES = (size_t)el::RED_MAX_BLOCKS * 16 * sizeof(double);
+constexpr int BLOCK = 256;
+
+inline bool is_f64(const el_params* p) { return p->precision == EL_F64 || p->precision == EL_F64_SHIFTED; }
+inline bool is_shifted(const el_params* p) { return p->precision == EL_F64_SHIFTED || p->precision == EL_F32_SHIFTED; }
+inline bool periodic_z(const el_params* p) { return (p->flags & EL_PERIODIC_Z) != 0; }
+inline bool coupling(const el_params* p) { return (p->flags & EL_NO_COUPLING) == 0; }
+inline int nzf_of(const el_params* p) { return periodic_z(p) ? p->nz : p->nz - 2; }
+
+inline el::Geom geom_of(const el_params* p)
+{
+    el::Geom g;
+    g.nx = p->nx;
+    g.ny = p->ny;
+    g.nzf = nzf_of(p);
+    g.periodic_z = periodic_z(p) ? 1 : 0;
+    g.N = p->nx * p->ny * g.nzf;
+    return g;
+}
+
+int basic_checks(const el_params* p);
+int stability_checks(const el_params* p);
+int state_checks(const el_params* p, const el_state* s);
+
+inline int grid_for(int N) { return (N + BLOCK - 1) / BLOCK; }
+
+template <typename T>
+el::LbmArgs<T> lbm_args(const el_params* p)
+{
+    el::LbmArgs<T> a;
+    a.g = geom_of(p);
+    a.omega = T(1.0 / p->tau);
+    a.cS = T(1.0 - 0.5 / p->tau);
+    a.gx = T(p->g[0]);
+    a.gy = T(p->g[1]);
+    a.gz = T(p->g[2]);
+    a.coupling = coupling(p) ? 1 : 0;
+    return a;
+}
+
+template <typename T>
+el::FdArgs<T> fd_args(const el_params* p)
+{
+    el::FdArgs<T> a;
+    a.g = geom_of(p);
+    const double g1 = p->alpha[2] - p->alpha[1];
+    const double g2 = p->alpha[2] + p->alpha[1];
+    a.dt = T(p->fd_ratio);
+    a.K = T(p->K);
+    a.Kq0x2 = T(2.0 * p->K * p->q0);
+    a.Kq0 = T(p->K * p->q0);
+    a.W0 = T(p->W0);
+    a.inv_g1 = T(1.0 / g1);
+    a.g2_over_g1 = T(g2 / g1);
+    a.g2 = T(g2);
+    a.a1 = T(p->alpha[0]);
+    a.a2 = T(p->alpha[1]);
+    a.a3 = T(p->alpha[2]);
+    a.a4p = T(p->alpha4p);
+    a.a5 = T(p->alpha[4]);
+    a.a6 = T(p->alpha[5]);
+    a.renorm_predictor = (p->flags & EL_NO_RENORM_PREDICTOR) ? 0 : 1;
+    return a;
+}
+
+template <typename T>
+T* sigma_of(const el_state* s)
+{
+    return reinterpret_cast<T*>(static_cast<char*>(s->scratch) + REDUCE_BYTES);
+}
+
+}  // namespace elh

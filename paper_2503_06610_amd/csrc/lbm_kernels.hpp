@@ -42,16 +42,16 @@ __device__ inline void node_moments(const T (&q)[19], T& rho, T& drho, T& jx, T&
     jz = (q[5] - q[6]) + (q[11] - q[12]) + (q[14] - q[13]) + (q[15] - q[16]) + (q[18] - q[17]);
 }
 
-// One LBM step: read q at own node from qa, collide, push to the neighbours
-// in qb.  A population whose destination is a wall node returns to its own
-// node in the opposite direction (wall midway between fluid and solid node).
+// One LBM step for fluid node k: read q at the own node from qa, collide,
+// push to the neighbours in qb.  A population whose destination is a wall
+// node returns to its own node in the opposite direction (wall midway between
+// fluid and solid node).  Shared by the single-channel and batched kernels so
+// both perform the same arithmetic.
 template <typename T, bool SHIFT>
-__global__ void __launch_bounds__(256) k_lbm_push(const T* __restrict__ qa, T* __restrict__ qb,
-                                                 const T* __restrict__ Flc, LbmArgs<T> a)
+__device__ __forceinline__ void lbm_node(const T* __restrict__ qa, T* __restrict__ qb, const T* __restrict__ Flc,
+                                         const LbmArgs<T>& a, int k)
 {
     const Geom& g = a.g;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= g.N) return;
     const int x = k % g.nx;
     const int t = k / g.nx;
     const int y = t % g.ny;
@@ -114,13 +114,20 @@ __global__ void __launch_bounds__(256) k_lbm_push(const T* __restrict__ qa, T* _
     }
 }
 
-// Velocity of the current state: u = (sum e q + F/2)/rho, F = rho g + F^LC.
 template <typename T, bool SHIFT>
-__global__ void __launch_bounds__(256) k_moments(const T* __restrict__ q_in, const T* __restrict__ Flc,
-                                                T* __restrict__ u, LbmArgs<T> a)
+__global__ void __launch_bounds__(256) k_lbm_push(const T* __restrict__ qa, T* __restrict__ qb,
+                                                 const T* __restrict__ Flc, LbmArgs<T> a)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.g.N) return;
+    lbm_node<T, SHIFT>(qa, qb, Flc, a, k);
+}
+
+// u = (sum e q + F/2)/rho, F = rho g + F^LC, at fluid node k.
+template <typename T, bool SHIFT>
+__device__ __forceinline__ void moments_node(const T* __restrict__ q_in, const T* __restrict__ Flc,
+                                             T* __restrict__ u, const LbmArgs<T>& a, int k)
+{
     const size_t N = (size_t)a.g.N;
     T q[19];
 #pragma unroll
@@ -137,6 +144,16 @@ __global__ void __launch_bounds__(256) k_moments(const T* __restrict__ q_in, con
     u[k] = (jx + T(0.5) * Fx) * inv_rho;
     u[N + k] = (jy + T(0.5) * Fy) * inv_rho;
     u[2 * N + k] = (jz + T(0.5) * Fz) * inv_rho;
+}
+
+// Velocity of the current state: u = (sum e q + F/2)/rho, F = rho g + F^LC.
+template <typename T, bool SHIFT>
+__global__ void __launch_bounds__(256) k_moments(const T* __restrict__ q_in, const T* __restrict__ Flc,
+                                                T* __restrict__ u, LbmArgs<T> a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.g.N) return;
+    moments_node<T, SHIFT>(q_in, Flc, u, a, k);
 }
 
 // Fills n values with v (used instead of a memset so the launch sequence can

@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_obs_partial(const T* __restrict
 }
 
 // Adds the block rows in order and fills an el_obs.
-__global__ void __launch_bounds__(RED_THREADS) k_obs_final(const double* __restrict__ partial, int nblocks,
+static __global__ void __launch_bounds__(RED_THREADS) k_obs_final(const double* __restrict__ partial, int nblocks,
                                                           el_obs* __restrict__ out, int nx, int ny)
 {
     __shared__ double lds[RED_THREADS / 64][OBS_NQ];
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_err_partial(const T* __restrict
         for (int j = 0; j < ERR_NQ; ++j) partial[blockIdx.x * ERR_NQ + j] = v[j];
 }
 
-__global__ void __launch_bounds__(RED_THREADS) k_err_final(const double* __restrict__ partial, int nblocks, int nout,
+static __global__ void __launch_bounds__(RED_THREADS) k_err_final(const double* __restrict__ partial, int nblocks, int nout,
                                                           double* __restrict__ out)
 {
     __shared__ double lds[RED_THREADS / 64][ERR_NQ];

@@ -26,7 +26,8 @@ PRECISIONS = {"f64": EL_F64, "f64_shifted": EL_F64_SHIFTED, "f32": EL_F32, "f32_
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTED = ("el_version", "el_strerror", "el_last_error", "el_buffer_bytes", "el_validate", "el_init_lattice",
             "el_init_flow", "el_step_lbm", "el_moments", "el_step_director", "el_force", "el_run",
-            "el_observables", "el_error_norms")
+            "el_observables", "el_error_norms", "el_batch_create", "el_batch_step", "el_batch_capture",
+            "el_batch_moments", "el_batch_observables", "el_batch_sync", "el_batch_get_tuning", "el_batch_destroy")
 
 
 class ElError(RuntimeError):
@@ -57,6 +58,11 @@ class el_obs(C.Structure):
 
 OBS_DOUBLES = C.sizeof(el_obs) // 8
 
+
+class el_batch_tuning(C.Structure):
+    _fields_ = [("lbm_block", C.c_int32), ("lbm_blocks_per_cu", C.c_int32), ("fd_block", C.c_int32),
+                ("fd_blocks_per_cu", C.c_int32), ("tuned", C.c_int32), ("reserved", C.c_int32)]
+
 _lib = None
 
 
@@ -84,6 +90,14 @@ def load(path: str = LIB_PATH):
         "el_run": (C.c_int, [P, S, C.c_int64, V]),
         "el_observables": (C.c_int, [P, S, V, V]),
         "el_error_norms": (C.c_int, [P, V, V, C.c_int32, V, V, V]),
+        "el_batch_create": (C.c_int, [P, S, C.c_int32, C.POINTER(el_batch_tuning), V, C.POINTER(C.c_void_p)]),
+        "el_batch_step": (C.c_int, [V, C.c_int32, V]),
+        "el_batch_capture": (C.c_int, [V, V]),
+        "el_batch_moments": (C.c_int, [V, V]),
+        "el_batch_observables": (C.c_int, [V, V, V]),
+        "el_batch_sync": (C.c_int, [V, S, C.c_int32]),
+        "el_batch_get_tuning": (C.c_int, [V, C.POINTER(el_batch_tuning)]),
+        "el_batch_destroy": (C.c_int, [V]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -249,3 +263,66 @@ class Lattice:
         import torch
         t = {"q": self.q_current(), "n": self.n, "nP": self.n_pred, "u": self.u, "F": self.F}[name]
         t.copy_(torch.as_tensor(np.ascontiguousarray(arr)).reshape(t.shape).to(t.dtype))
+
+
+class Batch:
+    """A batched ensemble over Lattice objects (all of one precision), through
+    el_batch_*; after capture() every step is one graph launch."""
+
+    def __init__(self, lattices, tuning=None, stream=None):
+        import torch
+        self.lib = load()
+        self.lattices = list(lattices)
+        n = len(self.lattices)
+        self._params = (el_params * n)(*[lat.params for lat in self.lattices])
+        self._states = (el_state * n)(*[lat.state for lat in self.lattices])
+        self.handle = C.c_void_p()
+        tu = None
+        if tuning is not None:
+            tu = el_batch_tuning(*tuning, 0, 0)
+        _check(self.lib.el_batch_create(self._params, self._states, n, C.byref(tu) if tu else None,
+                                        _stream_ptr(stream), C.byref(self.handle)), "el_batch_create")
+        torch.cuda.synchronize()
+
+    def step(self, nsteps: int = 1, stream=None):
+        _check(self.lib.el_batch_step(self.handle, int(nsteps), _stream_ptr(stream)), "el_batch_step")
+
+    def capture(self, stream=None):
+        _check(self.lib.el_batch_capture(self.handle, _stream_ptr(stream)), "el_batch_capture")
+
+    def moments(self, stream=None):
+        _check(self.lib.el_batch_moments(self.handle, _stream_ptr(stream)), "el_batch_moments")
+
+    def sync(self):
+        """Copy the batch's parity and step counters back into the lattices."""
+        n = len(self.lattices)
+        _check(self.lib.el_batch_sync(self.handle, self._states, n), "el_batch_sync")
+        for lat, st in zip(self.lattices, self._states):
+            lat.state.parity = st.parity
+            lat.state.step = st.step
+
+    def observables(self, stream=None):
+        import torch
+        n = len(self.lattices)
+        buf = torch.zeros(n * OBS_DOUBLES, dtype=torch.float64, device=self.lattices[0].n.device)
+        _check(self.lib.el_batch_observables(self.handle, C.c_void_p(buf.data_ptr()), _stream_ptr(stream)),
+               "el_batch_observables")
+        raw = buf.cpu().numpy().tobytes()
+        size = C.sizeof(el_obs)
+        return [el_obs.from_buffer_copy(raw[i * size:(i + 1) * size]) for i in range(n)]
+
+    def tuning(self) -> dict:
+        t = el_batch_tuning()
+        _check(self.lib.el_batch_get_tuning(self.handle, C.byref(t)), "el_batch_get_tuning")
+        return {f: getattr(t, f) for f, _ in el_batch_tuning._fields_}
+
+    def close(self):
+        if self.handle:
+            self.lib.el_batch_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

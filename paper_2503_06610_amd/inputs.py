@@ -196,3 +196,25 @@ def workload_c3(r: int = 10) -> tuple:
     prob = channel(256, 256, 48, set_b(), g=(5e-6, 0.0, 0.0), K=5e-3, q0=2.0 * math.pi / 32.0,
                    fd_ratio=r)
     return prob, director_tubes(prob, [(128.0, 128.0)], 16.0), 100000
+
+
+def workload_c4(seed: int = 4, nchan: int = 64) -> list:
+    """Batched ensemble: nchan channels with Nx, Ny ~ U{48..160}, Nz ~ U{16..48}
+    (walls included), 1-4 skyrmion tubes (pitch 32, R = 16, periodic separation
+    >= 2R, fewer when they do not fit), g_x log-uniform in [1e-7, 1e-5], r drawn
+    from {1, 5, 10}; Leslie set B, K = 5e-3, q0 = 2 pi/32.  Returns a list of
+    (Problem, n0)."""
+    u = uniform01(seed, 11, 8 * nchan)
+    out = []
+    for c in range(nchan):
+        v = u[8 * c:8 * c + 8]
+        nx = 48 + int(v[0] * 113)
+        ny = 48 + int(v[1] * 113)
+        nz = 16 + int(v[2] * 33)
+        gx = 10.0 ** (-7.0 + 2.0 * v[3])
+        r = (1, 5, 10)[int(v[4] * 3)]
+        ntubes = 1 + int(v[5] * 4)
+        prob = channel(nx, ny, nz, set_b(), g=(gx, 0.0, 0.0), K=5e-3, q0=2.0 * math.pi / 32.0, fd_ratio=r)
+        centres = place_tubes(nx, ny, ntubes, 16.0, seed=seed * 1000 + c)
+        out.append((prob, director_tubes(prob, centres, 16.0)))
+    return out
