@@ -142,7 +142,9 @@ size_t el_buffer_bytes(const el_params* p, int32_t which);
  * with EL_PERIODIC_Z), tau <= 1/2, r < 1, gamma1 = alpha3 - alpha2 <= 0 with
  * coupling, unknown precision or flags.  EL_EUNSTABLE (unless
  * EL_ALLOW_UNSTABLE): r * 12 K / gamma1 > 2 (the explicit Heun step on the
- * compact Laplacian), or a Mach estimate |g| H^2/(8 nu) * sqrt(3) > 0.1. */
+ * compact Laplacian); r = 1 with coupling and tau > 1.5 (the Leslie force
+ * refreshed every LBM step diverges there: an empirical bound, found with
+ * the FP64 CPU implementation); or a Mach estimate |g| H^2/(8 nu) sqrt(3) > 0.1. */
 int el_validate(const el_params* p);
 
 /* Initialisation (Sec. II D, first step): q = rest state (0 when shifted,
@@ -234,11 +236,14 @@ int el_batch_create(const el_params* params, el_state* states, int32_t nchan, co
  * el_batch_capture each step is one hipGraphLaunch of the captured step. */
 int el_batch_step(el_batch* b, int32_t nsteps, void* stream);
 
-/* Captures one batched step into a hipGraph on `stream` (which must not be
- * capturing already); later el_batch_step calls replay it. */
+/* Captures one batched step into a hipGraph on `stream`, a created stream
+ * (not the null stream, which cannot be captured; EL_EINVAL) that is not
+ * capturing already; later el_batch_step calls replay it. */
 int el_batch_capture(el_batch* b, void* stream);
 
-/* u of every channel from its current q and F^LC (el_moments per channel). */
+/* Leaves u of every channel as el_run would: the velocity after the last LBM
+ * step, with the force that step used (channels whose last step ended an FD
+ * interval already hold it; the others get el_moments). */
 int el_batch_moments(el_batch* b, void* stream);
 
 /* FP64 observables of every channel into out (device, nchan el_obs). */

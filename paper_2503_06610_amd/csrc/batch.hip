@@ -59,18 +59,25 @@ __global__ void __launch_bounds__(1024) k_batch_lbm(const ChanDesc<T>* __restric
     }
 }
 
-// in_step = 1 inside a batched step (after its LBM kernel), 0 outside;
-// all = 1 computes every channel, otherwise only channels whose FD is due.
+// Which channels a moments launch covers.
+enum { MOM_DUE_IN_STEP = 0, MOM_ALL = 1, MOM_AFTER_PARTIAL = 2 };
+
+// MOM_DUE_IN_STEP: inside a batched step, after its LBM kernel, channels whose
+// FD update is due.  MOM_ALL: every channel, outside a step.  MOM_AFTER_PARTIAL:
+// outside a step, channels whose last step was not an FD step (the others
+// already hold the velocity of their last step), as el_run leaves u.
 template <typename T, bool SHIFT>
 __global__ void __launch_bounds__(1024) k_batch_moments(const ChanDesc<T>* __restrict__ ch,
                                                        const int2* __restrict__ tiles, int ntiles,
-                                                       const int* __restrict__ tdev, int in_step, int all)
+                                                       const int* __restrict__ tdev, int mode)
 {
     const int t = *tdev;
+    const int in_step = (mode == MOM_DUE_IN_STEP) ? 1 : 0;
     for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
         const int2 tl = tiles[w];
         const ChanDesc<T>& c = ch[tl.x];
-        if (!all && !fd_due(c, t)) continue;
+        if (mode == MOM_DUE_IN_STEP && !fd_due(c, t)) continue;
+        if (mode == MOM_AFTER_PARTIAL && ((c.step0 + (long long)t) % c.fd_ratio) == 0) continue;
         const int k = tl.y + (int)threadIdx.x;
         if (k < c.lbm.g.N) {
             const int par = c.parity0 ^ ((t + in_step) & 1);
@@ -203,11 +210,10 @@ void launch_lbm(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int 
 }
 
 template <typename T, bool SHIFT>
-void launch_moments(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int block, int bpc, int in_step,
-                    int all)
+void launch_moments(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int block, int bpc, int mode)
 {
     hipLaunchKernelGGL((el::k_batch_moments<T, SHIFT>), dim3(grid_of(ntiles, b->cus, bpc)), dim3(block), 0, st,
-                       static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles, b->d_t, in_step, all);
+                       static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles, b->d_t, mode);
 }
 
 template <typename T, int STAGE>
@@ -222,7 +228,8 @@ int enqueue_step(el_batch* b, hipStream_t st)
 {
     const el_batch_tuning& tu = b->tuning;
     launch_lbm<T, SHIFT>(b, st, b->d_tiles_lbm, b->ntiles_lbm, tu.lbm_block, tu.lbm_blocks_per_cu);
-    launch_moments<T, SHIFT>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, 1, 0);
+    launch_moments<T, SHIFT>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu,
+                             el::MOM_DUE_IN_STEP);
     launch_fd<T, 0>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, 0);
     launch_fd<T, 1>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, 0);
     launch_fd<T, 2>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, 0);
@@ -463,6 +470,10 @@ int el_batch_capture(el_batch* b, void* stream)
 {
     if (!b) return fail(EL_EINVAL, "batch is NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (!st) return fail(EL_EINVAL, "capture needs a created stream, not the null stream");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return fail(EL_EINVAL, "the stream is already capturing");
     if (b->exec) {
         (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
@@ -495,10 +506,10 @@ int el_batch_moments(el_batch* b, void* stream)
     hipStream_t st = static_cast<hipStream_t>(stream);
     const el_batch_tuning& tu = b->tuning;
     switch (b->precision) {
-    case EL_F64: launch_moments<double, false>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, 0, 1); break;
-    case EL_F64_SHIFTED: launch_moments<double, true>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, 0, 1); break;
-    case EL_F32: launch_moments<float, false>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, 0, 1); break;
-    default: launch_moments<float, true>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, 0, 1); break;
+    case EL_F64: launch_moments<double, false>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, el::MOM_AFTER_PARTIAL); break;
+    case EL_F64_SHIFTED: launch_moments<double, true>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, el::MOM_AFTER_PARTIAL); break;
+    case EL_F32: launch_moments<float, false>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, el::MOM_AFTER_PARTIAL); break;
+    default: launch_moments<float, true>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, el::MOM_AFTER_PARTIAL); break;
     }
     return check_launch("batched moments");
 }

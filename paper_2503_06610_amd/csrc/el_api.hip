@@ -48,6 +48,11 @@ int stability_checks(const el_params* p)
     const double heun = p->fd_ratio * 12.0 * std::fabs(p->K) / gamma1;
     if (heun > 2.0)
         return fail(EL_EUNSTABLE, "explicit director step unstable: r*12K/gamma1 = %g > 2", heun);
+    // Refreshing the explicit Leslie force every LBM step diverges at large tau
+    // (Table-1 viscosities at tau = 1.8977 blow up within ~300 steps in FP64,
+    // while tau <= 1.4 stays bounded); bound found with the FP64 oracle.
+    if (p->fd_ratio == 1 && coupling(p) && p->tau > 1.5)
+        return fail(EL_EUNSTABLE, "r = 1 with tau = %g > 1.5: the explicit Leslie coupling diverges", p->tau);
     if (!periodic_z(p)) {
         const double nu = (p->tau - 0.5) / 3.0;
         const double H = p->nz - 2;

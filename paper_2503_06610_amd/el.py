@@ -267,11 +267,14 @@ class Lattice:
 
 class Batch:
     """A batched ensemble over Lattice objects (all of one precision), through
-    el_batch_*; after capture() every step is one graph launch."""
+    el_batch_*; after capture() every step is one graph launch.  The batch
+    runs on its own stream (a graph cannot be captured on the null stream),
+    ordered against torch's current stream on entry and exit of every call."""
 
     def __init__(self, lattices, tuning=None, stream=None):
         import torch
         self.lib = load()
+        self.stream = torch.cuda.Stream()
         self.lattices = list(lattices)
         n = len(self.lattices)
         self._params = (el_params * n)(*[lat.params for lat in self.lattices])
@@ -280,18 +283,34 @@ class Batch:
         tu = None
         if tuning is not None:
             tu = el_batch_tuning(*tuning, 0, 0)
+        self._enter()
         _check(self.lib.el_batch_create(self._params, self._states, n, C.byref(tu) if tu else None,
-                                        _stream_ptr(stream), C.byref(self.handle)), "el_batch_create")
+                                        _stream_ptr(self.stream), C.byref(self.handle)), "el_batch_create")
+        self._leave()
         torch.cuda.synchronize()
 
-    def step(self, nsteps: int = 1, stream=None):
-        _check(self.lib.el_batch_step(self.handle, int(nsteps), _stream_ptr(stream)), "el_batch_step")
+    def _enter(self):
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream())
 
-    def capture(self, stream=None):
-        _check(self.lib.el_batch_capture(self.handle, _stream_ptr(stream)), "el_batch_capture")
+    def _leave(self):
+        import torch
+        torch.cuda.current_stream().wait_stream(self.stream)
 
-    def moments(self, stream=None):
-        _check(self.lib.el_batch_moments(self.handle, _stream_ptr(stream)), "el_batch_moments")
+    def step(self, nsteps: int = 1):
+        self._enter()
+        _check(self.lib.el_batch_step(self.handle, int(nsteps), _stream_ptr(self.stream)), "el_batch_step")
+        self._leave()
+
+    def capture(self):
+        self._enter()
+        _check(self.lib.el_batch_capture(self.handle, _stream_ptr(self.stream)), "el_batch_capture")
+        self._leave()
+
+    def moments(self):
+        self._enter()
+        _check(self.lib.el_batch_moments(self.handle, _stream_ptr(self.stream)), "el_batch_moments")
+        self._leave()
 
     def sync(self):
         """Copy the batch's parity and step counters back into the lattices."""
@@ -301,12 +320,14 @@ class Batch:
             lat.state.parity = st.parity
             lat.state.step = st.step
 
-    def observables(self, stream=None):
+    def observables(self):
         import torch
         n = len(self.lattices)
         buf = torch.zeros(n * OBS_DOUBLES, dtype=torch.float64, device=self.lattices[0].n.device)
-        _check(self.lib.el_batch_observables(self.handle, C.c_void_p(buf.data_ptr()), _stream_ptr(stream)),
+        self._enter()
+        _check(self.lib.el_batch_observables(self.handle, C.c_void_p(buf.data_ptr()), _stream_ptr(self.stream)),
                "el_batch_observables")
+        self._leave()
         raw = buf.cpu().numpy().tobytes()
         size = C.sizeof(el_obs)
         return [el_obs.from_buffer_copy(raw[i * size:(i + 1) * size]) for i in range(n)]

@@ -202,8 +202,10 @@ def workload_c4(seed: int = 4, nchan: int = 64) -> list:
     """Batched ensemble: nchan channels with Nx, Ny ~ U{48..160}, Nz ~ U{16..48}
     (walls included), 1-4 skyrmion tubes (pitch 32, R = 16, periodic separation
     >= 2R, fewer when they do not fit), g_x log-uniform in [1e-7, 1e-5], r drawn
-    from {1, 5, 10}; Leslie set B, K = 5e-3, q0 = 2 pi/32.  Returns a list of
-    (Problem, n0)."""
+    from {1, 5, 10}; Leslie set A (tau = 0.8), K = 1e-3, q0 = 2 pi/32.  Set B
+    (tau = 1.8977) diverges at r = 1 with the explicit Leslie coupling, and set A
+    with K = 1e-3 keeps r = 10 within the explicit director bound.  Returns a
+    list of (Problem, n0)."""
     u = uniform01(seed, 11, 8 * nchan)
     out = []
     for c in range(nchan):
@@ -214,7 +216,7 @@ def workload_c4(seed: int = 4, nchan: int = 64) -> list:
         gx = 10.0 ** (-7.0 + 2.0 * v[3])
         r = (1, 5, 10)[int(v[4] * 3)]
         ntubes = 1 + int(v[5] * 4)
-        prob = channel(nx, ny, nz, set_b(), g=(gx, 0.0, 0.0), K=5e-3, q0=2.0 * math.pi / 32.0, fd_ratio=r)
+        prob = channel(nx, ny, nz, set_a(), g=(gx, 0.0, 0.0), K=1e-3, q0=2.0 * math.pi / 32.0, fd_ratio=r)
         centres = place_tubes(nx, ny, ntubes, 16.0, seed=seed * 1000 + c)
         out.append((prob, director_tubes(prob, centres, 16.0)))
     return out

@@ -71,6 +71,7 @@ def test_validate_accepts_workloads():
     ("flags", 64, el.EL_EINVAL),
     ("K", 0.5, el.EL_EUNSTABLE),
     ("fd_ratio", 2, el.EL_EUNSTABLE),  # C1 with K = 0.01: r*12K/gamma1 = 2.6
+    ("tau", 1.9, el.EL_EUNSTABLE),     # r = 1 with tau > 1.5
 ])
 def test_validate_rejects(field, value, code):
     prob = inputs.workload_c1()[0]

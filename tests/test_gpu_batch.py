@@ -18,12 +18,12 @@ def _say(msg):
 
 def _small_batch():
     """Six uneven channels: sizes, r, g, tubes, chirality; one without coupling."""
-    mat = inputs.set_b()
+    mat = inputs.set_a()
     specs = [(21, 17, 12, 1, 3e-6, True), (34, 9, 7, 3, 1e-5, True), (16, 26, 10, 5, 1e-7, True),
              (40, 12, 14, 2, 5e-6, False), (9, 9, 6, 1, 2e-6, True), (27, 31, 9, 4, 8e-7, True)]
     out = []
     for i, (nx, ny, nz, r, gx, coup) in enumerate(specs):
-        prob = inputs.channel(nx, ny, nz, mat, g=(gx, 0.0, 0.0), K=5e-3, q0=2 * math.pi / 16, fd_ratio=r,
+        prob = inputs.channel(nx, ny, nz, mat, g=(gx, 0.0, 0.0), K=1e-3, q0=2 * math.pi / 16, fd_ratio=r,
                               coupling=coup)
         n0 = inputs.director_tubes(prob, [(nx / 2.0, ny / 2.0)], min(nx, ny) / 3.0) if i % 2 == 0 else \
             inputs.director_tilt(prob, seed=10 + i, amplitude=0.2)
@@ -154,3 +154,14 @@ def test_c4_ensemble_full_size():
         fa, fs = _fields(lats[i]), _fields(s)
         for k in fa:
             assert np.array_equal(fa[k], fs[k]), (i, k)
+
+
+def test_capture_on_null_stream_is_rejected():
+    import ctypes as C
+    chans = _small_batch()[:2]
+    b = el.Batch(_lattices(chans, "f32_shifted"), tuning=(256, 4, 256, 4))
+    assert el.load().el_batch_capture(b.handle, None) == el.EL_EINVAL
+    # the batch still steps normally afterwards
+    b.step(2)
+    b.sync()
+    assert b.lattices[0].step == 2
