@@ -76,7 +76,9 @@ enum {
     EL_PERIODIC_Z = 1,            /* no walls: z periodic (analytic test cases) */
     EL_NO_COUPLING = 2,           /* F^LC held at zero: plain Guo-forced LBM */
     EL_NO_RENORM_PREDICTOR = 4,   /* do not normalise the Heun predictor */
-    EL_ALLOW_UNSTABLE = 8         /* skip the stability checks of el_validate */
+    EL_ALLOW_UNSTABLE = 8,        /* skip the stability checks of el_validate */
+    EL_FREEZE_DIRECTOR = 16       /* el_step_director only refreshes F^LC (quasi-steady flow
+                                     of a fixed director, used to make surrogate training pairs) */
 };
 
 typedef struct {
@@ -258,6 +260,74 @@ int el_batch_get_tuning(const el_batch* b, el_batch_tuning* out);
 /* Frees the handle and its device tables (not the channels' buffers);
  * waits for work on the handle's streams to finish. */
 int el_batch_destroy(el_batch* b);
+
+/* ------------------------------------------------------------------------
+ * Warm-start surrogate: a 3x3x3 convolutional network that maps the director
+ * and the analytic Poiseuille profile to the quasi-steady velocity, so the
+ * flow transient of a frozen director can be skipped.  BF16 weights and
+ * activations, FP32 accumulation on the gfx950 matrix cores (MFMA 16x16x32).
+ *
+ * Activations are BF16, channels-last, sample after sample, each sample with
+ * one halo plane below and above its fluid layers:
+ *   act[s][zf + 1][y][x][C],  zf = -1 .. nzf,  C channels stored;
+ * x and y are periodic; the halo planes hold the padding (wall director
+ * (0, 0, 1) and 0 for the network input, 0 for hidden activations; the caller
+ * allocates the arrays zero-filled).  Weights: w[co][tap][ci] with
+ * tap = (dz+1)*9 + (dy+1)*3 + (dx+1) and stored (padded) channel counts;
+ * the backward-data copy is wt[ci][26 - tap][co].
+ * Supported layers: 8 -> 32 and 32 -> 32 (BF16 output, optional ReLU) and
+ * 32 -> 3 (FP32 channel-major output res[c][s*N + v], no activation).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t nx, ny, nzf;    /* fluid voxels per sample */
+    int32_t nsamples;
+} el_nn_vol;
+
+/* Network input of one sample (director n of a lattice, T SoA [3][N]):
+ * channels (n_x, n_y, n_z, u_P(z)/V0, 0, 0, 0, 0) with the analytic
+ * Poiseuille velocity u_P = g_x/(2 nu) (z - 1/2)(nz - 3/2 - z) of the channel
+ * (nu = (tau - 1/2)/3, wall midway), and the halo planes (0, 0, 1, 0, ...).
+ * act0 holds nsamples samples of 8 channels; V0 > 0 is the velocity unit. */
+int el_nn_input(const el_params* p, const void* n, void* act0, int32_t sample, int32_t nsamples, float V0,
+                void* stream);
+
+/* y = act(conv(x, w) + bias) over every sample (see above for cin/cout). */
+int el_nn_conv_forward(const el_nn_vol* v, int32_t cin, int32_t cout, const void* x, const void* w,
+                       const float* bias, int32_t relu, void* y, void* stream);
+
+/* dx = conv^T(dy, w) [* (mask > 0)] for a layer with cin = 32 input channels
+ * and cout = 32 or 16 stored output-gradient channels; wt is the flipped,
+ * transposed kernel; mask (the layer's input activations) applies the ReLU
+ * derivative of the layer below, or NULL. */
+int el_nn_conv_backward_data(const el_nn_vol* v, int32_t cin, int32_t cout, const void* dy, const void* wt,
+                             const void* mask, void* dx, void* stream);
+
+/* Scratch bytes el_nn_conv_backward_weight needs. */
+size_t el_nn_work_bytes(const el_nn_vol* v, int32_t cin, int32_t cout);
+
+/* dw[co][tap][ci] = sum_v dy[v][co] x[v + d_tap][ci] and db[co] = sum_v dy[v][co]
+ * (FP32, summed over fixed voxel chunks in a fixed order: deterministic).
+ * (cin, cout) in {(8, 32), (32, 32), (32, 16)}. */
+int el_nn_conv_backward_weight(const el_nn_vol* v, int32_t cin, int32_t cout, const void* x, const void* dy,
+                               void* work, size_t work_bytes, float* dw, float* db, void* stream);
+
+/* Mean squared error of pred against target (FP32 [3][n_all]): partial sums
+ * of the loss in partial[0..npartial-1] (their sum is the loss) and the
+ * gradient dy = 2 (pred - target)/(3 n_all) as 16-channel BF16 activations. */
+int el_nn_mse(const el_nn_vol* v, const float* pred, const float* target, void* dy, double* partial,
+              int32_t npartial, void* stream);
+
+/* One Adam step (step >= 1) on FP32 master weights w[n] with moments m, v;
+ * writes the BF16 copies wfwd (same layout) and, if wt != NULL, the
+ * backward-data copy for a [cout][27][cin] kernel. */
+int el_nn_adam(float* w, float* m, float* v, const float* grad, int32_t n, float lr, float beta1, float beta2,
+               float eps, int32_t step, void* wfwd, void* wt, int32_t cout, int32_t cin, void* stream);
+
+/* Velocity of one sample from the network output res (FP32 [3][n_all]):
+ * u = V0 res + u_P(z) x-hat (u_P as in el_nn_input), written as T SoA
+ * [3][N] of the lattice p describes (ready for el_init_flow). */
+int el_nn_velocity(const el_params* p, const float* res, int32_t sample, int32_t nsamples, float V0, void* u,
+                   void* stream);
 
 #ifdef __cplusplus
 }

@@ -31,6 +31,7 @@ struct ChanDesc {
     LbmArgs<T> lbm;
     FdArgs<T> fd;
     int fd_ratio;
+    int frozen;       // 1: the FD step only refreshes F^LC (director fixed)
     int parity0;      // q[parity0] is current when the batch is created
     long long step0;  // LBM steps the channel had taken when the batch was created
 };
@@ -97,6 +98,7 @@ __global__ void __launch_bounds__(1024) k_batch_fd(const ChanDesc<T>* __restrict
         const int2 tl = tiles[w];
         const ChanDesc<T>& c = ch[tl.x];
         if (!all && !fd_due(c, t)) continue;
+        if (STAGE <= 1 && c.frozen) continue;
         const int k = tl.y + (int)threadIdx.x;
         if (k >= c.fd.g.N) continue;
         if (STAGE == 0) {
@@ -190,6 +192,7 @@ int build_table(el_batch* b)
         d.lbm = lbm_args<T>(p);
         d.fd = fd_args<T>(p);
         d.fd_ratio = p->fd_ratio;
+        d.frozen = (p->flags & EL_FREEZE_DIRECTOR) ? 1 : 0;
         d.parity0 = s->parity;
         d.step0 = s->step;
     }

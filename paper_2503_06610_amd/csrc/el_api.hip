@@ -25,7 +25,7 @@ int basic_checks(const el_params* p)
     if (!p) return fail(EL_EINVAL, "params is NULL");
     if (p->precision < EL_F64 || p->precision > EL_F32_SHIFTED)
         return fail(EL_EINVAL, "unknown precision %d", p->precision);
-    if (p->flags & ~(EL_PERIODIC_Z | EL_NO_COUPLING | EL_NO_RENORM_PREDICTOR | EL_ALLOW_UNSTABLE))
+    if (p->flags & ~(EL_PERIODIC_Z | EL_NO_COUPLING | EL_NO_RENORM_PREDICTOR | EL_ALLOW_UNSTABLE | EL_FREEZE_DIRECTOR))
         return fail(EL_EINVAL, "unknown flags 0x%x", p->flags);
     if (p->nx < 3 || p->ny < 3 || (periodic_z(p) ? p->nz < 3 : p->nz < 4))
         return fail(EL_EINVAL, "lattice %dx%dx%d too small", p->nx, p->ny, p->nz);
@@ -128,6 +128,7 @@ int launch_director(const el_params* p, el_state* s, hipStream_t st)
 {
     const el::FdArgs<T> a = fd_args<T>(p);
     const int grid = grid_for(a.g.N);
+    if (p->flags & EL_FREEZE_DIRECTOR) return launch_force<T>(p, s, st);
     hipLaunchKernelGGL((el::k_fd_predictor<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
                        static_cast<const T*>(s->u), static_cast<T*>(s->n_pred), static_cast<T*>(s->dndt), a);
     hipLaunchKernelGGL((el::k_fd_corrector<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<T*>(s->n),

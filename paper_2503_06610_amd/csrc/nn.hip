@@ -1,0 +1,212 @@
+// nn.hip -- C ABI of the warm-start surrogate: network input from the
+// director, BF16-MFMA convolutions (forward, backward-data, backward-weight),
+// MSE loss, Adam, and the velocity the flow is initialised from.
+#include "host_common.hpp"
+#include "nn_kernels.hpp"
+
+namespace {
+using namespace elh;
+using el::nn::VolGeom;
+
+constexpr int NN_CHUNK = 2048;  // voxels per block in the weight-gradient reduction
+
+int vol_of(const el_nn_vol* v, VolGeom* g)
+{
+    if (!v) return fail(EL_EINVAL, "volume is NULL");
+    if (v->nx < 3 || v->ny < 3 || v->nzf < 1 || v->nsamples < 1)
+        return fail(EL_EINVAL, "volume %dx%dx%d x %d invalid", v->nx, v->ny, v->nzf, v->nsamples);
+    g->nx = v->nx;
+    g->ny = v->ny;
+    g->nzf = v->nzf;
+    g->nsamples = v->nsamples;
+    const long long n_int = (long long)v->nx * v->ny * v->nzf;
+    if (n_int >= (1LL << 31)) return fail(EL_EINVAL, "sample too large");
+    g->n_int = (int)n_int;
+    g->n_all = n_int * v->nsamples;
+    return EL_OK;
+}
+
+int conv_blocks(const VolGeom& g) { return (int)((g.n_all + 63) / 64); }
+
+int wgrad_blocks(const VolGeom& g) { return (int)((g.n_all + NN_CHUNK - 1) / NN_CHUNK); }
+
+int pitch_of(int cin) { return ((27 * cin + 15) / 16) * 16; }
+
+// g_x / (2 nu V0): the Poiseuille velocity is this times (z - 1/2)(nz - 3/2 - z) V0.
+float poiseuille_coeff(const el_params* p, float V0) { return (float)(p->g[0] / (2.0 * (p->tau - 0.5) / 3.0) / V0); }
+
+}  // namespace
+
+extern "C" {
+
+int el_nn_input(const el_params* p, const void* n, void* act0, int32_t sample, int32_t nsamples, float V0,
+                void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if (!n || !act0) return fail(EL_EINVAL, "NULL pointer");
+    if (periodic_z(p)) return fail(EL_EINVAL, "the surrogate needs walls");
+    if (sample < 0 || sample >= nsamples) return fail(EL_EINVAL, "sample %d of %d", sample, nsamples);
+    if (!(V0 > 0.0f)) return fail(EL_EINVAL, "V0 must be positive");
+    el_nn_vol v{p->nx, p->ny, p->nz - 2, nsamples};
+    VolGeom g;
+    if ((rc = vol_of(&v, &g)) != EL_OK) return rc;
+    const float c = poiseuille_coeff(p, V0);
+    const long long per = (long long)g.nx * g.ny * (g.nzf + 2);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int grid = (int)((per + 255) / 256);
+    if (is_f64(p))
+        hipLaunchKernelGGL((el::nn::k_nn_input<double>), dim3(grid), dim3(256), 0, st, static_cast<const double*>(n),
+                           static_cast<__bf16*>(act0), g, sample, c);
+    else
+        hipLaunchKernelGGL((el::nn::k_nn_input<float>), dim3(grid), dim3(256), 0, st, static_cast<const float*>(n),
+                           static_cast<__bf16*>(act0), g, sample, c);
+    return check_launch("k_nn_input");
+}
+
+int el_nn_conv_forward(const el_nn_vol* vol, int32_t cin, int32_t cout, const void* x, const void* w,
+                       const float* bias, int32_t relu, void* y, void* stream)
+{
+    VolGeom g;
+    int rc = vol_of(vol, &g);
+    if (rc != EL_OK) return rc;
+    if (!x || !w || !y) return fail(EL_EINVAL, "NULL pointer");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const dim3 grid(conv_blocks(g)), block(256);
+    const __bf16* X = static_cast<const __bf16*>(x);
+    const __bf16* W = static_cast<const __bf16*>(w);
+    if (cout == 3) {
+        if (relu) return fail(EL_EINVAL, "the FP32 output layer has no activation");
+        if (cin == 32)
+            hipLaunchKernelGGL((el::nn::k_conv<32, 1, false, true>), grid, block, 0, st, X, W, bias, nullptr, y, g, 3);
+        else
+            return fail(EL_EINVAL, "output layer needs cin = 32");
+    } else if (cout == 32 && cin == 8) {
+        if (relu)
+            hipLaunchKernelGGL((el::nn::k_conv<8, 2, true, false>), grid, block, 0, st, X, W, bias, nullptr, y, g, 32);
+        else
+            hipLaunchKernelGGL((el::nn::k_conv<8, 2, false, false>), grid, block, 0, st, X, W, bias, nullptr, y, g, 32);
+    } else if (cout == 32 && cin == 32) {
+        if (relu)
+            hipLaunchKernelGGL((el::nn::k_conv<32, 2, true, false>), grid, block, 0, st, X, W, bias, nullptr, y, g, 32);
+        else
+            hipLaunchKernelGGL((el::nn::k_conv<32, 2, false, false>), grid, block, 0, st, X, W, bias, nullptr, y, g, 32);
+    } else {
+        return fail(EL_EINVAL, "unsupported conv %d -> %d", cin, cout);
+    }
+    return check_launch("k_conv forward");
+}
+
+int el_nn_conv_backward_data(const el_nn_vol* vol, int32_t cin, int32_t cout, const void* dy, const void* wt,
+                             const void* mask, void* dx, void* stream)
+{
+    VolGeom g;
+    int rc = vol_of(vol, &g);
+    if (rc != EL_OK) return rc;
+    if (!dy || !wt || !dx) return fail(EL_EINVAL, "NULL pointer");
+    if (cin != 32) return fail(EL_EINVAL, "backward-data is computed for cin = 32 layers only");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const dim3 grid(conv_blocks(g)), block(256);
+    const __bf16* DY = static_cast<const __bf16*>(dy);
+    const __bf16* WT = static_cast<const __bf16*>(wt);
+    const __bf16* M = static_cast<const __bf16*>(mask);
+    if (cout == 32)
+        hipLaunchKernelGGL((el::nn::k_conv<32, 2, false, false>), grid, block, 0, st, DY, WT, nullptr, M, dx, g, 32);
+    else if (cout == 16)
+        hipLaunchKernelGGL((el::nn::k_conv<16, 2, false, false>), grid, block, 0, st, DY, WT, nullptr, M, dx, g, 32);
+    else
+        return fail(EL_EINVAL, "unsupported backward-data cout = %d", cout);
+    return check_launch("k_conv backward-data");
+}
+
+size_t el_nn_work_bytes(const el_nn_vol* vol, int32_t cin, int32_t cout)
+{
+    VolGeom g;
+    if (vol_of(vol, &g) != EL_OK) return 0;
+    return (size_t)wgrad_blocks(g) * (size_t)cout * (size_t)(pitch_of(cin) + 1) * sizeof(float);
+}
+
+int el_nn_conv_backward_weight(const el_nn_vol* vol, int32_t cin, int32_t cout, const void* x, const void* dy,
+                               void* work, size_t work_bytes, float* dw, float* db, void* stream)
+{
+    VolGeom g;
+    int rc = vol_of(vol, &g);
+    if (rc != EL_OK) return rc;
+    if (!x || !dy || !work || !dw || !db) return fail(EL_EINVAL, "NULL pointer");
+    if (work_bytes < el_nn_work_bytes(vol, cin, cout)) return fail(EL_ENOMEM, "work buffer too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nb = wgrad_blocks(g);
+    float* part = static_cast<float*>(work);
+    float* bpart = part + (size_t)nb * cout * pitch_of(cin);
+    const __bf16* X = static_cast<const __bf16*>(x);
+    const __bf16* DY = static_cast<const __bf16*>(dy);
+    if (cin == 8 && cout == 32) {
+        hipLaunchKernelGGL((el::nn::k_conv_wgrad<8, 2>), dim3(nb), dim3(256), 0, st, X, DY, part, g, NN_CHUNK);
+        hipLaunchKernelGGL((el::nn::k_bias_grad<32>), dim3(nb), dim3(256), 0, st, DY, bpart, g, NN_CHUNK);
+    } else if (cin == 32 && cout == 32) {
+        hipLaunchKernelGGL((el::nn::k_conv_wgrad<32, 2>), dim3(nb), dim3(256), 0, st, X, DY, part, g, NN_CHUNK);
+        hipLaunchKernelGGL((el::nn::k_bias_grad<32>), dim3(nb), dim3(256), 0, st, DY, bpart, g, NN_CHUNK);
+    } else if (cin == 32 && cout == 16) {
+        hipLaunchKernelGGL((el::nn::k_conv_wgrad<32, 1>), dim3(nb), dim3(256), 0, st, X, DY, part, g, NN_CHUNK);
+        hipLaunchKernelGGL((el::nn::k_bias_grad<16>), dim3(nb), dim3(256), 0, st, DY, bpart, g, NN_CHUNK);
+    } else {
+        return fail(EL_EINVAL, "unsupported weight gradient %d -> %d", cin, cout);
+    }
+    const int nw = cout * 27 * cin;
+    hipLaunchKernelGGL(el::nn::k_sum_partials, dim3((nw + 255) / 256), dim3(256), 0, st,
+                       static_cast<const float*>(part), nb, cout, pitch_of(cin), 27 * cin, dw);
+    hipLaunchKernelGGL(el::nn::k_sum_partials, dim3(1), dim3(256), 0, st, static_cast<const float*>(bpart), nb, 1,
+                       cout, cout, db);
+    return check_launch("weight-gradient kernels");
+}
+
+int el_nn_mse(const el_nn_vol* vol, const float* pred, const float* target, void* dy, double* partial,
+              int32_t npartial, void* stream)
+{
+    VolGeom g;
+    int rc = vol_of(vol, &g);
+    if (rc != EL_OK) return rc;
+    if (!pred || !target || !dy || !partial || npartial < 1) return fail(EL_EINVAL, "bad argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL((el::nn::k_mse<16>), dim3(npartial), dim3(256), 0, st, pred, target,
+                       static_cast<__bf16*>(dy), partial, g);
+    return check_launch("k_mse");
+}
+
+int el_nn_adam(float* w, float* m, float* v, const float* grad, int32_t n, float lr, float beta1, float beta2,
+               float eps, int32_t step, void* wfwd, void* wbwd, int32_t cout, int32_t cin, void* stream)
+{
+    if (!w || !m || !v || !grad || n < 1 || step < 1) return fail(EL_EINVAL, "bad argument");
+    if (wbwd && n != cout * 27 * cin) return fail(EL_EINVAL, "n != cout*27*cin");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const float c1 = 1.0f - powf(beta1, (float)step);
+    const float c2 = 1.0f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(el::nn::k_adam, dim3((n + 255) / 256), dim3(256), 0, st, w, m, v, grad, n, lr, beta1, beta2,
+                       eps, c1, c2, static_cast<__bf16*>(wfwd), static_cast<__bf16*>(wbwd), cout, cin);
+    return check_launch("k_adam");
+}
+
+int el_nn_velocity(const el_params* p, const float* res, int32_t sample, int32_t nsamples, float V0, void* u,
+                   void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if (!res || !u) return fail(EL_EINVAL, "NULL pointer");
+    if (sample < 0 || sample >= nsamples) return fail(EL_EINVAL, "sample %d of %d", sample, nsamples);
+    if (!(V0 > 0.0f)) return fail(EL_EINVAL, "V0 must be positive");
+    el_nn_vol v{p->nx, p->ny, p->nz - 2, nsamples};
+    VolGeom g;
+    if ((rc = vol_of(&v, &g)) != EL_OK) return rc;
+    const float c = poiseuille_coeff(p, V0);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int grid = (int)((g.n_int + 255) / 256);
+    if (is_f64(p))
+        hipLaunchKernelGGL((el::nn::k_nn_velocity<double>), dim3(grid), dim3(256), 0, st, res, static_cast<double*>(u),
+                           g, sample, V0, c);
+    else
+        hipLaunchKernelGGL((el::nn::k_nn_velocity<float>), dim3(grid), dim3(256), 0, st, res, static_cast<float*>(u),
+                           g, sample, V0, c);
+    return check_launch("k_nn_velocity");
+}
+
+}  // extern "C"

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libel.so")
 
 EL_OK, EL_EINVAL, EL_EUNSTABLE, EL_EDEVICE, EL_ENAN, EL_ENOMEM = 0, -1, -2, -3, -4, -5
 EL_F64, EL_F64_SHIFTED, EL_F32, EL_F32_SHIFTED = 0, 1, 2, 3
-EL_PERIODIC_Z, EL_NO_COUPLING, EL_NO_RENORM_PREDICTOR, EL_ALLOW_UNSTABLE = 1, 2, 4, 8
+EL_PERIODIC_Z, EL_NO_COUPLING, EL_NO_RENORM_PREDICTOR, EL_ALLOW_UNSTABLE, EL_FREEZE_DIRECTOR = 1, 2, 4, 8, 16
 EL_BUF_Q, EL_BUF_VEC3, EL_BUF_SCRATCH = 0, 1, 2
 
 PRECISIONS = {"f64": EL_F64, "f64_shifted": EL_F64_SHIFTED, "f32": EL_F32, "f32_shifted": EL_F32_SHIFTED}
@@ -27,7 +27,9 @@ PRECISIONS = {"f64": EL_F64, "f64_shifted": EL_F64_SHIFTED, "f32": EL_F32, "f32_
 EXPORTED = ("el_version", "el_strerror", "el_last_error", "el_buffer_bytes", "el_validate", "el_init_lattice",
             "el_init_flow", "el_step_lbm", "el_moments", "el_step_director", "el_force", "el_run",
             "el_observables", "el_error_norms", "el_batch_create", "el_batch_step", "el_batch_capture",
-            "el_batch_moments", "el_batch_observables", "el_batch_sync", "el_batch_get_tuning", "el_batch_destroy")
+            "el_batch_moments", "el_batch_observables", "el_batch_sync", "el_batch_get_tuning", "el_batch_destroy",
+            "el_nn_input", "el_nn_conv_forward", "el_nn_conv_backward_data", "el_nn_work_bytes",
+            "el_nn_conv_backward_weight", "el_nn_mse", "el_nn_adam", "el_nn_velocity")
 
 
 class ElError(RuntimeError):
@@ -62,6 +64,10 @@ OBS_DOUBLES = C.sizeof(el_obs) // 8
 class el_batch_tuning(C.Structure):
     _fields_ = [("lbm_block", C.c_int32), ("lbm_blocks_per_cu", C.c_int32), ("fd_block", C.c_int32),
                 ("fd_blocks_per_cu", C.c_int32), ("tuned", C.c_int32), ("reserved", C.c_int32)]
+
+class el_nn_vol(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nzf", C.c_int32), ("nsamples", C.c_int32)]
+
 
 _lib = None
 
@@ -98,6 +104,16 @@ def load(path: str = LIB_PATH):
         "el_batch_sync": (C.c_int, [V, S, C.c_int32]),
         "el_batch_get_tuning": (C.c_int, [V, C.POINTER(el_batch_tuning)]),
         "el_batch_destroy": (C.c_int, [V]),
+        "el_nn_input": (C.c_int, [P, V, V, C.c_int32, C.c_int32, C.c_float, V]),
+        "el_nn_conv_forward": (C.c_int, [C.POINTER(el_nn_vol), C.c_int32, C.c_int32, V, V, V, C.c_int32, V, V]),
+        "el_nn_conv_backward_data": (C.c_int, [C.POINTER(el_nn_vol), C.c_int32, C.c_int32, V, V, V, V, V]),
+        "el_nn_work_bytes": (C.c_size_t, [C.POINTER(el_nn_vol), C.c_int32, C.c_int32]),
+        "el_nn_conv_backward_weight": (C.c_int, [C.POINTER(el_nn_vol), C.c_int32, C.c_int32, V, V, V, C.c_size_t,
+                                                 V, V, V]),
+        "el_nn_mse": (C.c_int, [C.POINTER(el_nn_vol), V, V, V, V, C.c_int32, V]),
+        "el_nn_adam": (C.c_int, [V, V, V, V, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32,
+                                 V, V, C.c_int32, C.c_int32, V]),
+        "el_nn_velocity": (C.c_int, [P, V, C.c_int32, C.c_int32, C.c_float, V, V]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -151,7 +167,8 @@ def _stream_ptr(stream=None):
 class Lattice:
     """Device buffers of one channel (torch tensors) and the C-ABI calls on them."""
 
-    def __init__(self, prob, precision: str = "f32_shifted", device: str = "cuda", allow_unstable: bool = False):
+    def __init__(self, prob, precision: str = "f32_shifted", device: str = "cuda", allow_unstable: bool = False,
+                 freeze_director: bool = False):
         import torch
         self.lib = load()
         self.prob = prob
@@ -159,6 +176,8 @@ class Lattice:
         self.params = make_params(prob, precision)
         if allow_unstable:
             self.params.flags |= EL_ALLOW_UNSTABLE
+        if freeze_director:
+            self.params.flags |= EL_FREEZE_DIRECTOR
         _check(self.lib.el_validate(C.byref(self.params)), "el_validate")
         self.dtype = torch.float64 if precision.startswith("f64") else torch.float32
         self.N = prob.fluid_nodes

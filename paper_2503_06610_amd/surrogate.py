@@ -1,0 +1,312 @@
+"""Learned warm start of the quasi-steady flow (through the el_nn_* C ABI).
+
+A 4-layer 3x3x3 convolutional network (4 -> 32 -> 32 -> 32 -> 3 channels,
+ReLU on the hidden layers) maps the director and the analytic Poiseuille
+velocity u_P (both as network input channels) to the residual
+(u - u_P x-hat)/V0 of the quasi-steady velocity of a frozen director.  The
+flow is then started from the equilibrium at that velocity instead of rest,
+and the solver finishes the transient; the solver is both the fallback (cold
+start) and the judge of the surrogate's error.
+
+Everything that touches the data runs in libel.so's kernels (BF16 MFMA
+convolutions with FP32 accumulation, loss, Adam); this module allocates the
+buffers (torch) and sequences the calls.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import time
+
+import numpy as np
+
+from paper_2503_06610_amd import el, inputs
+
+V0 = 1e-3  # velocity unit of the network's input channel and output
+
+# (stored input channels, stored output channels, real output channels, ReLU)
+LAYERS = [(8, 32, 32, True), (32, 32, 32, True), (32, 32, 32, True), (32, 16, 3, False)]
+REAL_CIN = [4, 32, 32, 32]
+
+
+def _vp(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Surrogate:
+    def __init__(self, seed: int = 0, device: str = "cuda", lr: float = 1e-3):
+        import torch
+        self.lib = el.load()
+        self.dev = torch.device(device)
+        self.lr = lr
+        self.step_count = 0
+        gen = torch.Generator().manual_seed(seed)
+        self.w, self.m, self.v, self.gw, self.wf, self.wt = [], [], [], [], [], []
+        self.b, self.bm, self.bv, self.gb = [], [], [], []
+        for li, (cin, cout, cout_real, relu) in enumerate(LAYERS):
+            std = math.sqrt(2.0 / (27 * REAL_CIN[li])) if relu else 0.1 * math.sqrt(1.0 / (27 * REAL_CIN[li]))
+            w = torch.zeros(cout, 27, cin, dtype=torch.float32)
+            w[:cout_real, :, :REAL_CIN[li]] = torch.randn(cout_real, 27, REAL_CIN[li], generator=gen) * std
+            self.w.append(w.reshape(-1).to(self.dev))
+            self.m.append(torch.zeros_like(self.w[-1]))
+            self.v.append(torch.zeros_like(self.w[-1]))
+            self.gw.append(torch.zeros_like(self.w[-1]))
+            self.wf.append(w.reshape(-1).to(torch.bfloat16).to(self.dev))
+            wt = torch.flip(w.reshape(cout, 27, cin), dims=[1]).permute(2, 1, 0).contiguous()  # [ci][26 - tap][co]
+            self.wt.append(wt.reshape(-1).to(torch.bfloat16).to(self.dev) if cin == 32 else None)
+            self.b.append(torch.zeros(cout, dtype=torch.float32, device=self.dev))
+            self.bm.append(torch.zeros_like(self.b[-1]))
+            self.bv.append(torch.zeros_like(self.b[-1]))
+            self.gb.append(torch.zeros_like(self.b[-1]))
+        self._bufs = {}
+
+    # -- buffers -------------------------------------------------------------
+    @staticmethod
+    def vol(nx, ny, nzf, nsamples):
+        return el.el_nn_vol(nx, ny, nzf, nsamples)
+
+    def _buffers(self, vol):
+        import torch
+        key = (vol.nx, vol.ny, vol.nzf, vol.nsamples)
+        if key not in self._bufs:
+            halo = vol.nsamples * (vol.nzf + 2) * vol.ny * vol.nx
+            n_all = vol.nsamples * vol.nzf * vol.ny * vol.nx
+            bf = lambda c: torch.zeros(halo * c, dtype=torch.bfloat16, device=self.dev)
+            work = max(int(self.lib.el_nn_work_bytes(C.byref(vol), cin, cout)) for cin, cout, _, _ in LAYERS)
+            self._bufs[key] = {"a": [None, bf(32), bf(32), bf(32)], "res": torch.zeros(3 * n_all, device=self.dev),
+                               "g": [bf(32), bf(32), bf(32), bf(16)],
+                               "work": torch.zeros(work, dtype=torch.uint8, device=self.dev),
+                               "part": torch.zeros(1024, dtype=torch.float64, device=self.dev)}
+        return self._bufs[key]
+
+    @staticmethod
+    def input_buffer(vol):
+        import torch
+        halo = vol.nsamples * (vol.nzf + 2) * vol.ny * vol.nx
+        return torch.zeros(halo * 8, dtype=torch.bfloat16, device="cuda")
+
+    # -- network ---------------------------------------------------------------
+    def forward(self, vol, act0):
+        """Residual (FP32 [3][n_all]) for the inputs act0 of vol."""
+        bufs = self._buffers(vol)
+        bufs["a"][0] = act0
+        x = act0
+        st = _stream()
+        for li, (cin, cout, cout_real, relu) in enumerate(LAYERS):
+            y = bufs["res"] if cout_real == 3 else bufs["a"][li + 1]
+            el._check(self.lib.el_nn_conv_forward(C.byref(vol), cin, cout_real if cout_real == 3 else cout, _vp(x),
+                                                  _vp(self.wf[li]), _vp(self.b[li]), int(relu), _vp(y), st),
+                      "el_nn_conv_forward")
+            x = y
+        return bufs["res"]
+
+    def backward(self, vol, target):
+        """MSE against target (FP32 [3][n_all]); fills the gradients and
+        returns the loss."""
+        bufs = self._buffers(vol)
+        st = _stream()
+        npart = int(bufs["part"].numel())
+        el._check(self.lib.el_nn_mse(C.byref(vol), _vp(bufs["res"]), _vp(target), _vp(bufs["g"][3]),
+                                     _vp(bufs["part"]), npart, st), "el_nn_mse")
+        work = bufs["work"]
+        g = bufs["g"][3]
+        for li in range(len(LAYERS) - 1, -1, -1):
+            cin, cout, _, _ = LAYERS[li]
+            x = bufs["a"][li]
+            el._check(self.lib.el_nn_conv_backward_weight(C.byref(vol), cin, cout, _vp(x), _vp(g), _vp(work),
+                                                          work.numel(), _vp(self.gw[li]), _vp(self.gb[li]), st),
+                      "el_nn_conv_backward_weight")
+            if li > 0:
+                dx = bufs["g"][li - 1]
+                el._check(self.lib.el_nn_conv_backward_data(C.byref(vol), cin, cout, _vp(g), _vp(self.wt[li]),
+                                                            _vp(bufs["a"][li]), _vp(dx), st),
+                          "el_nn_conv_backward_data")
+                g = dx
+        return float(bufs["part"].double().sum().item())
+
+    def adam(self, lr=None, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_count += 1
+        lr = self.lr if lr is None else lr
+        st = _stream()
+        for li, (cin, cout, _, _) in enumerate(LAYERS):
+            wt = _vp(self.wt[li]) if self.wt[li] is not None else None
+            el._check(self.lib.el_nn_adam(_vp(self.w[li]), _vp(self.m[li]), _vp(self.v[li]), _vp(self.gw[li]),
+                                          self.w[li].numel(), lr, beta1, beta2, eps, self.step_count,
+                                          _vp(self.wf[li]), wt, cout, cin, st), "el_nn_adam")
+            el._check(self.lib.el_nn_adam(_vp(self.b[li]), _vp(self.bm[li]), _vp(self.bv[li]), _vp(self.gb[li]),
+                                          self.b[li].numel(), lr, beta1, beta2, eps, self.step_count, None, None,
+                                          0, 0, st), "el_nn_adam")
+
+    # -- lattices --------------------------------------------------------------
+    def make_input(self, lats, act0=None):
+        return make_input(lats, act0)
+
+    def predict_velocity(self, lat):
+        """u the network predicts for one lattice (device tensor, lattice dtype)."""
+        import torch
+        vol, act0 = make_input([lat])
+        res = self.forward(vol, act0)
+        u = torch.empty_like(lat.u)
+        el._check(self.lib.el_nn_velocity(C.byref(lat.params), _vp(res), 0, 1, V0, _vp(u), _stream()),
+                  "el_nn_velocity")
+        return u
+
+    def warm_start(self, lat):
+        """q = equilibrium at the predicted velocity (then u is recomputed)."""
+        u = self.predict_velocity(lat)
+        lat.init_flow(u)
+        return u
+
+    # -- persistence -------------------------------------------------------------
+    def state_dict(self):
+        return {"w": [w.cpu() for w in self.w], "b": [b.cpu() for b in self.b], "step": self.step_count}
+
+
+def make_input(lats, act0=None):
+    """Network input (el_nn_input) for a list of lattices of one shape."""
+    lib = el.load()
+    p0 = lats[0].prob
+    vol = el.el_nn_vol(p0.nx, p0.ny, p0.nzf, len(lats))
+    act0 = Surrogate.input_buffer(vol) if act0 is None else act0
+    for s, lat in enumerate(lats):
+        el._check(lib.el_nn_input(C.byref(lat.params), _vp(lat.n), _vp(act0), s, len(lats), V0, _stream()),
+                  "el_nn_input")
+    return vol, act0
+
+
+def poiseuille_velocity(lat):
+    """u_P x-hat of the lattice (the surrogate's analytic input) as a device tensor."""
+    import torch
+    p = lat.prob
+    nu = (p.tau - 0.5) / 3.0
+    z = torch.arange(1, p.nz - 1, dtype=torch.float64)
+    up = p.g[0] / (2 * nu) * (z - 0.5) * (p.nz - 1.5 - z)
+    u = torch.zeros(p.shape(3), dtype=torch.float64)
+    u[0] = up[:, None, None]
+    return u.to(device=lat.u.device, dtype=lat.u.dtype)
+
+
+# ---------------------------------------------------------------------------
+# Training pairs: frozen director, flow relaxed by the batched solver.
+
+def sample_problem(rng_u, nx=64, ny=64, nz=32):
+    """One training channel: Leslie set B, K = 5e-3, pitch 32, 1-4 tubes,
+    g_x log-uniform in [1e-7, 1e-5]; rng_u: 4 uniforms + a placement seed."""
+    gx = 10.0 ** (-7.0 + 2.0 * rng_u[0])
+    ntubes = 1 + int(rng_u[1] * 4)
+    prob = inputs.channel(nx, ny, nz, inputs.set_b(), g=(gx, 0.0, 0.0), K=5e-3, q0=2 * math.pi / 32, fd_ratio=10)
+    centres = inputs.place_tubes(nx, ny, ntubes, 16.0, seed=int(rng_u[2] * 2 ** 31))
+    return prob, inputs.director_tubes(prob, centres, 16.0)
+
+
+def relax(lats, steps, capture=True):
+    """Advance frozen-director lattices with the batched runner; returns the
+    largest relative change of u over the last 100 steps."""
+    import torch
+    b = el.Batch(lats)
+    if capture:
+        b.capture()
+    b.step(steps - 100)
+    b.moments()
+    torch.cuda.synchronize()
+    u_prev = [lat.u.clone() for lat in lats]
+    b.step(100)
+    b.moments()
+    b.sync()
+    torch.cuda.synchronize()
+    change = max(float((lat.u - up).norm() / lat.u.norm()) for lat, up in zip(lats, u_prev))
+    b.close()
+    return change
+
+
+def generate_pairs(nsamples, seed=5, group=250, steps=4000, nx=64, ny=64, nz=32, log=print):
+    """Inputs (BF16 network input, all samples) and targets (FP32, one
+    [3][group*N] block per group) from solver runs."""
+    import torch
+    u01 = inputs.uniform01(seed, 21, 4 * nsamples)
+    ngroups = (nsamples + group - 1) // group
+    nzf = nz - 2
+    vol_all = el.el_nn_vol(nx, ny, nzf, nsamples)
+    act_all = Surrogate.input_buffer(vol_all)
+    targets, changes = [], []
+    per = (nzf + 2) * ny * nx * 8
+    N = nx * ny * nzf
+    for gi in range(ngroups):
+        s0, s1 = gi * group, min(nsamples, (gi + 1) * group)
+        lats = []
+        for s in range(s0, s1):
+            prob, n0 = sample_problem(u01[4 * s:4 * s + 4], nx, ny, nz)
+            lat = el.Lattice(prob, "f32_shifted", freeze_director=True)
+            lat.init_lattice(n0)
+            lats.append(lat)
+        t0 = time.perf_counter()
+        changes.append(relax(lats, steps))
+        vol_g, act_g = make_input(lats)
+        act_all[s0 * per:s1 * per].copy_(act_g)
+        tgt = torch.empty(3, (s1 - s0) * N, dtype=torch.float32, device="cuda")
+        for k, lat in enumerate(lats):
+            up = poiseuille_velocity(lat)
+            r = ((lat.u - up) / V0).reshape(3, N)
+            tgt[:, k * N:(k + 1) * N] = r
+        targets.append(tgt)
+        log(f"pairs {s0}..{s1 - 1}: relaxed {steps} steps in {time.perf_counter() - t0:.1f} s, "
+            f"last-100-step change {changes[-1]:.2e}")
+        del lats
+        torch.cuda.empty_cache()
+    return {"vol": (nx, ny, nzf), "nsamples": nsamples, "group": group, "act": act_all, "targets": targets,
+            "max_change": max(changes)}
+
+
+def train(net, data, epochs, batch=8, log=print, seed=0):
+    """Adam on minibatches of `batch` consecutive samples (batch divides the
+    generation group); minibatch order reshuffled every epoch."""
+    import torch
+    nx, ny, nzf = data["vol"]
+    n = data["nsamples"]
+    group = data["group"]
+    assert group % batch == 0
+    N = nx * ny * nzf
+    per = (nzf + 2) * ny * nx * 8
+    vol = el.el_nn_vol(nx, ny, nzf, batch)
+    nb = n // batch
+    order = np.arange(nb)
+    rs = np.random.default_rng(seed)
+    history = []
+    tgt_buf = torch.empty(3, batch * N, dtype=torch.float32, device="cuda")
+    for ep in range(epochs):
+        rs.shuffle(order)
+        tot = 0.0
+        t0 = time.perf_counter()
+        for k in order:
+            s0 = k * batch
+            act = data["act"][s0 * per:(s0 + batch) * per]
+            g, off = divmod(s0, group)
+            tgt_buf.copy_(data["targets"][g][:, off * N:(off + batch) * N])
+            net.forward(vol, act)
+            tot += net.backward(vol, tgt_buf)
+            net.adam()
+        torch.cuda.synchronize()
+        history.append(tot / nb)
+        log(f"epoch {ep}: loss {history[-1]:.4e} ({time.perf_counter() - t0:.1f} s)")
+    return history
+
+
+def steps_to_error(lat, u_ref, tol, check_every=100, max_steps=40000):
+    """LBM steps (frozen director) until rel-L2(u, u_ref) <= tol; also the wall
+    time of those steps."""
+    import torch
+    ref = torch.as_tensor(u_ref, dtype=torch.float64, device=lat.u.device)
+    err = lat.error_norms(lat.u, ref)["rel_l2"]
+    steps = 0
+    t0 = time.perf_counter()
+    while err > tol and steps < max_steps:
+        lat.run(check_every)
+        steps += check_every
+        err = lat.error_norms(lat.u, ref)["rel_l2"]
+    torch.cuda.synchronize()
+    return steps, time.perf_counter() - t0, err

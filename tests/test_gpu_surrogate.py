@@ -1,0 +1,236 @@
+"""The surrogate's BF16-MFMA kernels (through the el_nn_* C ABI) against the
+FP64 convolution reference, on a ragged volume (tail of the 64-voxel wave
+tiles, two samples): each layer type forward, backward-data,
+backward-weight, the loss gradient and Adam; then the whole network's
+weight gradients; then training and the warm start on solver data."""
+import ctypes as C
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import conv_oracle as co
+from paper_2503_06610_amd import el, inputs
+
+pytestmark = pytest.mark.gpu
+RNG = np.random.default_rng(11)
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _bf(a):
+    import torch
+    return torch.as_tensor(np.asarray(a, dtype=np.float64)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _to_act(x, cstore, zpad):
+    """[S][C][Z][Y][X] -> BF16 halo'd channels-last [S][Z+2][Y][X][cstore]."""
+    import torch
+    s, c, z, y, xx = x.shape
+    a = np.zeros((s, z + 2, y, xx, cstore))
+    a[:, 1:-1, :, :, :c] = np.transpose(x, (0, 2, 3, 4, 1))
+    a[:, 0, :, :, :c] = zpad
+    a[:, -1, :, :, :c] = zpad
+    return torch.as_tensor(a).to(torch.bfloat16).cuda().reshape(-1)
+
+
+def _from_act(t, s, cstore, z, y, x):
+    a = t.to(dtype=__import__("torch").float64).cpu().numpy().reshape(s, z + 2, y, x, cstore)
+    return np.transpose(a[:, 1:-1], (0, 4, 1, 2, 3))
+
+
+def _wpad(w, cout_pad, cin_pad):
+    """real [cout][27][cin] -> padded forward copy and backward-data copy (BF16)."""
+    import torch
+    cout, _, cin = w.shape
+    wp = np.zeros((cout_pad, 27, cin_pad))
+    wp[:cout, :, :cin] = w
+    wt = np.transpose(wp[:, ::-1, :], (2, 1, 0))  # [ci][26 - tap][co]
+    to = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to(torch.bfloat16).cuda().reshape(-1)
+    return to(wp), to(wt)
+
+
+def _vp(t):
+    return C.c_void_p(t.data_ptr())
+
+
+S, Z, Y, X = 2, 5, 7, 10  # 700 voxels: not a multiple of 64
+VOL = el.el_nn_vol(X, Y, Z, S)
+
+
+def _lib():
+    return el.load()
+
+
+@pytest.mark.parametrize("cin_real,cin,cout_real,cout,relu", [(4, 8, 32, 32, True), (32, 32, 32, 32, True),
+                                                              (32, 32, 32, 32, False), (32, 32, 3, 16, False)])
+def test_conv_forward_matches_reference(cin_real, cin, cout_real, cout, relu):
+    import torch
+    x = _bf(RNG.normal(size=(S, cin_real, Z, Y, X)))
+    zpad = _bf(RNG.normal(size=cin_real))
+    w = _bf(RNG.normal(scale=0.2, size=(cout_real, 27, cin_real)))
+    b = RNG.normal(scale=0.1, size=cout).astype(np.float32)
+    wf, _ = _wpad(w, cout, cin)
+    xa = _to_act(x, cin, zpad)
+    bt = torch.as_tensor(b).cuda()
+    ref = co.conv_forward(x, w, b[:cout_real].astype(np.float64), zpad, relu)
+    if cout_real == 3:
+        y = torch.zeros(3 * S * Z * Y * X, dtype=torch.float32, device="cuda")
+        assert _lib().el_nn_conv_forward(C.byref(VOL), cin, 3, _vp(xa), _vp(wf), _vp(bt), 0, _vp(y), None) == 0
+        got = y.cpu().numpy().reshape(3, S, Z, Y, X).transpose(1, 0, 2, 3, 4)
+        assert np.abs(got - ref).max() < 1e-5 * np.abs(ref).max()
+    else:
+        y = torch.zeros(S * (Z + 2) * Y * X * cout, dtype=torch.bfloat16, device="cuda")
+        assert _lib().el_nn_conv_forward(C.byref(VOL), cin, cout, _vp(xa), _vp(wf), _vp(bt), int(relu), _vp(y),
+                                         None) == 0
+        got = _from_act(y, S, cout, Z, Y, X)[:, :cout_real]
+        # BF16 rounding of the stored output: half an ulp of 8 significant bits
+        assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
+        # halo planes untouched
+        raw = y.to(torch.float32).cpu().numpy().reshape(S, Z + 2, Y, X, cout)
+        assert np.all(raw[:, 0] == 0) and np.all(raw[:, -1] == 0)
+
+
+@pytest.mark.parametrize("cout_real,cout", [(32, 32), (3, 16)])
+def test_conv_backward_data_matches_reference(cout_real, cout):
+    import torch
+    cin = 32
+    w = _bf(RNG.normal(scale=0.2, size=(cout_real, 27, cin)))
+    dy = _bf(RNG.normal(size=(S, cout_real, Z, Y, X)))
+    mask = _bf(np.maximum(RNG.normal(size=(S, cin, Z, Y, X)), 0.0))
+    _, wt = _wpad(w, cout, cin)
+    dya = _to_act(dy, cout, np.zeros(cout_real))
+    ma = _to_act(mask, cin, np.zeros(cin))
+    dx = torch.zeros(S * (Z + 2) * Y * X * cin, dtype=torch.bfloat16, device="cuda")
+    assert _lib().el_nn_conv_backward_data(C.byref(VOL), cin, cout, _vp(dya), _vp(wt), _vp(ma), _vp(dx), None) == 0
+    got = _from_act(dx, S, cin, Z, Y, X)
+    ref = co.conv_backward_data(dy, w) * (mask > 0)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("cin_real,cin,cout_real,cout", [(4, 8, 32, 32), (32, 32, 32, 32), (32, 32, 3, 16)])
+def test_conv_backward_weight_matches_reference(cin_real, cin, cout_real, cout):
+    import torch
+    x = _bf(RNG.normal(size=(S, cin_real, Z, Y, X)))
+    zpad = _bf(RNG.normal(size=cin_real))
+    dy = _bf(RNG.normal(size=(S, cout_real, Z, Y, X)))
+    xa = _to_act(x, cin, zpad)
+    dya = _to_act(dy, cout, np.zeros(cout_real))
+    nbytes = int(_lib().el_nn_work_bytes(C.byref(VOL), cin, cout))
+    work = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    dw = torch.zeros(cout * 27 * cin, dtype=torch.float32, device="cuda")
+    db = torch.zeros(cout, dtype=torch.float32, device="cuda")
+    assert _lib().el_nn_conv_backward_weight(C.byref(VOL), cin, cout, _vp(xa), _vp(dya), _vp(work), nbytes,
+                                             _vp(dw), _vp(db), None) == 0
+    got = dw.cpu().numpy().reshape(cout, 27, cin)
+    rdw, rdb = co.conv_backward_weight(x, dy, zpad)
+    assert np.abs(got[:cout_real, :, :cin_real] - rdw).max() < 1e-5 * np.abs(rdw).max()
+    assert np.abs(got[cout_real:]).max() == 0 and np.abs(got[:, :, cin_real:]).max() == 0
+    assert np.abs(db.cpu().numpy()[:cout_real] - rdb).max() < 1e-5 * np.abs(rdb).max()
+
+
+def test_mse_and_adam_match_reference():
+    import torch
+    n_all = S * Z * Y * X
+    pred = torch.as_tensor(RNG.normal(size=3 * n_all).astype(np.float32)).cuda()
+    tgt = torch.as_tensor(RNG.normal(size=3 * n_all).astype(np.float32)).cuda()
+    dy = torch.zeros(S * (Z + 2) * Y * X * 16, dtype=torch.bfloat16, device="cuda")
+    part = torch.zeros(64, dtype=torch.float64, device="cuda")
+    assert _lib().el_nn_mse(C.byref(VOL), _vp(pred), _vp(tgt), _vp(dy), _vp(part), 64, None) == 0
+    p, t = pred.cpu().double().numpy(), tgt.cpu().double().numpy()
+    assert abs(part.sum().item() - ((p - t) ** 2).mean()) < 1e-12
+    g = _from_act(dy, S, 16, Z, Y, X)
+    want = (2 * (p - t) / (3 * n_all)).reshape(3, S, Z, Y, X).transpose(1, 0, 2, 3, 4)
+    assert np.all(np.abs(g[:, :3] - want) <= 2.0 ** -8 * np.abs(want))
+    assert np.all(g[:, 3:] == 0)
+    # Adam, two steps
+    n = 32 * 27 * 32
+    w0 = RNG.normal(size=n).astype(np.float32)
+    grads = [RNG.normal(size=n).astype(np.float32) for _ in range(2)]
+    w, m, v = (torch.as_tensor(w0.copy()).cuda(), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"))
+    wf = torch.zeros(n, dtype=torch.bfloat16, device="cuda")
+    wt = torch.zeros(n, dtype=torch.bfloat16, device="cuda")
+    rw, rm, rv = w0.astype(np.float64), np.zeros(n), np.zeros(n)
+    for k, gr in enumerate(grads, start=1):
+        gt = torch.as_tensor(gr).cuda()
+        assert _lib().el_nn_adam(_vp(w), _vp(m), _vp(v), _vp(gt), n, 1e-2, 0.9, 0.999, 1e-8, k, _vp(wf), _vp(wt),
+                                 32, 32, None) == 0
+        rm = 0.9 * rm + 0.1 * gr
+        rv = 0.999 * rv + 0.001 * gr.astype(np.float64) ** 2
+        rw = rw - 1e-2 * (rm / (1 - 0.9 ** k)) / (np.sqrt(rv / (1 - 0.999 ** k)) + 1e-8)
+    assert np.abs(w.cpu().numpy() - rw).max() < 1e-5
+    wfn = wf.to(torch.float32).cpu().numpy()
+    assert np.abs(wfn - w.cpu().numpy()).max() <= 2.0 ** -8 * np.abs(w.cpu().numpy()).max()
+    wtn = wt.to(torch.float32).cpu().numpy().reshape(32, 27, 32)
+    assert np.array_equal(wtn, np.transpose(wfn.reshape(32, 27, 32)[:, ::-1, :], (2, 1, 0)))
+
+
+def test_network_weight_gradients_match_reference():
+    """Forward + backward of the 4-layer network through the C ABI against the
+    FP64 reference with the same BF16 weights and input (the GPU keeps BF16
+    activations and gradients, so agreement is to BF16 accuracy)."""
+    import torch
+    from paper_2503_06610_amd import surrogate as sg
+    net = sg.Surrogate(seed=3)
+    x = _bf(RNG.normal(size=(S, 4, Z, Y, X)))
+    zpad = np.array([0.0, 0.0, 1.0, 0.0])
+    tgt = RNG.normal(scale=0.5, size=(S, 3, Z, Y, X))
+    act0 = _to_act(x, 8, zpad)
+    res = net.forward(VOL, act0)
+    t = torch.as_tensor(tgt.transpose(1, 0, 2, 3, 4).reshape(3, -1).astype(np.float32)).cuda()
+    loss = net.backward(VOL, t)
+    layers = []
+    for li, (cin, cout, cout_real, relu) in enumerate(sg.LAYERS):
+        wf = net.wf[li].to(torch.float64).cpu().numpy().reshape(cout, 27, cin)[:cout_real, :, :sg.REAL_CIN[li]]
+        layers.append((wf, net.b[li].cpu().double().numpy()[:cout_real], relu))
+    rloss, rgrads = co.network_loss_and_grads(x, layers, zpad, tgt)
+    _say(f"loss gpu {loss:.6e} ref {rloss:.6e}")
+    assert abs(loss - rloss) < 2e-2 * rloss
+    for li, (cin, cout, cout_real, relu) in enumerate(sg.LAYERS):
+        g = net.gw[li].cpu().double().numpy().reshape(cout, 27, cin)[:cout_real, :, :sg.REAL_CIN[li]]
+        r = rgrads[li][0]
+        rel = np.linalg.norm(g - r) / np.linalg.norm(r)
+        cos = float((g * r).sum() / np.linalg.norm(g) / np.linalg.norm(r))
+        _say(f"layer {li}: rel-L2 {rel:.3e} cos {cos:.6f}")
+        assert rel < 3e-2 and cos > 0.999
+        gb = net.gb[li].cpu().double().numpy()[:cout_real]
+        assert np.linalg.norm(gb - rgrads[li][1]) <= 3e-2 * np.linalg.norm(rgrads[li][1])
+
+
+def test_training_and_warm_start_on_solver_data():
+    """A small surrogate trained on solver pairs lowers its loss, and starting
+    a held-out channel from its prediction reaches the converged flow in fewer
+    steps than a cold start and than the analytic Poiseuille start."""
+    import torch
+    from paper_2503_06610_amd import surrogate as sg
+    nx, ny, nz = 32, 32, 16
+    data = sg.generate_pairs(32, seed=9, group=32, steps=1500, nx=nx, ny=ny, nz=nz, log=_say)
+    assert data["max_change"] < 1e-5
+    net = sg.Surrogate(seed=1, lr=2e-3)
+    hist = sg.train(net, data, epochs=40, batch=4, log=lambda m: None)
+    _say(f"loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    assert hist[-1] < 0.3 * hist[0]
+    u01 = inputs.uniform01(99, 21, 4)
+    prob, n0 = sg.sample_problem(u01, nx, ny, nz)
+    ref = el.Lattice(prob, "f32_shifted", freeze_director=True)
+    ref.init_lattice(n0)
+    ref.run(3000)
+    u_ref = ref.get("u")
+    results = {}
+    for mode in ("cold", "poiseuille", "net"):
+        lat = el.Lattice(prob, "f32_shifted", freeze_director=True)
+        lat.init_lattice(n0)
+        if mode == "poiseuille":
+            lat.init_flow(sg.poiseuille_velocity(lat))
+        elif mode == "net":
+            net.warm_start(lat)
+        e0 = lat.error_norms(lat.u, u_ref)["rel_l2"]
+        steps, _, err = sg.steps_to_error(lat, u_ref, 1e-4, check_every=10)
+        results[mode] = (e0, steps)
+    _say(f"warm start: {results}")
+    assert results["net"][0] < results["poiseuille"][0] < results["cold"][0]
+    assert results["net"][1] < results["cold"][1]
+    assert results["net"][1] <= results["poiseuille"][1]
