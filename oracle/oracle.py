@@ -50,33 +50,38 @@ def _load():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        lib = C.CDLL(_LIB)
-        D = C.POINTER(C.c_double)
-        lib.or_create.restype = C.c_void_p
-        lib.or_create.argtypes = [C.POINTER(_Params)]
-        lib.or_destroy.argtypes = [C.c_void_p]
-        lib.or_set_threads.argtypes = [C.c_int32]
-        lib.or_init.argtypes = [C.c_void_p, D]
-        lib.or_init_flow.argtypes = [C.c_void_p, D]
-        lib.or_step_lbm.argtypes = [C.c_void_p, C.c_int32]
-        lib.or_step_director.argtypes = [C.c_void_p]
-        lib.or_run.argtypes = [C.c_void_p, C.c_int64]
-        lib.or_step_count.restype = C.c_int64
-        lib.or_step_count.argtypes = [C.c_void_p]
-        lib.or_get.argtypes = [C.c_void_p, C.c_int32, D]
-        lib.or_set.argtypes = [C.c_void_p, C.c_int32, D]
-        lib.or_moments.argtypes = [C.c_void_p]
-        lib.or_force.argtypes = [C.c_void_p]
-        lib.or_molecular_field.argtypes = [C.c_void_p, D]
-        lib.or_director_rhs.argtypes = [C.c_void_p, D, D]
-        lib.or_stress.argtypes = [C.c_void_p, C.c_int32, D]
-        lib.or_force_masked.argtypes = [C.c_void_p, C.c_int32, D]
-        lib.or_observables.argtypes = [C.c_void_p, C.POINTER(_Obs)]
-        lib.or_lattice.argtypes = [D, D, C.POINTER(C.c_int32)]
-        lib.or_equilibrium.argtypes = [C.c_double, C.c_double, D, C.c_int32, D]
-        lib.or_guo_source.argtypes = [D, D, D]
-        _lib = lib
+        _lib = load_library(_LIB)
     return _lib
+
+
+def load_library(path: str):
+    """Load an oracle shared library at `path` and declare its functions."""
+    lib = C.CDLL(path)
+    D = C.POINTER(C.c_double)
+    lib.or_create.restype = C.c_void_p
+    lib.or_create.argtypes = [C.POINTER(_Params)]
+    lib.or_destroy.argtypes = [C.c_void_p]
+    lib.or_set_threads.argtypes = [C.c_int32]
+    lib.or_init.argtypes = [C.c_void_p, D]
+    lib.or_init_flow.argtypes = [C.c_void_p, D]
+    lib.or_step_lbm.argtypes = [C.c_void_p, C.c_int32]
+    lib.or_step_director.argtypes = [C.c_void_p]
+    lib.or_run.argtypes = [C.c_void_p, C.c_int64]
+    lib.or_step_count.restype = C.c_int64
+    lib.or_step_count.argtypes = [C.c_void_p]
+    lib.or_get.argtypes = [C.c_void_p, C.c_int32, D]
+    lib.or_set.argtypes = [C.c_void_p, C.c_int32, D]
+    lib.or_moments.argtypes = [C.c_void_p]
+    lib.or_force.argtypes = [C.c_void_p]
+    lib.or_molecular_field.argtypes = [C.c_void_p, D]
+    lib.or_director_rhs.argtypes = [C.c_void_p, D, D]
+    lib.or_stress.argtypes = [C.c_void_p, C.c_int32, D]
+    lib.or_force_masked.argtypes = [C.c_void_p, C.c_int32, D]
+    lib.or_observables.argtypes = [C.c_void_p, C.POINTER(_Obs)]
+    lib.or_lattice.argtypes = [D, D, C.POINTER(C.c_int32)]
+    lib.or_equilibrium.argtypes = [C.c_double, C.c_double, D, C.c_int32, D]
+    lib.or_guo_source.argtypes = [D, D, D]
+    return lib
 
 
 def _dp(a: np.ndarray):

@@ -109,17 +109,19 @@ template <typename T>
 int launch_force(const el_params* p, el_state* s, hipStream_t st)
 {
     const el::FdArgs<T> a = fd_args<T>(p);
-    const int grid = grid_for(a.g.N);
     if (!coupling(p)) {
         hipLaunchKernelGGL((el::k_fill<T>), dim3(grid_for(3 * a.g.N)), dim3(BLOCK), 0, st, static_cast<T*>(s->F),
                            T(0), 3 * a.g.N);
         return check_launch("clear F");
     }
     T* sig = sigma_of<T>(s);
-    hipLaunchKernelGGL((el::k_fd_stress<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
-                       static_cast<const T*>(s->u), sig, a);
-    hipLaunchKernelGGL((el::k_fd_divergence<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(sig),
-                       static_cast<T*>(s->F), a);
+    const dim3 zg = zmarch_grid(a.g);
+    hipLaunchKernelGGL((el::k_fd_zmarch<T, 2>), zg, dim3(256), 0, st, static_cast<const T*>(s->n),
+                       static_cast<const T*>(s->u), sig, static_cast<T*>(nullptr), static_cast<const T*>(nullptr),
+                       static_cast<const T*>(nullptr), a, ZCHUNK);
+    hipLaunchKernelGGL((el::k_fd_zmarch<T, 3>), zg, dim3(256), 0, st, static_cast<const T*>(sig),
+                       static_cast<const T*>(nullptr), static_cast<T*>(s->F), static_cast<T*>(nullptr),
+                       static_cast<const T*>(nullptr), static_cast<const T*>(nullptr), a, ZCHUNK);
     return check_launch("force kernels");
 }
 
@@ -127,13 +129,14 @@ template <typename T>
 int launch_director(const el_params* p, el_state* s, hipStream_t st)
 {
     const el::FdArgs<T> a = fd_args<T>(p);
-    const int grid = grid_for(a.g.N);
     if (p->flags & EL_FREEZE_DIRECTOR) return launch_force<T>(p, s, st);
-    hipLaunchKernelGGL((el::k_fd_predictor<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
-                       static_cast<const T*>(s->u), static_cast<T*>(s->n_pred), static_cast<T*>(s->dndt), a);
-    hipLaunchKernelGGL((el::k_fd_corrector<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<T*>(s->n),
-                       static_cast<const T*>(s->n_pred), static_cast<const T*>(s->u),
-                       static_cast<const T*>(s->dndt), a);
+    const dim3 zg = zmarch_grid(a.g);
+    hipLaunchKernelGGL((el::k_fd_zmarch<T, 0>), zg, dim3(256), 0, st, static_cast<const T*>(s->n),
+                       static_cast<const T*>(s->u), static_cast<T*>(s->n_pred), static_cast<T*>(s->dndt),
+                       static_cast<const T*>(nullptr), static_cast<const T*>(nullptr), a, ZCHUNK);
+    hipLaunchKernelGGL((el::k_fd_zmarch<T, 1>), zg, dim3(256), 0, st, static_cast<const T*>(s->n_pred),
+                       static_cast<const T*>(s->u), static_cast<T*>(s->n), static_cast<T*>(nullptr),
+                       static_cast<const T*>(s->n), static_cast<const T*>(s->dndt), a, ZCHUNK);
     int rc = check_launch("director kernels");
     if (rc != EL_OK) return rc;
     return launch_force<T>(p, s, st);

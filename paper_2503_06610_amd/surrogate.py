@@ -310,3 +310,117 @@ def steps_to_error(lat, u_ref, tol, check_every=100, max_steps=40000):
         err = lat.error_norms(lat.u, ref)["rel_l2"]
     torch.cuda.synchronize()
     return steps, time.perf_counter() - t0, err
+
+
+# ---------------------------------------------------------------------------
+# The warm-start study: train on solver pairs, evaluate time-to-steady.
+
+FLOPS_PER_VOXEL = 2 * 27 * (4 * 32 + 32 * 32 + 32 * 32 + 32 * 3)  # 122,688 algorithmic flops
+
+
+def eval_problem(nx=512, ny=512, nz=64, ntubes=8, gx=5e-6, seed=55):
+    prob = inputs.channel(nx, ny, nz, inputs.set_b(), g=(gx, 0.0, 0.0), K=5e-3, q0=2 * math.pi / 32, fd_ratio=10)
+    centres = inputs.place_tubes(nx, ny, ntubes, 16.0, seed=seed)
+    return prob, inputs.director_tubes(prob, centres, 16.0)
+
+
+def time_forward(net, lat, reps=5):
+    """Average duration of one network forward pass on a lattice (HIP events on
+    the launch stream), and its algorithmic TFLOP/s."""
+    import torch
+    vol, act0 = make_input([lat])
+    net.forward(vol, act0)
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        net.forward(vol, act0)
+    b.record(st)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    n = lat.prob.fluid_nodes
+    return ms, FLOPS_PER_VOXEL * n / (ms * 1e-3) / 1e12
+
+
+def warm_start_study(net, prob, n0, tol=1e-4, ref_steps=15000, check_every=100, log=print):
+    import torch
+    t0 = time.perf_counter()
+    ref = el.Lattice(prob, "f32_shifted", freeze_director=True)
+    ref.init_lattice(n0)
+    ref.run(ref_steps)
+    u_ref = ref.get("u")
+    log(f"reference: {ref_steps} steps in {time.perf_counter() - t0:.1f} s")
+    del ref
+    torch.cuda.empty_cache()
+    out = {}
+    modes = [("cold", None), ("poiseuille", None), ("untrained_net", Surrogate(seed=1234)), ("trained_net", net)]
+    for mode, model in modes:
+        lat = el.Lattice(prob, "f32_shifted", freeze_director=True)
+        lat.init_lattice(n0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "poiseuille":
+            lat.init_flow(poiseuille_velocity(lat))
+        elif model is not None:
+            model.warm_start(lat)
+        torch.cuda.synchronize()
+        t_init = time.perf_counter() - t0
+        e0 = lat.error_norms(lat.u, torch.as_tensor(u_ref, device="cuda"))["rel_l2"]
+        steps, t_steps, err = steps_to_error(lat, u_ref, tol, check_every=check_every)
+        out[mode] = {"initial_rel_l2": e0, "steps_to_tol": steps, "final_rel_l2": err,
+                     "init_s": round(t_init, 4), "solve_s": round(t_steps, 3),
+                     "total_s": round(t_init + t_steps, 3)}
+        log(f"{mode}: e0 {e0:.3e}, {steps} steps to {tol:g} ({t_init + t_steps:.2f} s)")
+        del lat
+        torch.cuda.empty_cache()
+    return out
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import torch
+    ap = argparse.ArgumentParser(description="train the warm-start surrogate and measure time-to-steady")
+    ap.add_argument("--samples", type=int, default=2000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--relax-steps", type=int, default=4000)
+    ap.add_argument("--eval-size", type=int, nargs=3, default=[512, 512, 64])
+    ap.add_argument("--ref-steps", type=int, default=15000)
+    ap.add_argument("--out", default="")
+    args = ap.parse_args(argv)
+    log = lambda m: print(m, flush=True)
+    t0 = time.perf_counter()
+    data = generate_pairs(args.samples, steps=args.relax_steps, log=log)
+    t_gen = time.perf_counter() - t0
+    max_change = data["max_change"]
+    net = Surrogate(seed=0)
+    t0 = time.perf_counter()
+    hist = train(net, data, args.epochs, batch=args.batch, log=log)
+    t_train = time.perf_counter() - t0
+    del data
+    torch.cuda.empty_cache()
+    prob, n0 = eval_problem(*args.eval_size)
+    lat = el.Lattice(prob, "f32_shifted", freeze_director=True)
+    lat.init_lattice(n0)
+    ms, tflops = time_forward(net, lat)
+    log(f"forward on {prob.nx}x{prob.ny}x{prob.nz}: {ms:.2f} ms, {tflops:.1f} TFLOP/s algorithmic")
+    del lat
+    torch.cuda.empty_cache()
+    study = warm_start_study(net, prob, n0, ref_steps=args.ref_steps, log=log)
+    res = {"train": {"samples": args.samples, "epochs": args.epochs, "batch": args.batch,
+                     "generation_s": round(t_gen, 1), "max_last100_change": max_change,
+                     "train_s": round(t_train, 1), "loss_first": hist[0], "loss_last": hist[-1], "loss": hist},
+           "inference": {"size": list(args.eval_size), "forward_ms": round(ms, 3),
+                         "tflops_algorithmic": round(tflops, 2), "mfma_bf16_peak_tflops": 2500.0,
+                         "frac": round(tflops / 2500.0, 4)},
+           "warm_start": study}
+    print(json.dumps(res), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    import sys
+    main(sys.argv[1:])
