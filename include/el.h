@@ -126,6 +126,21 @@ typedef struct {
     int32_t reserved;
 } el_obs;
 
+/* Tube drift tracker (device memory, zero-filled by the caller before the
+ * first call): the observables of the last call, the centroid of the first
+ * call (origin), the periodically unwrapped centroid, the displacement
+ * unwrapped - origin, all in FP64, and the steps of the first and last call. */
+typedef struct {
+    el_obs obs;
+    double origin[2];
+    double unwrapped[2];
+    double displacement[2];
+    int64_t step0;
+    int64_t step;
+    int32_t ncalls;
+    int32_t reserved;
+} el_drift;
+
 /* Library version (EL_ABI_VERSION). */
 int el_version(void);
 
@@ -188,6 +203,15 @@ int el_run(const el_params* p, el_state* s, int64_t T, void* stream);
 /* FP64 observables of the current state into out (device memory, one el_obs).
  * Uses the first 128 KiB of s->scratch. */
 int el_observables(const el_params* p, const el_state* s, el_obs* out, void* stream);
+
+/* Tube drift (Sec. III follows skyrmion tubes carried by the flow): computes
+ * the observables of the current state into d->obs and advances the FP64
+ * unwrapped centroid by the periodic minimum-image change since the previous
+ * call (so displacements beyond one period accumulate correctly; the tube
+ * must move less than half a period between calls).  The mean drift
+ * velocity is d->displacement / (d->step - d->step0).  Uses the first
+ * 128 KiB of s->scratch. */
+int el_tube_drift(const el_params* p, const el_state* s, el_drift* d, void* stream);
 
 /* Error sums of a field a (device, ncomp*N T) against ref (device, ncomp*N
  * double) over fluid nodes, into out (device, 4 + 2*ncomp doubles):

@@ -170,7 +170,7 @@ int init_flow_impl(const el_params* p, el_state* s, const void* u0, hipStream_t 
 }
 
 template <typename T>
-int observables_impl(const el_params* p, const el_state* s, el_obs* out, hipStream_t st)
+int observables_impl(const el_params* p, const el_state* s, el_obs* out, el_drift* drift, hipStream_t st)
 {
     el::ObsArgs<T> a;
     a.g = geom_of(p);
@@ -186,7 +186,7 @@ int observables_impl(const el_params* p, const el_state* s, el_obs* out, hipStre
                        static_cast<const T*>(s->q[s->parity]), static_cast<const T*>(s->n),
                        static_cast<const T*>(s->u), static_cast<const T*>(s->F), partial, a);
     hipLaunchKernelGGL(el::k_obs_final, dim3(1), dim3(el::RED_THREADS), 0, st, static_cast<const double*>(partial),
-                       blocks, out, p->nx, p->ny);
+                       blocks, out, p->nx, p->ny, drift, (long long)s->step);
     return check_launch("observables kernels");
 }
 
@@ -349,8 +349,19 @@ int el_observables(const el_params* p, const el_state* s, el_obs* out, void* str
     if ((rc = state_checks(p, s)) != EL_OK) return rc;
     if (!out) return fail(EL_EINVAL, "out is NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (is_f64(p)) return observables_impl<double>(p, s, out, st);
-    return observables_impl<float>(p, s, out, st);
+    if (is_f64(p)) return observables_impl<double>(p, s, out, nullptr, st);
+    return observables_impl<float>(p, s, out, nullptr, st);
+}
+
+int el_tube_drift(const el_params* p, const el_state* s, el_drift* d, void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if ((rc = state_checks(p, s)) != EL_OK) return rc;
+    if (!d) return fail(EL_EINVAL, "drift tracker is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (is_f64(p)) return observables_impl<double>(p, s, nullptr, d, st);
+    return observables_impl<float>(p, s, nullptr, d, st);
 }
 
 int el_error_norms(const el_params* p, const void* a, const double* ref, int32_t ncomp, void* work, double* out,

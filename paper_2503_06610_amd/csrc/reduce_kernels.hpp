@@ -124,9 +124,11 @@ __global__ void __launch_bounds__(RED_THREADS) k_obs_partial(const T* __restrict
         for (int j = 0; j < OBS_NQ; ++j) partial[blockIdx.x * OBS_NQ + j] = v[j];
 }
 
-// Adds the block rows in order and fills an el_obs.
+// Adds the block rows in order and fills an el_obs; with a drift tracker,
+// also advances its unwrapped centroid (FP64).
 static __global__ void __launch_bounds__(RED_THREADS) k_obs_final(const double* __restrict__ partial, int nblocks,
-                                                          el_obs* __restrict__ out, int nx, int ny)
+                                                          el_obs* __restrict__ out, int nx, int ny,
+                                                          el_drift* __restrict__ drift, long long step)
 {
     __shared__ double lds[RED_THREADS / 64][OBS_NQ];
     double v[OBS_NQ];
@@ -163,7 +165,32 @@ static __global__ void __launch_bounds__(RED_THREADS) k_obs_final(const double* 
         o.tube_centroid[1] = v[7] > 0.0 ? cy : 0.0;
         o.nonfinite = v[14] > 0.0 ? 1 : 0;
         o.reserved = 0;
-        *out = o;
+        if (out) *out = o;
+        if (drift) {
+            drift->obs = o;
+            const double c[2] = {o.tube_centroid[0], o.tube_centroid[1]};
+            const double L[2] = {(double)nx, (double)ny};
+            if (drift->ncalls == 0) {
+                for (int a = 0; a < 2; ++a) {
+                    drift->origin[a] = c[a];
+                    drift->unwrapped[a] = c[a];
+                    drift->displacement[a] = 0.0;
+                }
+                drift->step0 = step;
+            } else {
+                for (int a = 0; a < 2; ++a) {
+                    // minimum-image change of the centroid since the last call
+                    double last = fmod(drift->unwrapped[a], L[a]);
+                    if (last < 0) last += L[a];
+                    double d = c[a] - last;
+                    d -= L[a] * floor(d / L[a] + 0.5);
+                    drift->unwrapped[a] += d;
+                    drift->displacement[a] = drift->unwrapped[a] - drift->origin[a];
+                }
+            }
+            drift->step = step;
+            drift->ncalls += 1;
+        }
     }
 }
 

@@ -26,7 +26,7 @@ PRECISIONS = {"f64": EL_F64, "f64_shifted": EL_F64_SHIFTED, "f32": EL_F32, "f32_
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTED = ("el_version", "el_strerror", "el_last_error", "el_buffer_bytes", "el_validate", "el_init_lattice",
             "el_init_flow", "el_step_lbm", "el_moments", "el_step_director", "el_force", "el_run",
-            "el_observables", "el_error_norms", "el_batch_create", "el_batch_step", "el_batch_capture",
+            "el_observables", "el_tube_drift", "el_error_norms", "el_batch_create", "el_batch_step", "el_batch_capture",
             "el_batch_moments", "el_batch_observables", "el_batch_sync", "el_batch_get_tuning", "el_batch_destroy",
             "el_nn_input", "el_nn_conv_forward", "el_nn_conv_backward_data", "el_nn_work_bytes",
             "el_nn_conv_backward_weight", "el_nn_mse", "el_nn_adam", "el_nn_velocity")
@@ -59,6 +59,12 @@ class el_obs(C.Structure):
 
 
 OBS_DOUBLES = C.sizeof(el_obs) // 8
+
+
+class el_drift(C.Structure):
+    _fields_ = [("obs", el_obs), ("origin", C.c_double * 2), ("unwrapped", C.c_double * 2),
+                ("displacement", C.c_double * 2), ("step0", C.c_int64), ("step", C.c_int64),
+                ("ncalls", C.c_int32), ("reserved", C.c_int32)]
 
 
 class el_batch_tuning(C.Structure):
@@ -96,6 +102,7 @@ def load(path: str = LIB_PATH):
         "el_run": (C.c_int, [P, S, C.c_int64, V]),
         "el_observables": (C.c_int, [P, S, V, V]),
         "el_error_norms": (C.c_int, [P, V, V, C.c_int32, V, V, V]),
+        "el_tube_drift": (C.c_int, [P, S, V, V]),
         "el_batch_create": (C.c_int, [P, S, C.c_int32, C.POINTER(el_batch_tuning), V, C.POINTER(C.c_void_p)]),
         "el_batch_step": (C.c_int, [V, C.c_int32, V]),
         "el_batch_capture": (C.c_int, [V, V]),
@@ -243,6 +250,17 @@ class Lattice:
                 "max_u": o.max_u, "max_unit_dev": o.max_unit_dev, "tube_weight": o.tube_weight,
                 "tube_centroid": np.array(o.tube_centroid[:]), "tube_cs": np.array(o.tube_cs[:]),
                 "nonfinite": int(o.nonfinite)}
+
+    def track_drift(self, stream=None) -> dict:
+        """Advance this lattice's FP64 tube-drift tracker (el_tube_drift)."""
+        import torch
+        if not hasattr(self, "drift_buf"):
+            self.drift_buf = torch.zeros((C.sizeof(el_drift) + 7) // 8, dtype=torch.float64, device=self.n.device)
+        _check(self.lib.el_tube_drift(C.byref(self.params), C.byref(self.state), C.c_void_p(self.drift_buf.data_ptr()),
+                                      _stream_ptr(stream)), "el_tube_drift")
+        d = el_drift.from_buffer_copy(self.drift_buf.cpu().numpy().tobytes()[:C.sizeof(el_drift)])
+        return {"centroid": np.array(d.obs.tube_centroid[:]), "unwrapped": np.array(d.unwrapped[:]),
+                "displacement": np.array(d.displacement[:]), "steps": int(d.step - d.step0), "ncalls": d.ncalls}
 
     def error_norms(self, a, ref, stream=None) -> dict:
         """Error sums of a device field `a` (this lattice's dtype) against an

@@ -40,8 +40,9 @@ def test_struct_sizes_match_header():
     #include <stddef.h>
     #include "el.h"
     int main(void) {
-      printf("%zu %zu %zu %zu %zu %zu\n", sizeof(el_params), sizeof(el_state), sizeof(el_obs),
-             offsetof(el_params, tau), offsetof(el_state, parity), offsetof(el_obs, nonfinite));
+      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(el_params), sizeof(el_state), sizeof(el_obs),
+             offsetof(el_params, tau), offsetof(el_state, parity), offsetof(el_obs, nonfinite),
+             sizeof(el_drift), offsetof(el_drift, step0), sizeof(el_batch_tuning));
       return 0; }
     '''
     import tempfile
@@ -52,7 +53,8 @@ def test_struct_sizes_match_header():
         subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), cpath, "-o", exe])
         vals = [int(v) for v in subprocess.check_output([exe], text=True).split()]
     assert vals == [C.sizeof(el.el_params), C.sizeof(el.el_state), C.sizeof(el.el_obs),
-                    el.el_params.tau.offset, el.el_state.parity.offset, el.el_obs.nonfinite.offset]
+                    el.el_params.tau.offset, el.el_state.parity.offset, el.el_obs.nonfinite.offset,
+                    C.sizeof(el.el_drift), el.el_drift.step0.offset, C.sizeof(el.el_batch_tuning)]
 
 
 def test_validate_accepts_workloads():

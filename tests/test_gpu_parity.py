@@ -243,3 +243,36 @@ def test_full_size_one_step(which):
         _say(f"  {errs}")
         for k, v in errs.items():
             assert v < tol[k], (which, precision, k, v)
+
+
+def test_tube_drift_unwraps_across_the_period():
+    """The FP64 drift tracker against centroids computed on the host from the
+    oracle's director, with the tube starting on the periodic boundary so
+    that its centroid wraps from x ~ nx to x ~ 0 while it is carried along."""
+    mat = inputs.set_b()
+    prob = inputs.channel(40, 20, 14, mat, g=(8e-5, 0.0, 0.0), K=3e-3, q0=2 * math.pi / 16, fd_ratio=5)
+    n0 = inputs.director_tubes(prob, [(39.9, 10.0)], 6.0)
+    lat = _gpu(prob, n0, "f64_shifted")
+    o = _oracle(prob, n0)
+    x = np.arange(prob.nx)[None, None, :]
+    ang = 2 * math.pi * x / prob.nx
+    host_unwrapped, last = None, None
+    for k in range(12):
+        d = lat.track_drift()
+        n = o.get("n")
+        w = np.maximum(0.0, -n[2])
+        cx = math.atan2((w * np.sin(ang)).sum(), (w * np.cos(ang)).sum()) * prob.nx / (2 * math.pi) % prob.nx
+        if host_unwrapped is None:
+            host_unwrapped = cx
+        else:
+            dlt = cx - last
+            dlt -= prob.nx * math.floor(dlt / prob.nx + 0.5)
+            host_unwrapped += dlt
+        last = cx
+        assert abs(d["centroid"][0] - cx) < 1e-8
+        assert abs(d["unwrapped"][0] - host_unwrapped) < 1e-8
+        lat.run(50)
+        o.run(50)
+    _say(f"tube displacement {d['displacement']} over {d['steps']} steps")
+    assert d["ncalls"] == 12 and d["steps"] == 550
+    assert abs(d["displacement"][0]) > 0.05
