@@ -85,15 +85,22 @@ int launch_lbm_steps(const el_params* p, el_state* s, int nsteps, hipStream_t st
 {
     const el::LbmArgs<T> a = lbm_args<T>(p);
     const int grid = grid_for(a.g.N);
+    // whole-row blocks with the x shifts through LDS when a row is a whole number of wavefronts
+    const bool rows = (a.g.nx % 64 == 0) && a.g.nx <= 1024;
+    const size_t shmem = rows ? 10 * (size_t)a.g.nx * sizeof(T) : 0;
     for (int k = 0; k < nsteps; ++k) {
         const T* qa = static_cast<const T*>(s->q[s->parity]);
         T* qb = static_cast<T*>(s->q[1 - s->parity]);
-        hipLaunchKernelGGL((el::k_lbm_push<T, SHIFT>), dim3(grid), dim3(BLOCK), 0, st, qa, qb,
-                           static_cast<const T*>(s->F), a);
+        if (rows)
+            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT>), dim3(a.g.ny * a.g.nzf), dim3(a.g.nx), shmem, st, qa, qb,
+                               static_cast<const T*>(s->F), a);
+        else
+            hipLaunchKernelGGL((el::k_lbm_push<T, SHIFT>), dim3(grid), dim3(BLOCK), 0, st, qa, qb,
+                               static_cast<const T*>(s->F), a);
         s->parity = 1 - s->parity;
         s->step += 1;
     }
-    return check_launch("k_lbm_push");
+    return check_launch("LBM step kernel");
 }
 
 template <typename T, bool SHIFT>

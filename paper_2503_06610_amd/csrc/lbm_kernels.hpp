@@ -42,22 +42,15 @@ __device__ inline void node_moments(const T (&q)[19], T& rho, T& drho, T& jx, T&
     jz = (q[5] - q[6]) + (q[11] - q[12]) + (q[14] - q[13]) + (q[15] - q[16]) + (q[18] - q[17]);
 }
 
-// One LBM step for fluid node k: read q at the own node from qa, collide,
-// push to the neighbours in qb.  A population whose destination is a wall
-// node returns to its own node in the opposite direction (wall midway between
-// fluid and solid node).  Shared by the single-channel and batched kernels so
-// both perform the same arithmetic.
+// Post-collision populations of fluid node k (Sec. II C): moments with
+// F = rho g + F^LC, BGK relaxation toward the (shifted) equilibrium and the
+// Guo source.  Shared by every LBM kernel, so all of them perform the same
+// arithmetic.
 template <typename T, bool SHIFT>
-__device__ __forceinline__ void lbm_node(const T* __restrict__ qa, T* __restrict__ qb, const T* __restrict__ Flc,
-                                         const LbmArgs<T>& a, int k)
+__device__ __forceinline__ void lbm_collide(const T* __restrict__ qa, const T* __restrict__ Flc, const LbmArgs<T>& a,
+                                            int k, T (&post)[19])
 {
-    const Geom& g = a.g;
-    const int x = k % g.nx;
-    const int t = k / g.nx;
-    const int y = t % g.ny;
-    const int z = t / g.ny;
-    const size_t N = (size_t)g.N;
-
+    const size_t N = (size_t)a.g.N;
     T q[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) q[i] = __builtin_nontemporal_load(qa + i * N + k);
@@ -76,8 +69,37 @@ __device__ __forceinline__ void lbm_node(const T* __restrict__ qa, T* __restrict
     const T uz = (jz + T(0.5) * Fz) * inv_rho;
     const T uu = ux * ux + uy * uy + uz * uz;
     const T uF = ux * Fx + uy * Fy + uz * Fz;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const T w = WGT<T>(i);
+        const T eu = T(EX(i)) * ux + T(EY(i)) * uy + T(EZ(i)) * uz;
+        const T eF = T(EX(i)) * Fx + T(EY(i)) * Fy + T(EZ(i)) * Fz;
+        T eq;
+        if (SHIFT)
+            eq = w * (rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu) + drho);
+        else
+            eq = w * rho * (T(1) + T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu);
+        const T S = w * (T(3) * (eF - uF) + T(9) * eu * eF);
+        post[i] = q[i] + a.omega * (eq - q[i]) + a.cS * S;
+    }
+}
 
-    // neighbour coordinates
+// One LBM step for fluid node k: collide, then push to the neighbours in qb.
+// A population whose destination is a wall node returns to its own node in
+// the opposite direction (wall midway between fluid and solid node).
+template <typename T, bool SHIFT>
+__device__ __forceinline__ void lbm_node(const T* __restrict__ qa, T* __restrict__ qb, const T* __restrict__ Flc,
+                                         const LbmArgs<T>& a, int k)
+{
+    const Geom& g = a.g;
+    const int x = k % g.nx;
+    const int t = k / g.nx;
+    const int y = t % g.ny;
+    const int z = t / g.ny;
+    const size_t N = (size_t)g.N;
+    T post[19];
+    lbm_collide<T, SHIFT>(qa, Flc, a, k, post);
+
     const int row = g.nx, plane = g.nx * g.ny;
     const int xs[3] = {(x == 0) ? g.nx - 1 : x - 1, x, (x == g.nx - 1) ? 0 : x + 1};
     const int ys[3] = {((y == 0) ? g.ny - 1 : y - 1) * row, y * row, ((y == g.ny - 1) ? 0 : y + 1) * row};
@@ -91,25 +113,68 @@ __device__ __forceinline__ void lbm_node(const T* __restrict__ qa, T* __restrict
         wall_p = zp == g.nzf;
     }
     const int zs[3] = {zm * plane, z * plane, zp * plane};
-
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
-        const T w = WGT<T>(i);
-        const T eu = T(EX(i)) * ux + T(EY(i)) * uy + T(EZ(i)) * uz;
-        const T eF = T(EX(i)) * Fx + T(EY(i)) * Fy + T(EZ(i)) * Fz;
-        T eq;
-        if (SHIFT)
-            eq = w * (rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu) + drho);
-        else
-            eq = w * rho * (T(1) + T(3) * eu + T(4.5) * eu * eu - T(1.5) * uu);
-        const T S = w * (T(3) * (eF - uF) + T(9) * eu * eF);
-        const T post = q[i] + a.omega * (eq - q[i]) + a.cS * S;
         const bool to_wall = (EZ(i) == 1 && wall_p) || (EZ(i) == -1 && wall_m);
         if (to_wall) {
-            qb[OPP(i) * N + k] = post;
+            qb[OPP(i) * N + k] = post[i];
         } else {
             const int d = xs[EX(i) + 1] + ys[EY(i) + 1] + zs[EZ(i) + 1];
-            qb[i * N + d] = post;
+            qb[i * N + d] = post[i];
+        }
+    }
+}
+
+// Row variant for nx a multiple of 64 (nx <= 1024): block = one x-row
+// (y, z) of nx threads.  Populations moving in x are passed through LDS to
+// the thread owning their destination column, so every global store writes
+// whole aligned rows; the arithmetic is lbm_collide's.
+template <typename T, bool SHIFT>
+__global__ void __launch_bounds__(1024) k_lbm_push_row(const T* __restrict__ qa, T* __restrict__ qb,
+                                                      const T* __restrict__ Flc, LbmArgs<T> a)
+{
+    extern __shared__ unsigned char lbm_smem[];
+    T* lds = reinterpret_cast<T*>(lbm_smem);  // [10][nx]: the directions with e_x != 0
+    const Geom& g = a.g;
+    const int x = threadIdx.x;
+    const int r = blockIdx.x;  // row index y + ny*z
+    const int y = r % g.ny;
+    const int z = r / g.ny;
+    const int k = x + g.nx * r;
+    const size_t N = (size_t)g.N;
+    T post[19];
+    lbm_collide<T, SHIFT>(qa, Flc, a, k, post);
+
+    const int row = g.nx, plane = g.nx * g.ny;
+    const int ys[3] = {((y == 0) ? g.ny - 1 : y - 1) * row, y * row, ((y == g.ny - 1) ? 0 : y + 1) * row};
+    int zm = z - 1, zp = z + 1;
+    bool wall_m = false, wall_p = false;
+    if (g.periodic_z) {
+        if (zm < 0) zm = g.nzf - 1;
+        if (zp == g.nzf) zp = 0;
+    } else {
+        wall_m = zm < 0;
+        wall_p = zp == g.nzf;
+    }
+    const int zs[3] = {zm * plane, z * plane, zp * plane};
+    // slot of each direction with e_x != 0 in the LDS staging area
+    constexpr int SLOT[19] = {-1, 0, 1, -1, -1, -1, -1, 2, 3, 4, 5, 6, 7, 8, 9, -1, -1, -1, -1};
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+        if (SLOT[i] >= 0) lds[SLOT[i] * g.nx + x] = post[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const bool to_wall = (EZ(i) == 1 && wall_p) || (EZ(i) == -1 && wall_m);
+        if (to_wall) {
+            qb[OPP(i) * N + k] = post[i];  // bounce-back: own value, own node
+        } else if (SLOT[i] < 0) {
+            qb[i * N + x + ys[EY(i) + 1] + zs[EZ(i) + 1]] = post[i];
+        } else {
+            // the population arriving at column x came from column x - e_x
+            int xs = x - EX(i);
+            xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
+            qb[i * N + x + ys[EY(i) + 1] + zs[EZ(i) + 1]] = lds[SLOT[i] * g.nx + xs];
         }
     }
 }
