@@ -45,6 +45,50 @@ def run_one(prob, n0, precision, steps):
     return out
 
 
+def tube_drift(steps=100000, every=1000, precisions=("f32_shifted", "f64_shifted"), log=print):
+    """The single-tube channel (256x256x48, r = 10): FP64 tube-drift tracking
+    every `every` steps for each precision; returns the displacement series
+    and the mean drift velocity over the second half of the run."""
+    import torch
+    from paper_2503_06610_amd import el, inputs
+    prob, n0, _ = inputs.workload_c3(r=10)
+    out = {}
+    for prec in precisions:
+        lat = el.Lattice(prob, prec)
+        lat.init_lattice(n0)
+        series = []
+        t0 = time.perf_counter()
+        d = lat.track_drift()
+        series.append((0, d["displacement"].tolist(), d["centroid"].tolist()))
+        for k in range(steps // every):
+            lat.run(every)
+            d = lat.track_drift()
+            series.append((lat.step, d["displacement"].tolist(), d["centroid"].tolist()))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        half = len(series) // 2
+        (t_a, d_a, _), (t_b, d_b, _) = series[half], series[-1]
+        v = [(d_b[i] - d_a[i]) / (t_b - t_a) for i in range(2)]
+        obs = lat.observables()
+        out[prec] = {"series": series, "drift_velocity": v, "wall_s": wall,
+                     "mlups": prob.fluid_nodes * steps / wall / 1e6, "max_u": obs["max_u"],
+                     "max_unit_dev": obs["max_unit_dev"], "nonfinite": obs["nonfinite"],
+                     "n": lat.get("n"), "u": lat.get("u")}
+        log(f"{prec}: drift velocity {v[0]:.4e}, {v[1]:.4e} (lattice units), {wall:.1f} s")
+        del lat
+        torch.cuda.empty_cache()
+    if "f32_shifted" in out and "f64_shifted" in out:
+        a, b = out["f32_shifted"], out["f64_shifted"]
+        out["f32s_vs_f64s"] = {"u": _errs(a["u"], b["u"]), "n": _errs(a["n"], b["n"]),
+                               "drift_velocity_rel": float(np.hypot(a["drift_velocity"][0] - b["drift_velocity"][0],
+                                                                    a["drift_velocity"][1] - b["drift_velocity"][1])
+                                                           / np.hypot(*b["drift_velocity"]))}
+    for prec in precisions:
+        out[prec].pop("n")
+        out[prec].pop("u")
+    return out
+
+
 def main(argv=None):
     from paper_2503_06610_amd import inputs
     ap = argparse.ArgumentParser()
@@ -53,7 +97,17 @@ def main(argv=None):
     ap.add_argument("--ratios", type=int, nargs="+", default=[1, 2, 5, 10, 20])
     ap.add_argument("--variants", nargs="+", default=["f64", "f32", "f32_shifted"])
     ap.add_argument("--out", default="")
+    ap.add_argument("--tube", action="store_true", help="run the tube-drift study of the 256x256x48 channel instead")
     args = ap.parse_args(argv)
+    if args.tube:
+        res = tube_drift(steps=args.steps)
+        summary = {k: {kk: vv for kk, vv in v.items() if kk != "series"} if isinstance(v, dict) else v
+                   for k, v in res.items()}
+        print(json.dumps(summary), flush=True)
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump(res, f, indent=1)
+        return res
     results = []
     for gx in args.gx:
         ref_r1 = None
