@@ -171,7 +171,12 @@ int el_validate(const el_params* p);
 int el_init_lattice(const el_params* p, el_state* s, const void* n0, void* stream);
 
 /* Optional warm start: q = equilibrium at rho = 1 and velocity u0 (device,
- * 3*N T); then u is recomputed from q and F^LC. */
+ * 3*N T), after removing from u0 its checkerboard components
+ * A_a (-1)^{x_a} (least-squares amplitudes, FP64): streaming maps the
+ * equilibrium of such a component onto minus itself and no collision damps
+ * it, so it would never decay.  The x and y modes exist for even periodic
+ * lengths, the z mode for an even periodic length or between walls.  Then u
+ * is recomputed from q and F^LC.  Uses the first 128 KiB of s->scratch. */
 int el_init_flow(const el_params* p, el_state* s, const void* u0, void* stream);
 
 /* nsteps LBM steps (Sec. II C): per fluid node the moments rho - 1 = sum q,

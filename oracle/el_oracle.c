@@ -595,11 +595,40 @@ void or_init(or_state* s, const double* n0)
     or_force(s); /* R10: initial force from n0 with u = 0 */
 }
 
+/* Warm start: q = equilibrium at rho = 1 and velocity u0, with the velocity's
+ * checkerboard components removed first.  The equilibrium at velocity
+ * A (-1)^{x_a} e_a is mapped by streaming onto minus itself and no collision
+ * damps it (it has no density and no non-equilibrium part), so any such
+ * component of u0 would persist forever.  For each component a the mode
+ * exists when the lattice extent along a is even (periodic x, y, z) and
+ * always along z between walls; its least-squares amplitude is removed. */
 void or_init_flow(or_state* s, const double* u0)
 {
     const or_params* p = &s->p;
     double* ufull = (double*)calloc((size_t)(3 * s->N), sizeof(double));
     from_external(s, u0, 3, ufull);
+    const int ext[3] = {p->nx, p->ny, nzf(p)};
+    for (int a = 0; a < 3; ++a) {
+        const int has_mode = (a == 2 && !p->periodic_z) || (ext[a] % 2 == 0);
+        if (!has_mode) continue;
+        double sum = 0.0, count = 0.0;
+        for (int z = z_lo(p); z < z_hi(p); ++z)
+            for (int y = 0; y < p->ny; ++y)
+                for (int x = 0; x < p->nx; ++x) {
+                    const int c[3] = {x, y, z - z_lo(p)};
+                    const double sign = (c[a] % 2 == 0) ? 1.0 : -1.0;
+                    sum += sign * ufull[(int64_t)a * s->N + idx(p, x, y, z)];
+                    count += 1.0;
+                }
+        const double amp = sum / count;
+        for (int z = z_lo(p); z < z_hi(p); ++z)
+            for (int y = 0; y < p->ny; ++y)
+                for (int x = 0; x < p->nx; ++x) {
+                    const int c[3] = {x, y, z - z_lo(p)};
+                    const double sign = (c[a] % 2 == 0) ? 1.0 : -1.0;
+                    ufull[(int64_t)a * s->N + idx(p, x, y, z)] -= amp * sign;
+                }
+    }
     for (int z = z_lo(p); z < z_hi(p); ++z)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {

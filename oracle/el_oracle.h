@@ -69,7 +69,9 @@ void or_set_threads(int32_t nthreads);
  * n0 with u = 0.  n0 is in external layout (3 components). */
 void or_init(or_state* s, const double* n0);
 
-/* Overwrite q with the equilibrium at rho = 1 and velocity u0 (external layout). */
+/* Overwrite q with the equilibrium at rho = 1 and velocity u0 (external
+ * layout) after removing u0's undamped checkerboard components (see the
+ * definition). */
 void or_init_flow(or_state* s, const double* u0);
 
 /* nsteps LBM steps with F^LC held fixed; u is recomputed after every step. */

@@ -168,10 +168,23 @@ int init_impl(const el_params* p, el_state* s, const void* n0, hipStream_t st)
 template <typename T, bool SHIFT>
 int init_flow_impl(const el_params* p, el_state* s, const void* u0, hipStream_t st)
 {
-    const int N = geom_of(p).N;
-    hipLaunchKernelGGL((el::k_equilibrium<T, SHIFT>), dim3(grid_for(N)), dim3(BLOCK), 0, st,
-                       static_cast<T*>(s->q[s->parity]), static_cast<const T*>(u0), N);
-    int rc = check_launch("k_equilibrium");
+    const el::Geom g = geom_of(p);
+    // checkerboard amplitudes: x and y modes exist for even periodic lengths,
+    // the z mode for an even periodic length or between walls
+    const int has_mode = ((g.nx % 2 == 0) ? 1 : 0) | ((g.ny % 2 == 0) ? 2 : 0) |
+                         ((!g.periodic_z || g.nzf % 2 == 0) ? 4 : 0);
+    int blocks = grid_for(g.N);
+    if (blocks > el::RED_MAX_BLOCKS) blocks = el::RED_MAX_BLOCKS;
+    double* partial = static_cast<double*>(s->scratch);
+    double* amp = partial + (REDUCE_BYTES / sizeof(double)) - 8;
+    hipLaunchKernelGGL((el::k_checker_partial<T>), dim3(blocks), dim3(el::RED_THREADS), 0, st,
+                       static_cast<const T*>(u0), g, partial);
+    hipLaunchKernelGGL(el::k_checker_final, dim3(1), dim3(el::RED_THREADS), 0, st, static_cast<const double*>(partial),
+                       blocks, g.N, has_mode, amp);
+    hipLaunchKernelGGL((el::k_equilibrium<T, SHIFT>), dim3(grid_for(g.N)), dim3(BLOCK), 0, st,
+                       static_cast<T*>(s->q[s->parity]), static_cast<const T*>(u0), g,
+                       static_cast<const double*>(amp));
+    int rc = check_launch("warm-start kernels");
     if (rc != EL_OK) return rc;
     return launch_moments<T, SHIFT>(p, s, st);
 }

@@ -240,14 +240,22 @@ __global__ void __launch_bounds__(256) k_rest(T* __restrict__ q, int N)
     for (int i = 0; i < 19; ++i) q[(size_t)i * N + k] = SHIFT ? T(0) : WGT<T>(i);
 }
 
-// Equilibrium at rho = 1 and velocity u0 (warm start).
+// Equilibrium at rho = 1 and velocity u0 minus its checkerboard components
+// amp[a] (-1)^{x_a} (warm start).
 template <typename T, bool SHIFT>
-__global__ void __launch_bounds__(256) k_equilibrium(T* __restrict__ q, const T* __restrict__ u0, int N)
+__global__ void __launch_bounds__(256) k_equilibrium(T* __restrict__ q, const T* __restrict__ u0, Geom g,
+                                                    const double* __restrict__ amp)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N) return;
-    const size_t n = (size_t)N;
-    const T ux = u0[k], uy = u0[n + k], uz = u0[2 * n + k];
+    if (k >= g.N) return;
+    const size_t n = (size_t)g.N;
+    const int x = k % g.nx;
+    const int t = k / g.nx;
+    const int y = t % g.ny;
+    const int z = t / g.ny;
+    const T ux = (T)((double)u0[k] - ((x & 1) ? -amp[0] : amp[0]));
+    const T uy = (T)((double)u0[n + k] - ((y & 1) ? -amp[1] : amp[1]));
+    const T uz = (T)((double)u0[2 * n + k] - ((z & 1) ? -amp[2] : amp[2]));
     const T uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
     for (int i = 0; i < 19; ++i) {

@@ -194,6 +194,46 @@ static __global__ void __launch_bounds__(RED_THREADS) k_obs_final(const double* 
     }
 }
 
+// Signed sums sum_v u_a(v) (-1)^{x_a(v)} of a velocity field (FP64), the
+// amplitudes of its checkerboard components.
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) k_checker_partial(const T* __restrict__ u, Geom g,
+                                                                double* __restrict__ partial)
+{
+    __shared__ double lds[RED_THREADS / 64][3];
+    double v[3] = {0.0, 0.0, 0.0};
+    const size_t N = (size_t)g.N;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < g.N; k += gridDim.x * blockDim.x) {
+        const int x = k % g.nx;
+        const int t = k / g.nx;
+        const int y = t % g.ny;
+        const int z = t / g.ny;
+        v[0] += (x & 1) ? -(double)u[k] : (double)u[k];
+        v[1] += (y & 1) ? -(double)u[N + k] : (double)u[N + k];
+        v[2] += (z & 1) ? -(double)u[2 * N + k] : (double)u[2 * N + k];
+    }
+    block_reduce<3, 3>(v, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) partial[blockIdx.x * 3 + j] = v[j];
+}
+
+// amp[a] = (sum of the block rows) / N for the components whose checkerboard
+// mode exists (has_mode bit a), else 0.
+static __global__ void __launch_bounds__(RED_THREADS) k_checker_final(const double* __restrict__ partial, int nblocks,
+                                                              int N, int has_mode, double* __restrict__ amp)
+{
+    __shared__ double lds[RED_THREADS / 64][3];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) v[j] += partial[b * 3 + j];
+    block_reduce<3, 3>(v, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) amp[j] = ((has_mode >> j) & 1) ? v[j] / (double)N : 0.0;
+}
+
 // Error sums of a (T) against ref (double), ncomp components.
 template <typename T>
 __global__ void __launch_bounds__(RED_THREADS) k_err_partial(const T* __restrict__ a, const double* __restrict__ ref,

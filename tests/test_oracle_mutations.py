@@ -50,6 +50,8 @@ MUTATIONS = [
     ("solid_director_value", "if (field_kind == 0) return comp == 2 ? 1.0 : 0.0;",
      "if (field_kind == 0) return comp == 0 ? 1.0 : 0.0;"),
     ("no_corrector_normalisation", "normalise(v);\n                /* n(x) is read only", "/* n(x) is read only"),
+    ("checkerboard_projection_sign", "ufull[(int64_t)a * s->N + idx(p, x, y, z)] -= amp * sign;",
+     "ufull[(int64_t)a * s->N + idx(p, x, y, z)] += amp * sign;"),
 ]
 
 PINS = [
@@ -75,6 +77,8 @@ PINS = [
     pins.test_alpha4p_term_on_shear_wave,
     pins.test_elastic_stress_satisfies_ericksen_identity,
     pins.test_viscous_stress_power_identity,
+    pins.test_checkerboard_velocity_mode_is_undamped,
+    pins.test_warm_start_converges_back_to_steady_flow,
 ]
 
 

@@ -597,3 +597,45 @@ def test_viscous_stress_power_identity():
         sig = o.stress(mask)
         power = np.einsum("abzyx,bazyx->zyx", sig, A)
         assert np.abs(power - w).max() < 1e-13 * max(np.abs(w).max(), 1e-30) + 1e-25, mask
+
+
+def test_checkerboard_velocity_mode_is_undamped():
+    """Streaming maps the first-order equilibrium of u_x = A (-1)^x onto minus
+    itself and no collision damps it: the reported velocity flips sign every
+    step, forever (the reason the warm start removes this component)."""
+    prob = inputs.Problem(nx=8, ny=5, nz=6, tau=0.9, coupling=False, alpha=(0, -0.1, 0.1, 0, 0, 0))
+    o = oracle_for(prob)
+    o.init(_uniform_director(prob))
+    e, w, _ = lattice()
+    A = 1e-9
+    x = np.arange(prob.nx)
+    ux = A * (-1.0) ** x
+    q = np.zeros(prob.shape(19))
+    for i in range(19):
+        q[i] = (w[i] * 3.0 * e[i, 0] * ux)[None, None, :]
+    o.set("q", q)
+    u_prev = None
+    for t in range(6):
+        o.step_lbm(1)
+        u = o.get("u")[0]
+        if u_prev is not None:
+            assert np.abs(u + u_prev).max() < 1e-20
+        assert abs(np.abs(u).max() / A - 1.0) < 1e-6
+        u_prev = u
+
+
+def test_warm_start_converges_back_to_steady_flow():
+    """A warm start from the steady channel flow plus random noise returns to
+    the steady flow (the checkerboard components of the noise are removed by
+    the initialiser; everything else decays)."""
+    prob = inputs.channel(16, 10, 12, inputs.set_b(), g=(1e-6, 0, 0), coupling=False)
+    ref = oracle_for(prob)
+    ref.init(_uniform_director(prob))
+    ref.step_lbm(2000)
+    u_ref = ref.get("u")
+    o = oracle_for(prob)
+    o.init(_uniform_director(prob))
+    o.init_flow(u_ref + 1e-4 * RNG.normal(size=u_ref.shape))
+    o.step_lbm(3000)
+    ref.step_lbm(3000)
+    assert rel_l2(o.get("u"), ref.get("u")) < 1e-6
