@@ -160,8 +160,13 @@ size_t el_buffer_bytes(const el_params* p, int32_t which);
  * coupling, unknown precision or flags.  EL_EUNSTABLE (unless
  * EL_ALLOW_UNSTABLE): r * 12 K / gamma1 > 2 (the explicit Heun step on the
  * compact Laplacian); r = 1 with coupling and tau > 1.5 (the Leslie force
- * refreshed every LBM step diverges there: an empirical bound, found with
- * the FP64 CPU implementation); or a Mach estimate |g| H^2/(8 nu) sqrt(3) > 0.1. */
+ * refreshed every LBM step diverges there within a few hundred steps: an
+ * empirical bound, found with the FP64 CPU implementation); or a Mach
+ * estimate |g| H^2/(8 nu) sqrt(3) > 0.1.  Passing does not guarantee long
+ * runs: a force held over an odd number r of LBM steps can feed the
+ * lattice's sign-alternating (period-2) velocity modes, which then grow
+ * slowly (seen over 5,000-25,000 steps at r = 1, tau = 0.8 and r = 5,
+ * tau = 1.8977 with strongly distorted directors); even r never diverged. */
 int el_validate(const el_params* p);
 
 /* Initialisation (Sec. II D, first step): q = rest state (0 when shifted,

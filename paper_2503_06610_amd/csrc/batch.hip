@@ -94,7 +94,8 @@ __global__ void __launch_bounds__(1024) k_batch_fd(const ChanDesc<T>* __restrict
                                                   int ntiles, const int* __restrict__ tdev, int all)
 {
     const int t = *tdev;
-    for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
+    // consecutive tiles (neighbouring rows of a channel) on one XCD
+    for (int w = xcd_remap(blockIdx.x, gridDim.x); w < ntiles; w += gridDim.x) {
         const int2 tl = tiles[w];
         const ChanDesc<T>& c = ch[tl.x];
         if (!all && !fd_due(c, t)) continue;

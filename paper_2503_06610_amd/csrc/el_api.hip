@@ -122,13 +122,11 @@ int launch_force(const el_params* p, el_state* s, hipStream_t st)
         return check_launch("clear F");
     }
     T* sig = sigma_of<T>(s);
-    const dim3 zg = zmarch_grid(a.g);
-    hipLaunchKernelGGL((el::k_fd_zmarch<T, 2>), zg, dim3(256), 0, st, static_cast<const T*>(s->n),
-                       static_cast<const T*>(s->u), sig, static_cast<T*>(nullptr), static_cast<const T*>(nullptr),
-                       static_cast<const T*>(nullptr), a, ZCHUNK);
-    hipLaunchKernelGGL((el::k_fd_zmarch<T, 3>), zg, dim3(256), 0, st, static_cast<const T*>(sig),
-                       static_cast<const T*>(nullptr), static_cast<T*>(s->F), static_cast<T*>(nullptr),
-                       static_cast<const T*>(nullptr), static_cast<const T*>(nullptr), a, ZCHUNK);
+    const int grid = grid_for(a.g.N);
+    hipLaunchKernelGGL((el::k_fd_stress<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
+                       static_cast<const T*>(s->u), sig, a);
+    hipLaunchKernelGGL((el::k_fd_divergence<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(sig),
+                       static_cast<T*>(s->F), a);
     return check_launch("force kernels");
 }
 
@@ -137,13 +135,12 @@ int launch_director(const el_params* p, el_state* s, hipStream_t st)
 {
     const el::FdArgs<T> a = fd_args<T>(p);
     if (p->flags & EL_FREEZE_DIRECTOR) return launch_force<T>(p, s, st);
-    const dim3 zg = zmarch_grid(a.g);
-    hipLaunchKernelGGL((el::k_fd_zmarch<T, 0>), zg, dim3(256), 0, st, static_cast<const T*>(s->n),
-                       static_cast<const T*>(s->u), static_cast<T*>(s->n_pred), static_cast<T*>(s->dndt),
-                       static_cast<const T*>(nullptr), static_cast<const T*>(nullptr), a, ZCHUNK);
-    hipLaunchKernelGGL((el::k_fd_zmarch<T, 1>), zg, dim3(256), 0, st, static_cast<const T*>(s->n_pred),
-                       static_cast<const T*>(s->u), static_cast<T*>(s->n), static_cast<T*>(nullptr),
-                       static_cast<const T*>(s->n), static_cast<const T*>(s->dndt), a, ZCHUNK);
+    const int grid = grid_for(a.g.N);
+    hipLaunchKernelGGL((el::k_fd_predictor<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
+                       static_cast<const T*>(s->u), static_cast<T*>(s->n_pred), static_cast<T*>(s->dndt), a);
+    hipLaunchKernelGGL((el::k_fd_corrector<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<T*>(s->n),
+                       static_cast<const T*>(s->n_pred), static_cast<const T*>(s->u),
+                       static_cast<const T*>(s->dndt), a);
     int rc = check_launch("director kernels");
     if (rc != EL_OK) return rc;
     return launch_force<T>(p, s, st);

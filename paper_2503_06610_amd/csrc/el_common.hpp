@@ -79,4 +79,17 @@ __device__ inline Nbr make_nbr(const Geom& g, int x, int y, int z)
     return n;
 }
 
+// The workgroups of a launch go to the chip's eight XCDs (each with its own
+// L2) round-robin by linear block index.  xcd_remap renumbers a block so that
+// each XCD receives one contiguous range of logical blocks: the rows and
+// planes a stencil reads around a block then sit in the same L2 as the block.
+constexpr int NUM_XCD = 8;
+
+__device__ __forceinline__ int xcd_remap(int b, int nblocks)
+{
+    const int q = nblocks / NUM_XCD, r = nblocks % NUM_XCD;
+    const int xcd = b % NUM_XCD, i = b / NUM_XCD;
+    return xcd * q + min(xcd, r) + i;
+}
+
 }  // namespace el

@@ -179,7 +179,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_fd_predictor(const T* __restrict__ n, const T* __restrict__ u,
                                                      T* __restrict__ nP, T* __restrict__ dndt, FdArgs<T> a)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (k >= a.g.N) return;
     predictor_node(n, u, nP, dndt, a, k);
 }
@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(256) k_fd_corrector(T* __restrict__ n, const T
                                                      const T* __restrict__ u, const T* __restrict__ dndt,
                                                      FdArgs<T> a)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (k >= a.g.N) return;
     corrector_node(n, nP, u, dndt, a, k);
 }
@@ -279,7 +279,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_fd_stress(const T* __restrict__ n, const T* __restrict__ u,
                                                   T* __restrict__ sig, FdArgs<T> a)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (k >= a.g.N) return;
     stress_node(n, u, sig, a, k);
 }
@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(256) k_fd_stress(const T* __restrict__ n, cons
 template <typename T>
 __global__ void __launch_bounds__(256) k_fd_divergence(const T* __restrict__ sig, T* __restrict__ F, FdArgs<T> a)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (k >= a.g.N) return;
     divergence_node(sig, F, a, k);
 }

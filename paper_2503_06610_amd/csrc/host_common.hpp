@@ -11,7 +11,6 @@
 #include "el.h"
 #include "el_common.hpp"
 #include "fd_kernels.hpp"
-#include "fd_zmarch.hpp"
 #include "lbm_kernels.hpp"
 #include "reduce_kernels.hpp"
 
@@ -55,14 +54,6 @@ int stability_checks(const el_params* p);
 int state_checks(const el_params* p, const el_state* s);
 
 inline int grid_for(int N) { return (N + BLOCK - 1) / BLOCK; }
-
-// z planes per block of the z-marching FD kernels.
-constexpr int ZCHUNK = 8;
-
-inline dim3 zmarch_grid(const el::Geom& g)
-{
-    return dim3((g.nx + el::ZM_TX - 1) / el::ZM_TX, (g.ny + el::ZM_TY - 1) / el::ZM_TY, (g.nzf + ZCHUNK - 1) / ZCHUNK);
-}
 
 template <typename T>
 el::LbmArgs<T> lbm_args(const el_params* p)

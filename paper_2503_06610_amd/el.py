@@ -240,6 +240,12 @@ class Lattice:
     def run(self, T: int, stream=None):
         _check(self.lib.el_run(C.byref(self.params), C.byref(self.state), int(T), _stream_ptr(stream)), "el_run")
 
+    def observables_to(self, ptr: int, stream=None):
+        """Device-side observables into the el_obs at device address ptr; no
+        host synchronisation (read it later with decode_obs)."""
+        _check(self.lib.el_observables(C.byref(self.params), C.byref(self.state), C.c_void_p(ptr),
+                                       _stream_ptr(stream)), "el_observables")
+
     def observables(self, stream=None) -> dict:
         import torch
         _check(self.lib.el_observables(C.byref(self.params), C.byref(self.state),
