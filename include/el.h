@@ -238,7 +238,10 @@ int el_error_norms(const el_params* p, const void* a, const double* ref, int32_t
  * and FD/LBM step ratios advanced together.  Each step launches persistent
  * kernels over a work list of (channel, tile) pairs; a device step counter
  * decides per channel whether the finite-difference update of Sec. II D is
- * due ((step + 1) % r == 0), so one captured step replays without the host.
+ * due ((step + 1) % r == 0).  When the least common multiple P of the
+ * channels' r is at most 64, el_batch_capture records P graphs, one per
+ * phase of the step count, each launching exactly the due tiles; the host
+ * replays the one for the current step.
  * Every channel performs the same arithmetic as the single-lattice calls, in
  * the same order, so its state is bitwise equal to an el_run of that channel.
  * ------------------------------------------------------------------------ */
@@ -246,9 +249,13 @@ typedef struct el_batch el_batch;   /* opaque handle owned by the library */
 
 typedef struct {
     int32_t lbm_block;          /* threads per block = nodes per tile of the LBM kernel (64..1024) */
-    int32_t lbm_blocks_per_cu;  /* persistent grid = compute units * this */
+    int32_t lbm_blocks_per_cu;  /* 0: one block per tile; 1..64: persistent grid of
+                                   compute units * this blocks looping over the tiles */
     int32_t fd_block;           /* the same for the moments and FD kernels */
-    int32_t fd_blocks_per_cu;
+    int32_t fd_blocks_per_cu;   /* used only when the least common multiple of the
+                                   channels' r exceeds 64 (persistent grid; 0 means 8):
+                                   otherwise each step launches one block per due
+                                   tile, and none when no channel is due */
     int32_t tuned;              /* out: 1 if chosen by the autotuner, 2 if taken from its cache */
     int32_t reserved;
 } el_batch_tuning;
@@ -269,7 +276,8 @@ int el_batch_create(const el_params* params, el_state* states, int32_t nchan, co
                     void* stream, el_batch** out);
 
 /* nsteps coupled steps of every channel (Sec. II D per channel).  After
- * el_batch_capture each step is one hipGraphLaunch of the captured step. */
+ * el_batch_capture each step is one hipGraphLaunch (of the graph for the
+ * step's phase). */
 int el_batch_step(el_batch* b, int32_t nsteps, void* stream);
 
 /* Captures one batched step into a hipGraph on `stream`, a created stream

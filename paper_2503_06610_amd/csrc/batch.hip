@@ -34,14 +34,37 @@ struct ChanDesc {
     int frozen;       // 1: the FD step only refreshes F^LC (director fixed)
     int parity0;      // q[parity0] is current when the batch is created
     long long step0;  // LBM steps the channel had taken when the batch was created
+    int phase;        // step0 mod fd_ratio
 };
 
 // The FD update of a channel is due after the LBM step that brings its step
 // count to a multiple of r; t = batched steps completed before this one.
-template <typename T>
-__device__ __forceinline__ bool fd_due(const ChanDesc<T>& c, int t)
+__device__ __forceinline__ bool fd_due(int r, int phase, int t) { return (phase + t % r + 1) % r == 0; }
+
+// The FD tile list is sorted by (r, step mod r): group k holds the tiles
+// [first, first + count) of every channel with that ratio and phase, so the
+// tiles due at a step are a few whole groups.
+struct DueGroup {
+    int r, phase, first, count;
+};
+
+__device__ __forceinline__ int due_count(const DueGroup* __restrict__ gr, int ng, int t)
 {
-    return ((c.step0 + (long long)t + 1) % c.fd_ratio) == 0;
+    int n = 0;
+    for (int k = 0; k < ng; ++k)
+        if (fd_due(gr[k].r, gr[k].phase, t)) n += gr[k].count;
+    return n;
+}
+
+// The tile of the i-th due tile at step t (i < due_count).
+__device__ __forceinline__ int due_tile(const DueGroup* __restrict__ gr, int ng, int t, int i)
+{
+    for (int k = 0; k < ng; ++k) {
+        if (!fd_due(gr[k].r, gr[k].phase, t)) continue;
+        if (i < gr[k].count) return gr[k].first + i;
+        i -= gr[k].count;
+    }
+    return 0;
 }
 
 template <typename T, bool SHIFT>
@@ -70,15 +93,17 @@ enum { MOM_DUE_IN_STEP = 0, MOM_ALL = 1, MOM_AFTER_PARTIAL = 2 };
 template <typename T, bool SHIFT>
 __global__ void __launch_bounds__(1024) k_batch_moments(const ChanDesc<T>* __restrict__ ch,
                                                        const int2* __restrict__ tiles, int ntiles,
-                                                       const int* __restrict__ tdev, int mode)
+                                                       const DueGroup* __restrict__ groups, int ngroups,
+                                                       const int* __restrict__ tdev, int mode, int remap)
 {
     const int t = *tdev;
     const int in_step = (mode == MOM_DUE_IN_STEP) ? 1 : 0;
-    for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
+    const int n = in_step ? due_count(groups, ngroups, t) : ntiles;
+    for (int i = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x; i < n; i += gridDim.x) {
+        const int w = in_step ? due_tile(groups, ngroups, t, i) : i;
         const int2 tl = tiles[w];
         const ChanDesc<T>& c = ch[tl.x];
-        if (mode == MOM_DUE_IN_STEP && !fd_due(c, t)) continue;
-        if (mode == MOM_AFTER_PARTIAL && ((c.step0 + (long long)t) % c.fd_ratio) == 0) continue;
+        if (mode == MOM_AFTER_PARTIAL && (c.phase + t % c.fd_ratio) % c.fd_ratio == 0) continue;
         const int k = tl.y + (int)threadIdx.x;
         if (k < c.lbm.g.N) {
             const int par = c.parity0 ^ ((t + in_step) & 1);
@@ -88,17 +113,20 @@ __global__ void __launch_bounds__(1024) k_batch_moments(const ChanDesc<T>* __res
 }
 
 // stage 0 predictor, 1 corrector, 2 stress, 3 divergence (or F = 0 without
-// coupling); all = 1 runs every channel (autotuning), else due channels only.
+// coupling); all = 1 runs every channel (autotuning), else the due tiles only.
+// remap = 1 (persistent grids): the XCDs take contiguous runs of the due
+// tiles, so stencil neighbours share an L2 and every XCD gets an equal share.
 template <typename T, int STAGE>
 __global__ void __launch_bounds__(1024) k_batch_fd(const ChanDesc<T>* __restrict__ ch, const int2* __restrict__ tiles,
-                                                  int ntiles, const int* __restrict__ tdev, int all)
+                                                  int ntiles, const DueGroup* __restrict__ groups, int ngroups,
+                                                  const int* __restrict__ tdev, int all, int remap)
 {
     const int t = *tdev;
-    // consecutive tiles (neighbouring rows of a channel) on one XCD
-    for (int w = xcd_remap(blockIdx.x, gridDim.x); w < ntiles; w += gridDim.x) {
+    const int n = all ? ntiles : due_count(groups, ngroups, t);
+    for (int i = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x; i < n; i += gridDim.x) {
+        const int w = all ? i : due_tile(groups, ngroups, t, i);
         const int2 tl = tiles[w];
         const ChanDesc<T>& c = ch[tl.x];
-        if (!all && !fd_due(c, t)) continue;
         if (STAGE <= 1 && c.frozen) continue;
         const int k = tl.y + (int)threadIdx.x;
         if (k >= c.fd.g.N) continue;
@@ -137,14 +165,18 @@ struct el_batch {
     void* d_chan = nullptr;
     int2* d_tiles_lbm = nullptr;
     int ntiles_lbm = 0;
-    int2* d_tiles_fd = nullptr;
+    int2* d_tiles_fd = nullptr;  // sorted by (r, step mod r)
     int ntiles_fd = 0;
+    el::DueGroup* d_groups = nullptr;
+    int ngroups = 0;
     int* d_t = nullptr;
     long long h_t = 0;
     int cus = 0;
     el_batch_tuning tuning{};
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    std::vector<el::DueGroup> h_groups;  // host copy of the group table
+    int period = 0;  // lcm of the channels' r when <= MAX_PERIOD (one graph per phase), else 0
+    std::vector<hipGraph_t> graphs;
+    std::vector<hipGraphExec_t> execs;
 };
 
 namespace {
@@ -159,6 +191,30 @@ std::vector<int2> make_tiles(const std::vector<el_params>& params, int tile)
     for (size_t c = 0; c < params.size(); ++c) {
         const int N = geom_of(&params[c]).N;
         for (int s = 0; s < N; s += tile) tiles.push_back(make_int2((int)c, s));
+    }
+    return tiles;
+}
+
+// FD tiles grouped by (r, step mod r), channel order kept inside a group,
+// and the group table.
+std::vector<int2> make_fd_tiles(const el_batch* b, int tile, std::vector<el::DueGroup>& groups)
+{
+    std::vector<int> order(b->nchan);
+    for (int c = 0; c < b->nchan; ++c) order[c] = c;
+    auto key = [&](int c) {
+        const int r = b->params[c].fd_ratio;
+        return std::make_pair(r, (int)(b->states0[c].step % r));
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return key(a) < key(c); });
+    std::vector<int2> tiles;
+    groups.clear();
+    for (int c : order) {
+        const auto k = key(c);
+        if (groups.empty() || groups.back().r != k.first || groups.back().phase != k.second)
+            groups.push_back(el::DueGroup{k.first, k.second, (int)tiles.size(), 0});
+        const int N = geom_of(&b->params[c]).N;
+        for (int s = 0; s < N; s += tile) tiles.push_back(make_int2(c, s));
+        groups.back().count = (int)tiles.size() - groups.back().first;
     }
     return tiles;
 }
@@ -196,6 +252,7 @@ int build_table(el_batch* b)
         d.frozen = (p->flags & EL_FREEZE_DIRECTOR) ? 1 : 0;
         d.parity0 = s->parity;
         d.step0 = s->step;
+        d.phase = (int)(s->step % p->fd_ratio);
     }
     if (hipMalloc(&b->d_chan, sizeof(el::ChanDesc<T>) * b->nchan) != hipSuccess)
         return fail(EL_EDEVICE, "hipMalloc of the batch channel table failed");
@@ -204,7 +261,8 @@ int build_table(el_batch* b)
     return EL_OK;
 }
 
-int grid_of(int ntiles, int cus, int bpc) { return std::max(1, std::min(ntiles, cus * bpc)); }
+// bpc == 0: one block per tile; otherwise a persistent grid of cus * bpc blocks.
+int grid_of(int ntiles, int cus, int bpc) { return std::max(1, bpc == 0 ? ntiles : std::min(ntiles, cus * bpc)); }
 
 template <typename T, bool SHIFT>
 void launch_lbm(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int block, int bpc)
@@ -214,41 +272,66 @@ void launch_lbm(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int 
 }
 
 template <typename T, bool SHIFT>
-void launch_moments(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int block, int bpc, int mode)
+void launch_moments(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int block, int grid, int mode,
+                    int remap)
 {
-    hipLaunchKernelGGL((el::k_batch_moments<T, SHIFT>), dim3(grid_of(ntiles, b->cus, bpc)), dim3(block), 0, st,
-                       static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles, b->d_t, mode);
+    hipLaunchKernelGGL((el::k_batch_moments<T, SHIFT>), dim3(grid), dim3(block), 0, st,
+                       static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles,
+                       static_cast<const el::DueGroup*>(b->d_groups), b->ngroups, b->d_t, mode, remap);
 }
 
 template <typename T, int STAGE>
-void launch_fd(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int block, int bpc, int all)
+void launch_fd(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int block, int grid, int all, int remap)
 {
-    hipLaunchKernelGGL((el::k_batch_fd<T, STAGE>), dim3(grid_of(ntiles, b->cus, bpc)), dim3(block), 0, st,
-                       static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles, b->d_t, all);
+    hipLaunchKernelGGL((el::k_batch_fd<T, STAGE>), dim3(grid), dim3(block), 0, st,
+                       static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles,
+                       static_cast<const el::DueGroup*>(b->d_groups), b->ngroups, b->d_t, all, remap);
 }
 
+// Tiles whose FD update is due in batched step t (host side of due_count).
+int due_tiles_host(const el_batch* b, long long t)
+{
+    int n = 0;
+    for (const el::DueGroup& g : b->h_groups)
+        if ((g.phase + t % g.r + 1) % g.r == 0) n += g.count;
+    return n;
+}
+
+// One batched step, batched step index t.  With a period (every channel's r
+// divides it) the moments and FD kernels get exactly one block per due tile,
+// and none at all when no channel is due; the kernels still find the due
+// tiles from the device step counter, which equals t.  Without a period they
+// run on persistent grids over the device-side due list.
 template <typename T, bool SHIFT>
-int enqueue_step(el_batch* b, hipStream_t st)
+int enqueue_step(el_batch* b, hipStream_t st, long long t)
 {
     const el_batch_tuning& tu = b->tuning;
     launch_lbm<T, SHIFT>(b, st, b->d_tiles_lbm, b->ntiles_lbm, tu.lbm_block, tu.lbm_blocks_per_cu);
-    launch_moments<T, SHIFT>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu,
-                             el::MOM_DUE_IN_STEP);
-    launch_fd<T, 0>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, 0);
-    launch_fd<T, 1>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, 0);
-    launch_fd<T, 2>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, 0);
-    launch_fd<T, 3>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, 0);
+    int grid = 0;
+    if (b->period > 0)
+        grid = due_tiles_host(b, t);
+    else
+        grid = grid_of(b->ntiles_fd, b->cus, tu.fd_blocks_per_cu > 0 ? tu.fd_blocks_per_cu : 8);
+    if (grid > 0) {
+        const int2* tl = b->d_tiles_fd;
+        const int n = b->ntiles_fd, blk = tu.fd_block;
+        launch_moments<T, SHIFT>(b, st, tl, n, blk, grid, el::MOM_DUE_IN_STEP, 1);
+        launch_fd<T, 0>(b, st, tl, n, blk, grid, 0, 1);
+        launch_fd<T, 1>(b, st, tl, n, blk, grid, 0, 1);
+        launch_fd<T, 2>(b, st, tl, n, blk, grid, 0, 1);
+        launch_fd<T, 3>(b, st, tl, n, blk, grid, 0, 1);
+    }
     hipLaunchKernelGGL(el::k_batch_tick, dim3(1), dim3(64), 0, st, b->d_t);
     return check_launch("batched step kernels");
 }
 
-int dispatch_step(el_batch* b, hipStream_t st)
+int dispatch_step(el_batch* b, hipStream_t st, long long t)
 {
     switch (b->precision) {
-    case EL_F64: return enqueue_step<double, false>(b, st);
-    case EL_F64_SHIFTED: return enqueue_step<double, true>(b, st);
-    case EL_F32: return enqueue_step<float, false>(b, st);
-    default: return enqueue_step<float, true>(b, st);
+    case EL_F64: return enqueue_step<double, false>(b, st, t);
+    case EL_F64_SHIFTED: return enqueue_step<double, true>(b, st, t);
+    case EL_F32: return enqueue_step<float, false>(b, st, t);
+    default: return enqueue_step<float, true>(b, st, t);
     }
 }
 
@@ -298,7 +381,7 @@ int autotune(el_batch* b, hipStream_t st)
 {
     const int lbm_blocks[] = {128, 256, 512, 1024};
     const int fd_blocks[] = {128, 256, 512};
-    const int bpcs[] = {2, 4, 8, 16, 32};
+    const int bpcs[] = {0, 2, 4, 8, 16, 32};
     float best = 1e30f;
     el_batch_tuning tu = b->tuning;
     int2* dt = nullptr;
@@ -316,16 +399,20 @@ int autotune(el_batch* b, hipStream_t st)
             }
         }
     }
+    // FD tile size, timed with every tile active.  With a period the step
+    // launches one block per due tile (blocks_per_cu 0); without one, the
+    // persistent grids are timed too.
     best = 1e30f;
     for (int blk : fd_blocks) {
         const std::vector<int2> tiles = make_tiles(b->params, blk);
         int rc = upload_tiles(tiles, &dt);
         if (rc != EL_OK) return rc;
         for (int bpc : bpcs) {
-            if (bpc * blk > 16 * 1024) continue;
+            if ((b->period > 0) != (bpc == 0) || bpc * blk > 16 * 1024) continue;
+            const int grid = grid_of((int)tiles.size(), b->cus, bpc);
             const float ms = time_launches(st, [&] {
-                launch_fd<T, 0>(b, st, dt, (int)tiles.size(), blk, bpc, 1);
-                launch_fd<T, 2>(b, st, dt, (int)tiles.size(), blk, bpc, 1);
+                launch_fd<T, 0>(b, st, dt, (int)tiles.size(), blk, grid, 1, bpc > 0 ? 1 : 0);
+                launch_fd<T, 2>(b, st, dt, (int)tiles.size(), blk, grid, 1, bpc > 0 ? 1 : 0);
             });
             if (ms < best) {
                 best = ms;
@@ -343,7 +430,7 @@ int autotune(el_batch* b, hipStream_t st)
 int valid_tuning(const el_batch_tuning& t)
 {
     auto ok_block = [](int v) { return v >= 64 && v <= 1024 && v % 64 == 0; };
-    return ok_block(t.lbm_block) && ok_block(t.fd_block) && t.lbm_blocks_per_cu >= 1 && t.fd_blocks_per_cu >= 1 &&
+    return ok_block(t.lbm_block) && ok_block(t.fd_block) && t.lbm_blocks_per_cu >= 0 && t.fd_blocks_per_cu >= 0 &&
            t.lbm_blocks_per_cu <= 64 && t.fd_blocks_per_cu <= 64;
 }
 
@@ -353,28 +440,59 @@ int build_tiles(el_batch* b)
     int rc = upload_tiles(lt, &b->d_tiles_lbm);
     if (rc != EL_OK) return rc;
     b->ntiles_lbm = (int)lt.size();
-    const std::vector<int2> ft = make_tiles(b->params, b->tuning.fd_block);
+    std::vector<el::DueGroup> groups;
+    const std::vector<int2> ft = make_fd_tiles(b, b->tuning.fd_block, groups);
     rc = upload_tiles(ft, &b->d_tiles_fd);
     if (rc != EL_OK) return rc;
     b->ntiles_fd = (int)ft.size();
+    if (b->d_groups) (void)hipFree(b->d_groups);
+    b->d_groups = nullptr;
+    if (hipMalloc(&b->d_groups, sizeof(el::DueGroup) * groups.size()) != hipSuccess)
+        return fail(EL_EDEVICE, "hipMalloc of the batch group table failed");
+    if (hipMemcpy(b->d_groups, groups.data(), sizeof(el::DueGroup) * groups.size(), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return fail(EL_EDEVICE, "upload of the batch group table failed");
+    b->ngroups = (int)groups.size();
+    b->h_groups = groups;
     return EL_OK;
 }
 
 void free_batch(el_batch* b)
 {
     if (!b) return;
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (hipGraphExec_t e : b->execs) (void)hipGraphExecDestroy(e);
+    for (hipGraph_t g : b->graphs) (void)hipGraphDestroy(g);
     if (b->d_chan) (void)hipFree(b->d_chan);
     if (b->d_tiles_lbm) (void)hipFree(b->d_tiles_lbm);
     if (b->d_tiles_fd) (void)hipFree(b->d_tiles_fd);
+    if (b->d_groups) (void)hipFree(b->d_groups);
     if (b->d_t) (void)hipFree(b->d_t);
     delete b;
+}
+
+// Longest period (lcm of the channels' r) for which one graph per phase is captured.
+constexpr int MAX_PERIOD = 64;
+
+int period_of(const std::vector<el_params>& params)
+{
+    long long l = 1;
+    for (const el_params& p : params) {
+        long long a = l, c = p.fd_ratio;
+        while (c) {
+            const long long r = a % c;
+            a = c;
+            c = r;
+        }
+        l = l / a * p.fd_ratio;
+        if (l > MAX_PERIOD) return 0;
+    }
+    return (int)l;
 }
 
 template <typename T, bool SHIFT>
 int create_impl(el_batch* b, const el_batch_tuning* tuning, hipStream_t st)
 {
+    b->period = period_of(b->params);
     int rc = build_table<T>(b);
     if (rc != EL_OK) return rc;
     if (hipMalloc(&b->d_t, sizeof(int)) != hipSuccess) return fail(EL_EDEVICE, "hipMalloc of the step counter failed");
@@ -382,7 +500,7 @@ int create_impl(el_batch* b, const el_batch_tuning* tuning, hipStream_t st)
     long long total = 0;
     for (const el_params& p : b->params) total += geom_of(&p).N;
     const std::string key = std::to_string(b->precision) + "|" + arch_name() + "|" + std::to_string(ilog2(total)) +
-                            "|" + std::to_string(ilog2(b->nchan));
+                            "|" + std::to_string(ilog2(b->nchan)) + (b->period > 0 ? "|phased" : "|persistent");
     if (tuning) {
         if (!valid_tuning(*tuning)) return fail(EL_EINVAL, "invalid batch tuning");
         b->tuning = *tuning;
@@ -459,10 +577,11 @@ int el_batch_step(el_batch* b, int32_t nsteps, void* stream)
     if (nsteps < 0) return fail(EL_EINVAL, "nsteps = %d", nsteps);
     hipStream_t st = static_cast<hipStream_t>(stream);
     for (int i = 0; i < nsteps; ++i) {
-        if (b->exec) {
-            if (hipGraphLaunch(b->exec, st) != hipSuccess) return fail(EL_EDEVICE, "hipGraphLaunch failed");
+        if (!b->execs.empty()) {
+            const hipGraphExec_t e = b->execs[b->period > 0 ? (size_t)(b->h_t % b->period) : 0];
+            if (hipGraphLaunch(e, st) != hipSuccess) return fail(EL_EDEVICE, "hipGraphLaunch failed");
         } else {
-            int rc = dispatch_step(b, st);
+            int rc = dispatch_step(b, st, b->h_t);
             if (rc != EL_OK) return rc;
         }
         b->h_t += 1;
@@ -478,28 +597,28 @@ int el_batch_capture(el_batch* b, void* stream)
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
         return fail(EL_EINVAL, "the stream is already capturing");
-    if (b->exec) {
-        (void)hipGraphExecDestroy(b->exec);
-        b->exec = nullptr;
-    }
-    if (b->graph) {
-        (void)hipGraphDestroy(b->graph);
-        b->graph = nullptr;
-    }
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return fail(EL_EDEVICE, "hipStreamBeginCapture failed (is the stream already capturing?)");
-    const int rc = dispatch_step(b, st);
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(st, &g);
-    if (rc != EL_OK) {
-        if (g) (void)hipGraphDestroy(g);
-        return rc;
-    }
-    if (e != hipSuccess || !g) return fail(EL_EDEVICE, "hipStreamEndCapture failed");
-    b->graph = g;
-    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
-        b->exec = nullptr;
-        return fail(EL_EDEVICE, "hipGraphInstantiate failed");
+    for (hipGraphExec_t e : b->execs) (void)hipGraphExecDestroy(e);
+    for (hipGraph_t g : b->graphs) (void)hipGraphDestroy(g);
+    b->execs.clear();
+    b->graphs.clear();
+    // one graph per phase of the period (graph k replays steps t = k mod period)
+    const int ngraphs = b->period > 0 ? b->period : 1;
+    for (int k = 0; k < ngraphs; ++k) {
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(EL_EDEVICE, "hipStreamBeginCapture failed (is the stream already capturing?)");
+        const int rc = dispatch_step(b, st, k);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(st, &g);
+        if (rc != EL_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess || !g) return fail(EL_EDEVICE, "hipStreamEndCapture failed");
+        b->graphs.push_back(g);
+        hipGraphExec_t ex = nullptr;
+        if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess)
+            return fail(EL_EDEVICE, "hipGraphInstantiate failed");
+        b->execs.push_back(ex);
     }
     return EL_OK;
 }
@@ -510,10 +629,10 @@ int el_batch_moments(el_batch* b, void* stream)
     hipStream_t st = static_cast<hipStream_t>(stream);
     const el_batch_tuning& tu = b->tuning;
     switch (b->precision) {
-    case EL_F64: launch_moments<double, false>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, el::MOM_AFTER_PARTIAL); break;
-    case EL_F64_SHIFTED: launch_moments<double, true>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, el::MOM_AFTER_PARTIAL); break;
-    case EL_F32: launch_moments<float, false>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, el::MOM_AFTER_PARTIAL); break;
-    default: launch_moments<float, true>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, tu.fd_blocks_per_cu, el::MOM_AFTER_PARTIAL); break;
+    case EL_F64: launch_moments<double, false>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, b->ntiles_fd, el::MOM_AFTER_PARTIAL, 0); break;
+    case EL_F64_SHIFTED: launch_moments<double, true>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, b->ntiles_fd, el::MOM_AFTER_PARTIAL, 0); break;
+    case EL_F32: launch_moments<float, false>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, b->ntiles_fd, el::MOM_AFTER_PARTIAL, 0); break;
+    default: launch_moments<float, true>(b, st, b->d_tiles_fd, b->ntiles_fd, tu.fd_block, b->ntiles_fd, el::MOM_AFTER_PARTIAL, 0); break;
     }
     return check_launch("batched moments");
 }

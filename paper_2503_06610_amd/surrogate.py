@@ -224,7 +224,7 @@ def relax(lats, steps, capture=True):
     return change
 
 
-def generate_pairs(nsamples, seed=5, group=250, steps=4000, nx=64, ny=64, nz=32, log=print):
+def generate_pairs(nsamples, seed=5, group=200, steps=4000, nx=64, ny=64, nz=32, log=print):
     """Inputs (BF16 network input, all samples) and targets (FP32, one
     [3][group*N] block per group) from solver runs."""
     import torch
@@ -387,6 +387,8 @@ def main(argv=None):
     ap.add_argument("--relax-steps", type=int, default=4000)
     ap.add_argument("--eval-size", type=int, nargs=3, default=[512, 512, 64])
     ap.add_argument("--ref-steps", type=int, default=15000)
+    ap.add_argument("--no-study", action="store_true",
+                    help="train and time the forward pass, without the time-to-steady comparison")
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
@@ -407,7 +409,7 @@ def main(argv=None):
     log(f"forward on {prob.nx}x{prob.ny}x{prob.nz}: {ms:.2f} ms, {tflops:.1f} TFLOP/s algorithmic")
     del lat
     torch.cuda.empty_cache()
-    study = warm_start_study(net, prob, n0, ref_steps=args.ref_steps, log=log)
+    study = None if args.no_study else warm_start_study(net, prob, n0, ref_steps=args.ref_steps, log=log)
     res = {"train": {"samples": args.samples, "epochs": args.epochs, "batch": args.batch,
                      "generation_s": round(t_gen, 1), "max_last100_change": max_change,
                      "train_s": round(t_train, 1), "loss_first": hist[0], "loss_last": hist[-1], "loss": hist},

@@ -66,6 +66,38 @@ def test_batch_channels_bitwise_equal_single_runs(precision):
             assert np.array_equal(fa[k], fs[k]), (precision, i, k)
 
 
+def test_batch_of_channels_at_different_steps():
+    """Channels that have already taken different numbers of steps (so their
+    FD updates fall on different batched steps) still match single runs."""
+    import torch
+    chans = _small_batch()
+    pre = [0, 3, 7, 1, 4, 2]
+    T = 17
+    singles = _lattices(chans, "f32_shifted")
+    for lat, k in zip(singles, pre):
+        lat.run(k + T)
+    lats = _lattices(chans, "f32_shifted")
+    for lat, k in zip(lats, pre):
+        lat.run(k)
+    for tuning in (None, (256, 0, 128, 0), (128, 4, 256, 2)):
+        if tuning is not None:
+            lats = _lattices(chans, "f32_shifted")
+            for lat, k in zip(lats, pre):
+                lat.run(k)
+        b = el.Batch(lats, tuning=tuning)
+        b.capture()
+        b.step(T)
+        b.moments()
+        b.sync()
+        torch.cuda.synchronize()
+        for i, (a, s) in enumerate(zip(lats, singles)):
+            assert a.step == s.step == pre[i] + T
+            fa, fs = _fields(a), _fields(s)
+            for k in fa:
+                assert np.array_equal(fa[k], fs[k]), (tuning, i, k)
+        b.close()
+
+
 def test_graph_replay_equals_eager_with_interleaved_work():
     import torch
     chans = _small_batch()
@@ -95,18 +127,20 @@ def test_autotuned_shapes_give_identical_results():
     chans = _small_batch()
     tuned = el.Batch(_lattices(chans, "f32_shifted"))
     fixed = el.Batch(_lattices(chans, "f32_shifted"), tuning=(512, 2, 64, 16))
+    per_tile = el.Batch(_lattices(chans, "f32_shifted"), tuning=(256, 0, 128, 0))  # one block per tile
     t = tuned.tuning()
     assert t["tuned"] in (1, 2)
     assert t["lbm_block"] in (128, 256, 512, 1024) and t["fd_block"] in (128, 256, 512)
-    for bt in (tuned, fixed):
+    for bt in (tuned, fixed, per_tile):
         bt.step(11)
         bt.moments()
         bt.sync()
     torch.cuda.synchronize()
-    for a, f in zip(tuned.lattices, fixed.lattices):
-        fa, ff = _fields(a), _fields(f)
-        for k in fa:
-            assert np.array_equal(fa[k], ff[k]), k
+    for other in (fixed, per_tile):
+        for a, f in zip(tuned.lattices, other.lattices):
+            fa, ff = _fields(a), _fields(f)
+            for k in fa:
+                assert np.array_equal(fa[k], ff[k]), k
     # a second batch of the same shape class takes the cached choice
     again = el.Batch(_lattices(chans, "f32_shifted"))
     assert again.tuning()["tuned"] == 2
