@@ -1,6 +1,8 @@
 // nn.hip -- C ABI of the warm-start surrogate: network input from the
 // director, BF16-MFMA convolutions (forward, backward-data, backward-weight),
 // MSE loss, Adam, and the velocity the flow is initialised from.
+#include <algorithm>
+
 #include "host_common.hpp"
 #include "nn_kernels.hpp"
 
@@ -8,7 +10,7 @@ namespace {
 using namespace elh;
 using el::nn::VolGeom;
 
-constexpr int NN_CHUNK = 2048;  // voxels per block in the weight-gradient reduction
+constexpr int NN_CHUNK = 1024;  // voxels per block in the weight-gradient reduction
 
 int vol_of(const el_nn_vol* v, VolGeom* g)
 {
@@ -26,7 +28,42 @@ int vol_of(const el_nn_vol* v, VolGeom* g)
     return EL_OK;
 }
 
-int conv_blocks(const VolGeom& g) { return (int)((g.n_all + 63) / 64); }
+// Persistent grid of the convolution kernels: two blocks of CONV_THREADS
+// per compute unit (their weight copies fit the LDS), fewer for small volumes.
+int conv_blocks(const VolGeom& g)
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    }
+    const long long items = (g.n_all + 16 * el::nn::CONV_MT - 1) / (16 * el::nn::CONV_MT);
+    const long long need = (items + el::nn::CONV_THREADS / 64 - 1) / (el::nn::CONV_THREADS / 64);
+    return (int)std::max(1LL, std::min(need, 2LL * cus));
+}
+
+template <int CIN, int NT, bool RELU, bool SOA>
+void launch_conv(const VolGeom& g, hipStream_t st, const __bf16* x, const __bf16* w, const float* bias,
+                 const __bf16* mask, void* y, int cout_store)
+{
+    constexpr int lds = el::nn::conv_lds_bytes(CIN, NT);
+    hipLaunchKernelGGL((el::nn::k_conv<CIN, NT, RELU, SOA>), dim3(conv_blocks(g)), dim3(el::nn::CONV_THREADS), lds, st,
+                       x, w, bias, mask, y, g, cout_store);
+}
+
+template <int CIN, int MT>
+void launch_wgrad(const VolGeom& g, hipStream_t st, int nb, const __bf16* x, const __bf16* dy, float* part)
+{
+    constexpr int lds = el::nn::wgrad_lds_bytes(CIN, 16 * MT);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&el::nn::k_conv_wgrad<CIN, MT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        attr = true;
+    }
+    hipLaunchKernelGGL((el::nn::k_conv_wgrad<CIN, MT>), dim3(nb), dim3(256), lds, st, x, dy, part, g, NN_CHUNK);
+}
 
 int wgrad_blocks(const VolGeom& g) { return (int)((g.n_all + NN_CHUNK - 1) / NN_CHUNK); }
 
@@ -72,25 +109,24 @@ int el_nn_conv_forward(const el_nn_vol* vol, int32_t cin, int32_t cout, const vo
     if (rc != EL_OK) return rc;
     if (!x || !w || !y) return fail(EL_EINVAL, "NULL pointer");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const dim3 grid(conv_blocks(g)), block(256);
     const __bf16* X = static_cast<const __bf16*>(x);
     const __bf16* W = static_cast<const __bf16*>(w);
     if (cout == 3) {
         if (relu) return fail(EL_EINVAL, "the FP32 output layer has no activation");
         if (cin == 32)
-            hipLaunchKernelGGL((el::nn::k_conv<32, 1, false, true>), grid, block, 0, st, X, W, bias, nullptr, y, g, 3);
+            launch_conv<32, 1, false, true>(g, st, X, W, bias, nullptr, y, 3);
         else
             return fail(EL_EINVAL, "output layer needs cin = 32");
     } else if (cout == 32 && cin == 8) {
         if (relu)
-            hipLaunchKernelGGL((el::nn::k_conv<8, 2, true, false>), grid, block, 0, st, X, W, bias, nullptr, y, g, 32);
+            launch_conv<8, 2, true, false>(g, st, X, W, bias, nullptr, y, 32);
         else
-            hipLaunchKernelGGL((el::nn::k_conv<8, 2, false, false>), grid, block, 0, st, X, W, bias, nullptr, y, g, 32);
+            launch_conv<8, 2, false, false>(g, st, X, W, bias, nullptr, y, 32);
     } else if (cout == 32 && cin == 32) {
         if (relu)
-            hipLaunchKernelGGL((el::nn::k_conv<32, 2, true, false>), grid, block, 0, st, X, W, bias, nullptr, y, g, 32);
+            launch_conv<32, 2, true, false>(g, st, X, W, bias, nullptr, y, 32);
         else
-            hipLaunchKernelGGL((el::nn::k_conv<32, 2, false, false>), grid, block, 0, st, X, W, bias, nullptr, y, g, 32);
+            launch_conv<32, 2, false, false>(g, st, X, W, bias, nullptr, y, 32);
     } else {
         return fail(EL_EINVAL, "unsupported conv %d -> %d", cin, cout);
     }
@@ -106,14 +142,13 @@ int el_nn_conv_backward_data(const el_nn_vol* vol, int32_t cin, int32_t cout, co
     if (!dy || !wt || !dx) return fail(EL_EINVAL, "NULL pointer");
     if (cin != 32) return fail(EL_EINVAL, "backward-data is computed for cin = 32 layers only");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const dim3 grid(conv_blocks(g)), block(256);
     const __bf16* DY = static_cast<const __bf16*>(dy);
     const __bf16* WT = static_cast<const __bf16*>(wt);
     const __bf16* M = static_cast<const __bf16*>(mask);
     if (cout == 32)
-        hipLaunchKernelGGL((el::nn::k_conv<32, 2, false, false>), grid, block, 0, st, DY, WT, nullptr, M, dx, g, 32);
+        launch_conv<32, 2, false, false>(g, st, DY, WT, nullptr, M, dx, 32);
     else if (cout == 16)
-        hipLaunchKernelGGL((el::nn::k_conv<16, 2, false, false>), grid, block, 0, st, DY, WT, nullptr, M, dx, g, 32);
+        launch_conv<16, 2, false, false>(g, st, DY, WT, nullptr, M, dx, 32);
     else
         return fail(EL_EINVAL, "unsupported backward-data cout = %d", cout);
     return check_launch("k_conv backward-data");
@@ -141,21 +176,21 @@ int el_nn_conv_backward_weight(const el_nn_vol* vol, int32_t cin, int32_t cout, 
     const __bf16* X = static_cast<const __bf16*>(x);
     const __bf16* DY = static_cast<const __bf16*>(dy);
     if (cin == 8 && cout == 32) {
-        hipLaunchKernelGGL((el::nn::k_conv_wgrad<8, 2>), dim3(nb), dim3(256), 0, st, X, DY, part, g, NN_CHUNK);
+        launch_wgrad<8, 2>(g, st, nb, X, DY, part);
         hipLaunchKernelGGL((el::nn::k_bias_grad<32>), dim3(nb), dim3(256), 0, st, DY, bpart, g, NN_CHUNK);
     } else if (cin == 32 && cout == 32) {
-        hipLaunchKernelGGL((el::nn::k_conv_wgrad<32, 2>), dim3(nb), dim3(256), 0, st, X, DY, part, g, NN_CHUNK);
+        launch_wgrad<32, 2>(g, st, nb, X, DY, part);
         hipLaunchKernelGGL((el::nn::k_bias_grad<32>), dim3(nb), dim3(256), 0, st, DY, bpart, g, NN_CHUNK);
     } else if (cin == 32 && cout == 16) {
-        hipLaunchKernelGGL((el::nn::k_conv_wgrad<32, 1>), dim3(nb), dim3(256), 0, st, X, DY, part, g, NN_CHUNK);
+        launch_wgrad<32, 1>(g, st, nb, X, DY, part);
         hipLaunchKernelGGL((el::nn::k_bias_grad<16>), dim3(nb), dim3(256), 0, st, DY, bpart, g, NN_CHUNK);
     } else {
         return fail(EL_EINVAL, "unsupported weight gradient %d -> %d", cin, cout);
     }
     const int nw = cout * 27 * cin;
-    hipLaunchKernelGGL(el::nn::k_sum_partials, dim3((nw + 255) / 256), dim3(256), 0, st,
+    hipLaunchKernelGGL(el::nn::k_sum_partials, dim3((nw + 15) / 16), dim3(256), 0, st,
                        static_cast<const float*>(part), nb, cout, pitch_of(cin), 27 * cin, dw);
-    hipLaunchKernelGGL(el::nn::k_sum_partials, dim3(1), dim3(256), 0, st, static_cast<const float*>(bpart), nb, 1,
+    hipLaunchKernelGGL(el::nn::k_sum_partials, dim3((cout + 15) / 16), dim3(256), 0, st, static_cast<const float*>(bpart), nb, 1,
                        cout, cout, db);
     return check_launch("weight-gradient kernels");
 }

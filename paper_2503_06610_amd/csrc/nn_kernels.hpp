@@ -28,24 +28,6 @@ struct VolGeom {
     long long n_all;   // n_int * nsamples
 };
 
-// Halo'd linear index of interior voxel v (over all samples) shifted by a tap.
-__device__ __forceinline__ long long tap_index(const VolGeom& g, long long v, int dz, int dy, int dx)
-{
-    const int s = (int)(v / g.n_int);
-    const int r = (int)(v - (long long)s * g.n_int);
-    const int x = r % g.nx;
-    const int t = r / g.nx;
-    const int y = t % g.ny;
-    const int z = t / g.ny;
-    int xn = x + dx;
-    xn = xn < 0 ? xn + g.nx : (xn >= g.nx ? xn - g.nx : xn);
-    int yn = y + dy;
-    yn = yn < 0 ? yn + g.ny : (yn >= g.ny ? yn - g.ny : yn);
-    const int zn = z + dz + 1;  // halo planes at 0 and nzf + 1
-    const long long plane = (long long)g.nx * g.ny;
-    return (long long)s * plane * (g.nzf + 2) + zn * plane + (long long)yn * g.nx + xn;
-}
-
 __device__ __forceinline__ long long own_index(const VolGeom& g, long long v)
 {
     const int s = (int)(v / g.n_int);
@@ -53,85 +35,186 @@ __device__ __forceinline__ long long own_index(const VolGeom& g, long long v)
     return v + (long long)s * 2 * plane + plane;
 }
 
-__device__ __forceinline__ void tap_offsets(int tap, int& dz, int& dy, int& dx)
+// Position of one voxel (linear index over all samples): its sample's
+// halo'd base index and x, y, z.
+struct VoxPos {
+    long long sbase;
+    int x, y, z;
+};
+
+__device__ __forceinline__ VoxPos vox_pos(const VolGeom& g, long long v)
 {
-    dz = tap / 9 - 1;
-    dy = (tap / 3) % 3 - 1;
-    dx = tap % 3 - 1;
+    const int s = (int)(v / g.n_int);
+    const int r = (int)(v - (long long)s * g.n_int);
+    VoxPos p;
+    p.x = r % g.nx;
+    const int t = r / g.nx;
+    p.y = t % g.ny;
+    p.z = t / g.ny;
+    p.sbase = (long long)s * g.nx * g.ny * (g.nzf + 2);
+    return p;
 }
 
-// y = act(conv(x, w) + bias) [* (mask > 0)], one wave per 16 output voxels.
+// Halo'd linear index of the voxel at p shifted by (dx, dy, dz); x, y periodic.
+__device__ __forceinline__ long long vox_shift(const VolGeom& g, const VoxPos& p, int dz, int dy, int dx)
+{
+    int xn = p.x + dx;
+    xn = xn < 0 ? xn + g.nx : (xn >= g.nx ? xn - g.nx : xn);
+    int yn = p.y + dy;
+    yn = yn < 0 ? yn + g.ny : (yn >= g.ny ? yn - g.ny : yn);
+    return p.sbase + ((long long)(p.z + dz + 1) * g.ny + yn) * g.nx + xn;
+}
+
+// Threads per block of the convolution kernels, and 16-voxel M tiles per
+// wave work item (a B fragment is reused for all of them).
+constexpr int CONV_THREADS = 512;
+constexpr int CONV_MT = 4;
+
+// k-steps (of 32) of a layer with CIN input channels: one tap x 32 channels,
+// or 4/(CIN/8) taps x CIN channels.
+__host__ __device__ constexpr int conv_steps(int cin) { return (27 + 4 / (cin / 8) - 1) / (4 / (cin / 8)); }
+
+// LDS bytes of k_conv: the B fragments of every k-step, k-group and column.
+__host__ __device__ constexpr int conv_lds_bytes(int cin, int nt) { return conv_steps(cin) * 4 * 16 * nt * 16; }
+
+// y = act(conv(x, w) + bias) [* (mask > 0)].  Persistent blocks: the layer's
+// weights are staged once per block into LDS in B-fragment order
+// ([k-step][k-group][output channel], 16 bytes each), then each wave takes
+// work items of CONV_MT x 16 voxels x all output channels; per k-step it
+// loads one A fragment per M tile from the activations (16 voxels x 8
+// channels of one tap per k-group, 16 contiguous bytes per lane) and one B
+// fragment per N tile from LDS, and issues CONV_MT x NT MFMAs.
 // CIN in {8, 16, 32}; NT = output channels / 16 (COUT = 16 NT stored).
 // OUT_SOA: write FP32 channel-major y[co * n_all + v] for co < cout_store
 // (no halo) instead of channels-last BF16.
 template <int CIN, int NT, bool RELU, bool OUT_SOA>
-__global__ void __launch_bounds__(256) k_conv(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
-                                             const float* __restrict__ bias, const __bf16* __restrict__ mask,
-                                             void* __restrict__ y, VolGeom g, int cout_store)
+__global__ void __launch_bounds__(CONV_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_conv(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
+                                                      const float* __restrict__ bias, const __bf16* __restrict__ mask,
+                                                      void* __restrict__ y, VolGeom g, int cout_store)
 {
     constexpr int GPT = CIN / 8;          // k-groups per tap
     constexpr int TPM = 4 / GPT;          // taps per MFMA (k = 32 per MFMA)
-    constexpr int NSTEP = (27 + TPM - 1) / TPM;
+    constexpr int NSTEP = conv_steps(CIN);
     constexpr int KTOT = 27 * CIN;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const long long base = ((long long)blockIdx.x * 4 + wave) * 16;
-    if (base >= g.n_all) return;
-    const int m = lane & 15;
-    const int grp = lane >> 4;
-    long long v = base + m;
-    if (v >= g.n_all) v = g.n_all - 1;
+    constexpr int COUT = 16 * NT;
+    constexpr int MT = CONV_MT;
+    extern __shared__ bf16x8 wl[];
 
-    f32x4 acc[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    for (int s = 0; s < NSTEP; ++s) {
+    for (int i = threadIdx.x; i < NSTEP * 4 * COUT; i += blockDim.x) {
+        const int co = i % COUT;
+        const int grp = (i / COUT) % 4;
+        const int s = i / (4 * COUT);
         const int tap = s * TPM + grp / GPT;
         const int c0 = 8 * (grp % GPT);
-        bf16x8 a;
-        bf16x8 b[NT];
+        bf16x8 v;
         if (tap < 27) {
-            int dz, dy, dx;
-            tap_offsets(tap, dz, dy, dx);
-            a = *reinterpret_cast<const bf16x8*>(x + tap_index(g, v, dz, dy, dx) * CIN + c0);
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                b[nt] = *reinterpret_cast<const bf16x8*>(w + (long long)(nt * 16 + m) * KTOT + tap * CIN + c0);
+            v = *reinterpret_cast<const bf16x8*>(w + (long long)co * KTOT + tap * CIN + c0);
         } else {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) a[i] = (__bf16)0.0f;
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) b[nt] = a;
+            for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.0f;
         }
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nt], acc[nt], 0, 0, 0);
+        wl[i] = v;
     }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwave = blockDim.x >> 6;
+    const int m = lane & 15;
+    const int grp = lane >> 4;
+    const long long nitem = (g.n_all + 16 * MT - 1) / (16 * MT);
+    for (long long it = (long long)blockIdx.x * nwave + wave; it < nitem; it += (long long)gridDim.x * nwave) {
+        const long long base = it * 16 * MT;
+        VoxPos pos[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            long long v = base + mt * 16 + m;
+            if (v >= g.n_all) v = g.n_all - 1;
+            pos[mt] = vox_pos(g, v);
+        }
+        f32x4 acc[MT][NT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+        // A fragments of k-step s (16 voxels x 8 channels of one tap per lane group)
+        auto load_a = [&](int s, bf16x8 (&a)[MT]) {
+            const int tap = s * TPM + grp / GPT;
+            const int c0 = 8 * (grp % GPT);
+            if (tap < 27) {
+                const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    a[mt] = *reinterpret_cast<const bf16x8*>(x + vox_shift(g, pos[mt], dz, dy, dx) * CIN + c0);
+            } else {
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) a[mt][j] = (__bf16)0.0f;
+            }
+        };
+        // the loads of step s + 1 are in flight while step s multiplies
+        bf16x8 a[MT], an[MT];
+        load_a(0, a);
+        for (int s = 0; s < NSTEP; ++s) {
+            if (s + 1 < NSTEP) load_a(s + 1, an);
+            bf16x8 b[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) b[nt] = wl[(s * 4 + grp) * COUT + nt * 16 + m];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) a[mt] = an[mt];
+        }
 
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int co = nt * 16 + m;
+        for (int mt = 0; mt < MT; ++mt) {
+            const long long bm = base + mt * 16;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const long long vv = base + 4 * grp + j;
-            if (vv >= g.n_all) continue;
-            float val = acc[nt][j] + (bias ? bias[co] : 0.0f);
-            if (RELU) val = fmaxf(val, 0.0f);
-            if (OUT_SOA) {
-                if (co < cout_store) static_cast<float*>(y)[(long long)co * g.n_all + vv] = val;
-            } else {
-                const long long oi = own_index(g, vv) * (16 * NT) + co;
-                if (mask && !((float)mask[oi] > 0.0f)) val = 0.0f;
-                static_cast<__bf16*>(y)[oi] = (__bf16)val;
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = nt * 16 + m;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const long long vv = bm + 4 * grp + j;
+                    if (vv >= g.n_all) continue;
+                    float val = acc[mt][nt][j] + (bias ? bias[co] : 0.0f);
+                    if (RELU) val = fmaxf(val, 0.0f);
+                    if (OUT_SOA) {
+                        if (co < cout_store) static_cast<float*>(y)[(long long)co * g.n_all + vv] = val;
+                    } else {
+                        const long long oi = own_index(g, vv) * COUT + co;
+                        if (mask && !((float)mask[oi] > 0.0f)) val = 0.0f;
+                        static_cast<__bf16*>(y)[oi] = (__bf16)val;
+                    }
+                }
             }
         }
     }
 }
 
+// Padded LDS row of the weight-gradient kernel: 32 voxels + 8 (80 bytes, so
+// the 16 rows read by a quarter-wave fall in distinct banks).
+constexpr int WG_ROW = 40;
+
+// LDS bytes of k_conv_wgrad: x^T [(tap, ci) rows padded to 16][WG_ROW] and
+// dy^T [co][WG_ROW].
+__host__ __device__ constexpr int wgrad_lds_bytes(int cin, int cout)
+{
+    return (((27 * cin + 15) / 16) * 16 + cout) * WG_ROW * 2;
+}
+
 // Partial weight gradients dW[co][tap][ci] = sum_v dy[v][co] x[v + d_tap][ci]
-// over a chunk of voxels per block: M = output channels (MT tiles of 16),
-// N = 27 CIN (tap, ci) columns padded to whole 16-column tiles, K = voxels.
-// Each block writes its partial tile rows to part[block][co][col].
+// over a chunk of voxels per block, as a GEMM with M = output channels (MT
+// tiles of 16), N = 27 CIN (tap, ci) columns padded to whole 16-column tiles,
+// K = voxels.  Per k-step of 32 voxels the block stages dy and the 27
+// shifted copies of x transposed into LDS (voxels along a row, so an MFMA
+// fragment is 16 contiguous bytes), then each wave multiplies its column
+// tiles (every 4th) with all M tiles.  Each block writes its partial rows to
+// part[block][co][col].
 template <int CIN, int MT>
 __global__ void __launch_bounds__(256) k_conv_wgrad(const __bf16* __restrict__ x, const __bf16* __restrict__ dy,
                                                    float* __restrict__ part, VolGeom g, int chunk)
@@ -139,56 +222,124 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const __bf16* __restrict__ x
     constexpr int COUT = 16 * MT;
     constexpr int NCOL = 27 * CIN;
     constexpr int NTT = (NCOL + 15) / 16;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    constexpr int NTW = (NTT + 3) / 4;
+    constexpr int GPC = CIN / 8;
+    extern __shared__ __bf16 wg_lds[];
+    __bf16* xs = wg_lds;                         // [NTT * 16][WG_ROW]
+    __bf16* ds = wg_lds + NTT * 16 * WG_ROW;     // [COUT][WG_ROW]
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     const int m = lane & 15;
     const int grp = lane >> 4;
     const long long v0 = (long long)blockIdx.x * chunk;
     long long v1 = v0 + chunk;
     if (v1 > g.n_all) v1 = g.n_all;
-    float* out = part + (long long)blockIdx.x * COUT * (16 * NTT);
-    for (int tile = wave; tile < MT * NTT; tile += 4) {
-        const int mt = tile / NTT;
-        const int nt = tile % NTT;
-        const int co = mt * 16 + m;
-        const int col = nt * 16 + m;
-        const int tap = col / CIN;
-        const int ci = col % CIN;
-        int dz = 0, dy_ = 0, dx = 0;
-        if (tap < 27) tap_offsets(tap, dz, dy_, dx);
-        f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (long long kb = v0; kb < v1; kb += 32) {
-            bf16x8 a, b;
+    // padding rows of x^T (27 CIN .. 16 NTT) stay zero
+    for (int i = tid; i < (NTT * 16 - NCOL) * WG_ROW; i += blockDim.x) xs[NCOL * WG_ROW + i] = (__bf16)0.0f;
+
+    f32x4 acc[NTW][MT];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const long long v = kb + 8 * grp + i;
-                const bool ok = v < v1;
-                a[i] = ok ? dy[own_index(g, v) * COUT + co] : (__bf16)0.0f;
-                b[i] = (ok && tap < 27) ? x[tap_index(g, v, dz, dy_, dx) * CIN + ci] : (__bf16)0.0f;
+    for (int j = 0; j < NTW; ++j)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[j][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int vp = tid % 16;  // the voxel pair this thread stages
+    for (long long kb = v0; kb < v1; kb += 32) {
+        const long long va = kb + 2 * vp, vb = va + 1;
+        const bool oka = va < v1, okb = vb < v1;
+        const VoxPos pa = vox_pos(g, oka ? va : v0);
+        const VoxPos pb = vox_pos(g, okb ? vb : v0);
+        if (tid < 16 * (COUT / 8)) {
+            const int cc = tid / 16;
+            bf16x8 da, db;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) da[j] = db[j] = (__bf16)0.0f;
+            if (oka) da = *reinterpret_cast<const bf16x8*>(dy + vox_shift(g, pa, 0, 0, 0) * COUT + 8 * cc);
+            if (okb) db = *reinterpret_cast<const bf16x8*>(dy + vox_shift(g, pb, 0, 0, 0) * COUT + 8 * cc);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                __bf16* d = ds + (8 * cc + j) * WG_ROW + 2 * vp;
+                d[0] = da[j];
+                d[1] = db[j];
             }
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
         }
-        // D[row = co tile row 4 grp + j][col = m]
+        for (int u = tid; u < 16 * 27 * GPC; u += blockDim.x) {
+            const int rest = u / 16;
+            const int cc = rest % GPC;
+            const int tap = rest / GPC;
+            const int dz = tap / 9 - 1, dyy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            bf16x8 xa, xb;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = mt * 16 + 4 * grp + j;
-            out[(long long)r * (16 * NTT) + nt * 16 + m] = acc[j];
+            for (int j = 0; j < 8; ++j) xa[j] = xb[j] = (__bf16)0.0f;
+            if (oka) xa = *reinterpret_cast<const bf16x8*>(x + vox_shift(g, pa, dz, dyy, dx) * CIN + 8 * cc);
+            if (okb) xb = *reinterpret_cast<const bf16x8*>(x + vox_shift(g, pb, dz, dyy, dx) * CIN + 8 * cc);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                __bf16* d = xs + (tap * CIN + 8 * cc + j) * WG_ROW + 2 * vp;
+                d[0] = xa[j];
+                d[1] = xb[j];
+            }
         }
+        __syncthreads();
+        bf16x8 a[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) a[mt] = *reinterpret_cast<const bf16x8*>(ds + (mt * 16 + m) * WG_ROW + 8 * grp);
+#pragma unroll
+        for (int j = 0; j < NTW; ++j) {
+            const int nt = wave + 4 * j;
+            if (nt < NTT) {
+                const bf16x8 b = *reinterpret_cast<const bf16x8*>(xs + (nt * 16 + m) * WG_ROW + 8 * grp);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[j][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[j][mt], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // D[row = co = 16 mt + 4 grp + r][col = 16 nt + m]
+    float* out = part + (long long)blockIdx.x * COUT * (16 * NTT);
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
+        const int nt = wave + 4 * j;
+        if (nt >= NTT) continue;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[(long long)(mt * 16 + 4 * grp + r) * (16 * NTT) + nt * 16 + m] = acc[j][mt][r];
     }
 }
 
-// Sums nblocks partial rows in block order: out[i] = sum_b part[b][i], for the
-// first `ncols` of each padded row of width `pitch` (drops the padding).
+// Sums nblocks partial rows: out[i] = sum_b part[b][i] over the first
+// `ncols` of each padded row of width `pitch` (drops the padding).  A block
+// covers 16 outputs with SUM_Q threads each; thread q adds the partials
+// b = q, q + SUM_Q, ... in order, and the SUM_Q sums are added in q order,
+// so the result does not depend on timing.
+constexpr int SUM_Q = 16;
+
 static __global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ part, int nblocks, int rows,
                                                      int pitch, int ncols, float* __restrict__ out)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rows * ncols) return;
-    const int r = i / ncols;
-    const int c = i % ncols;
+    __shared__ float red[SUM_Q][16];
+    const int e = threadIdx.x % 16;
+    const int q = threadIdx.x / 16;
+    const int i = blockIdx.x * 16 + e;
+    const bool ok = i < rows * ncols;
     float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += part[((long long)b * rows + r) * pitch + c];
-    out[i] = s;
+    if (ok) {
+        const int r = i / ncols;
+        const int c = i % ncols;
+        for (int b = q; b < nblocks; b += SUM_Q) s += part[((long long)b * rows + r) * pitch + c];
+    }
+    red[q][e] = s;
+    __syncthreads();
+    if (q == 0 && ok) {
+        float tot = 0.0f;
+        for (int k = 0; k < SUM_Q; ++k) tot += red[k][e];
+        out[i] = tot;
+    }
 }
 
 // Bias gradient partials: part[block][co] = sum over the block's chunk of dy[v][co].
