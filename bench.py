@@ -236,7 +236,7 @@ def main():
             traffic = entry.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": ("k_lbm_push_row" if prob.nx % 64 == 0 and prob.nx <= 1024 else "k_lbm_push")
+                "kernel": ("k_lbm_push_row" if prob.nx <= 1024 else "k_lbm_push")
                           + "<float, shifted>", "bytes_per_launch": bytes_per_launch,
                 "avg_launch_us": round(lbm_s * 1e6, 3)}
     # whole-step algorithmic bytes s*(41 + 15/r) per fluid-node update

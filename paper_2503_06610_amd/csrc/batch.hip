@@ -83,6 +83,21 @@ __global__ void __launch_bounds__(1024) k_batch_lbm(const ChanDesc<T>* __restric
     }
 }
 
+// Row tiles: tile = (channel, first row); the block handles
+// R = blockDim / nx whole rows of the channel (every channel has nx <= blockDim).
+template <typename T, bool SHIFT>
+__global__ void __launch_bounds__(1024) k_batch_lbm_rows(const ChanDesc<T>* __restrict__ ch,
+                                                        const int2* __restrict__ tiles, const int* __restrict__ tdev)
+{
+    extern __shared__ unsigned char lbm_smem[];
+    const int t = *tdev;
+    const int2 tl = tiles[blockIdx.x];
+    const ChanDesc<T>& c = ch[tl.x];
+    const int R = max(1, (int)blockDim.x / c.lbm.g.nx);
+    const int par = c.parity0 ^ (t & 1);
+    lbm_rows<T, SHIFT>(c.q[par], c.q[par ^ 1], c.F, c.lbm, tl.y, R, reinterpret_cast<T*>(lbm_smem));
+}
+
 // Which channels a moments launch covers.
 enum { MOM_DUE_IN_STEP = 0, MOM_ALL = 1, MOM_AFTER_PARTIAL = 2 };
 
@@ -173,6 +188,7 @@ struct el_batch {
     long long h_t = 0;
     int cus = 0;
     el_batch_tuning tuning{};
+    bool lbm_rows = false;  // LBM tiles are row tiles (one block per tile, whole rows)
     std::vector<el::DueGroup> h_groups;  // host copy of the group table
     int period = 0;  // lcm of the channels' r when <= MAX_PERIOD (one graph per phase), else 0
     std::vector<hipGraph_t> graphs;
@@ -184,6 +200,26 @@ using namespace elh;
 
 std::mutex g_tune_mu;
 std::map<std::string, el_batch_tuning> g_tune_cache;
+
+// Row tiles of blockDim `block` threads: R = block / nx rows per tile.
+std::vector<int2> make_row_tiles(const std::vector<el_params>& params, int block)
+{
+    std::vector<int2> tiles;
+    for (size_t c = 0; c < params.size(); ++c) {
+        const el::Geom g = geom_of(&params[c]);
+        const int R = std::max(1, block / g.nx);
+        for (int r = 0; r < g.ny * g.nzf; r += R) tiles.push_back(make_int2((int)c, r));
+    }
+    return tiles;
+}
+
+// Whether the row kernel can take every channel with `block` threads.
+bool rows_fit(const std::vector<el_params>& params, int block, size_t value_bytes)
+{
+    for (const el_params& p : params)
+        if (p.nx > block) return false;
+    return 10 * (size_t)block * value_bytes <= 65536;
+}
 
 std::vector<int2> make_tiles(const std::vector<el_params>& params, int tile)
 {
@@ -264,11 +300,16 @@ int build_table(el_batch* b)
 // bpc == 0: one block per tile; otherwise a persistent grid of cus * bpc blocks.
 int grid_of(int ntiles, int cus, int bpc) { return std::max(1, bpc == 0 ? ntiles : std::min(ntiles, cus * bpc)); }
 
+// rows: tiles are row tiles and the row kernel runs (one block per tile).
 template <typename T, bool SHIFT>
-void launch_lbm(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int block, int bpc)
+void launch_lbm(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int block, int bpc, bool rows)
 {
-    hipLaunchKernelGGL((el::k_batch_lbm<T, SHIFT>), dim3(grid_of(ntiles, b->cus, bpc)), dim3(block), 0, st,
-                       static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles, b->d_t);
+    if (rows)
+        hipLaunchKernelGGL((el::k_batch_lbm_rows<T, SHIFT>), dim3(ntiles), dim3(block), 10 * (size_t)block * sizeof(T),
+                           st, static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, b->d_t);
+    else
+        hipLaunchKernelGGL((el::k_batch_lbm<T, SHIFT>), dim3(grid_of(ntiles, b->cus, bpc)), dim3(block), 0, st,
+                           static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles, b->d_t);
 }
 
 template <typename T, bool SHIFT>
@@ -306,7 +347,7 @@ template <typename T, bool SHIFT>
 int enqueue_step(el_batch* b, hipStream_t st, long long t)
 {
     const el_batch_tuning& tu = b->tuning;
-    launch_lbm<T, SHIFT>(b, st, b->d_tiles_lbm, b->ntiles_lbm, tu.lbm_block, tu.lbm_blocks_per_cu);
+    launch_lbm<T, SHIFT>(b, st, b->d_tiles_lbm, b->ntiles_lbm, tu.lbm_block, tu.lbm_blocks_per_cu, b->lbm_rows);
     int grid = 0;
     if (b->period > 0)
         grid = due_tiles_host(b, t);
@@ -386,12 +427,16 @@ int autotune(el_batch* b, hipStream_t st)
     el_batch_tuning tu = b->tuning;
     int2* dt = nullptr;
     for (int blk : lbm_blocks) {
-        const std::vector<int2> tiles = make_tiles(b->params, blk);
-        int rc = upload_tiles(tiles, &dt);
-        if (rc != EL_OK) return rc;
+        const bool rows = rows_fit(b->params, blk, sizeof(T));
         for (int bpc : bpcs) {
             if (bpc * blk > 16 * 1024) continue;
-            const float ms = time_launches(st, [&] { launch_lbm<T, SHIFT>(b, st, dt, (int)tiles.size(), blk, bpc); });
+            // one block per tile: row tiles when every row fits the block
+            const bool use_rows = rows && bpc == 0;
+            const std::vector<int2> tiles = use_rows ? make_row_tiles(b->params, blk) : make_tiles(b->params, blk);
+            int rc = upload_tiles(tiles, &dt);
+            if (rc != EL_OK) return rc;
+            const float ms =
+                time_launches(st, [&] { launch_lbm<T, SHIFT>(b, st, dt, (int)tiles.size(), blk, bpc, use_rows); });
             if (ms < best) {
                 best = ms;
                 tu.lbm_block = blk;
@@ -434,9 +479,11 @@ int valid_tuning(const el_batch_tuning& t)
            t.lbm_blocks_per_cu <= 64 && t.fd_blocks_per_cu <= 64;
 }
 
-int build_tiles(el_batch* b)
+int build_tiles(el_batch* b, size_t value_bytes)
 {
-    const std::vector<int2> lt = make_tiles(b->params, b->tuning.lbm_block);
+    b->lbm_rows = b->tuning.lbm_blocks_per_cu == 0 && rows_fit(b->params, b->tuning.lbm_block, value_bytes);
+    const std::vector<int2> lt = b->lbm_rows ? make_row_tiles(b->params, b->tuning.lbm_block)
+                                             : make_tiles(b->params, b->tuning.lbm_block);
     int rc = upload_tiles(lt, &b->d_tiles_lbm);
     if (rc != EL_OK) return rc;
     b->ntiles_lbm = (int)lt.size();
@@ -523,7 +570,7 @@ int create_impl(el_batch* b, const el_batch_tuning* tuning, hipStream_t st)
             g_tune_cache[key] = b->tuning;
         }
     }
-    return build_tiles(b);
+    return build_tiles(b, sizeof(T));
 }
 
 }  // namespace

@@ -1,6 +1,8 @@
 // el_api.hip -- the C ABI of libel.so (declared in include/el.h): argument
 // validation, precision dispatch and the launch sequence of the hybrid step
 // (Sec. II D).  All device memory belongs to the caller.
+#include <algorithm>
+
 #include "host_common.hpp"
 
 namespace elh {
@@ -85,15 +87,22 @@ int launch_lbm_steps(const el_params* p, el_state* s, int nsteps, hipStream_t st
 {
     const el::LbmArgs<T> a = lbm_args<T>(p);
     const int grid = grid_for(a.g.N);
-    // whole-row blocks with the x shifts through LDS when a row is a whole number of wavefronts
-    const bool rows = (a.g.nx % 64 == 0) && a.g.nx <= 1024;
-    const size_t shmem = rows ? 10 * (size_t)a.g.nx * sizeof(T) : 0;
+    // whole-row blocks with the x shifts through LDS: one row per block when a
+    // row is a whole number of wavefronts, else as many rows as fit in 256 threads
+    const int R = (a.g.nx % 64 == 0) ? 1 : std::max(1, 256 / a.g.nx);
+    const bool rows = a.g.nx <= 1024 && 10 * (size_t)R * a.g.nx * sizeof(T) <= 65536;
+    const int threads = ((R * a.g.nx + 63) / 64) * 64;
+    const int nrow = a.g.ny * a.g.nzf;
+    const size_t shmem = rows ? 10 * (size_t)R * a.g.nx * sizeof(T) : 0;
     for (int k = 0; k < nsteps; ++k) {
         const T* qa = static_cast<const T*>(s->q[s->parity]);
         T* qb = static_cast<T*>(s->q[1 - s->parity]);
-        if (rows)
-            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT>), dim3(a.g.ny * a.g.nzf), dim3(a.g.nx), shmem, st, qa, qb,
-                               static_cast<const T*>(s->F), a);
+        if (rows && threads == a.g.nx)
+            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, true>), dim3(nrow), dim3(threads), shmem, st, qa, qb,
+                               static_cast<const T*>(s->F), a, 1);
+        else if (rows)
+            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, false>), dim3((nrow + R - 1) / R), dim3(threads), shmem,
+                               st, qa, qb, static_cast<const T*>(s->F), a, R);
         else
             hipLaunchKernelGGL((el::k_lbm_push<T, SHIFT>), dim3(grid), dim3(BLOCK), 0, st, qa, qb,
                                static_cast<const T*>(s->F), a);

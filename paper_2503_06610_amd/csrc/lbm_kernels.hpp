@@ -125,26 +125,40 @@ __device__ __forceinline__ void lbm_node(const T* __restrict__ qa, T* __restrict
     }
 }
 
-// Row variant for nx a multiple of 64 (nx <= 1024): block = one x-row
-// (y, z) of nx threads.  Populations moving in x are passed through LDS to
-// the thread owning their destination column, so every global store writes
-// whole aligned rows; the arithmetic is lbm_collide's.
-template <typename T, bool SHIFT>
-__global__ void __launch_bounds__(1024) k_lbm_push_row(const T* __restrict__ qa, T* __restrict__ qb,
-                                                      const T* __restrict__ Flc, LbmArgs<T> a)
+// Row variant: a block handles R whole x-rows (y, z) = row0 .. row0 + R - 1,
+// thread (row rl, column x) = threadIdx.x = rl nx + x (R nx <= blockDim.x;
+// the rest idle).  Populations moving in x are passed through LDS
+// (lds: [10][R nx], the directions with e_x != 0) to the thread owning their
+// destination column, so every store writes whole rows; the arithmetic is
+// lbm_collide's.  Every thread of the block must call this (barrier).
+// ONE_ROW: R = 1 and blockDim = nx (no idle lanes, no division).
+template <typename T, bool SHIFT, bool ONE_ROW = false>
+__device__ __forceinline__ void lbm_rows(const T* __restrict__ qa, T* __restrict__ qb, const T* __restrict__ Flc,
+                                         const LbmArgs<T>& a, int row0, int R, T* lds)
 {
-    extern __shared__ unsigned char lbm_smem[];
-    T* lds = reinterpret_cast<T*>(lbm_smem);  // [10][nx]: the directions with e_x != 0
     const Geom& g = a.g;
-    const int x = threadIdx.x;
-    const int r = blockIdx.x;  // row index y + ny*z
+    const int rl = ONE_ROW ? 0 : (int)threadIdx.x / g.nx;
+    const int x = (int)threadIdx.x - rl * g.nx;
+    const int r = row0 + rl;
+    const bool active = rl < R && r < g.ny * g.nzf;
+    const int span = R * g.nx;
+    const int base = rl * g.nx;
+    const size_t N = (size_t)g.N;
+    // slot of each direction with e_x != 0 in the LDS staging area
+    constexpr int SLOT[19] = {-1, 0, 1, -1, -1, -1, -1, 2, 3, 4, 5, 6, 7, 8, 9, -1, -1, -1, -1};
+    T post[19];
+    int k = 0;
+    if (active) {
+        k = x + g.nx * r;
+        lbm_collide<T, SHIFT>(qa, Flc, a, k, post);
+#pragma unroll
+        for (int i = 0; i < 19; ++i)
+            if (SLOT[i] >= 0) lds[SLOT[i] * span + base + x] = post[i];
+    }
+    __syncthreads();
+    if (!active) return;
     const int y = r % g.ny;
     const int z = r / g.ny;
-    const int k = x + g.nx * r;
-    const size_t N = (size_t)g.N;
-    T post[19];
-    lbm_collide<T, SHIFT>(qa, Flc, a, k, post);
-
     const int row = g.nx, plane = g.nx * g.ny;
     const int ys[3] = {((y == 0) ? g.ny - 1 : y - 1) * row, y * row, ((y == g.ny - 1) ? 0 : y + 1) * row};
     int zm = z - 1, zp = z + 1;
@@ -157,12 +171,6 @@ __global__ void __launch_bounds__(1024) k_lbm_push_row(const T* __restrict__ qa,
         wall_p = zp == g.nzf;
     }
     const int zs[3] = {zm * plane, z * plane, zp * plane};
-    // slot of each direction with e_x != 0 in the LDS staging area
-    constexpr int SLOT[19] = {-1, 0, 1, -1, -1, -1, -1, 2, 3, 4, 5, 6, 7, 8, 9, -1, -1, -1, -1};
-#pragma unroll
-    for (int i = 0; i < 19; ++i)
-        if (SLOT[i] >= 0) lds[SLOT[i] * g.nx + x] = post[i];
-    __syncthreads();
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
         const bool to_wall = (EZ(i) == 1 && wall_p) || (EZ(i) == -1 && wall_m);
@@ -174,9 +182,19 @@ __global__ void __launch_bounds__(1024) k_lbm_push_row(const T* __restrict__ qa,
             // the population arriving at column x came from column x - e_x
             int xs = x - EX(i);
             xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
-            qb[i * N + x + ys[EY(i) + 1] + zs[EZ(i) + 1]] = lds[SLOT[i] * g.nx + xs];
+            qb[i * N + x + ys[EY(i) + 1] + zs[EZ(i) + 1]] = lds[SLOT[i] * span + base + xs];
         }
     }
+}
+
+// Rows of one lattice: block b handles rows b R .. b R + R - 1 (nx <= 1024,
+// blockDim >= R nx; ONE_ROW: R = 1, blockDim = nx); dynamic LDS 10 R nx values.
+template <typename T, bool SHIFT, bool ONE_ROW>
+__global__ void __launch_bounds__(1024) k_lbm_push_row(const T* __restrict__ qa, T* __restrict__ qb,
+                                                      const T* __restrict__ Flc, LbmArgs<T> a, int R)
+{
+    extern __shared__ unsigned char lbm_smem[];
+    lbm_rows<T, SHIFT, ONE_ROW>(qa, qb, Flc, a, (int)blockIdx.x * R, R, reinterpret_cast<T*>(lbm_smem));
 }
 
 template <typename T, bool SHIFT>

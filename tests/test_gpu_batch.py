@@ -202,25 +202,28 @@ def test_capture_on_null_stream_is_rejected():
 
 
 def test_row_kernel_matches_generic_kernel():
-    """Rows that are whole wavefronts take the LDS row-shift LBM kernel on the
-    single-lattice path; the batch uses the generic push.  Both must agree
-    bitwise (same collision code, only the data movement differs)."""
+    """The single-lattice path takes the LDS row-shift LBM kernel; the batch
+    uses the generic push (node tiles) or the row kernel on row tiles.  All
+    must agree bitwise (same collision code, only the data movement differs)."""
     import torch
     mat = inputs.set_a()
     chans = []
-    for i, (nx, ny, nz, r) in enumerate([(64, 9, 10, 1), (128, 5, 7, 3), (192, 3, 6, 2)]):
+    for i, (nx, ny, nz, r) in enumerate([(64, 9, 10, 1), (128, 5, 7, 3), (192, 3, 6, 2), (100, 4, 6, 2)]):
         prob = inputs.channel(nx, ny, nz, mat, g=(2e-6, 1e-7, 0.0), K=1e-3, q0=2 * math.pi / 16, fd_ratio=r)
         chans.append((prob, inputs.director_tilt(prob, seed=30 + i, amplitude=0.3)))
     singles = _lattices(chans, "f32_shifted")
     for lat in singles:
         lat.run(17)
     lats = _lattices(chans, "f32_shifted")
-    b = el.Batch(lats, tuning=(256, 4, 256, 4))
-    b.step(17)
-    b.moments()
-    b.sync()
-    torch.cuda.synchronize()
-    for i, (a, s) in enumerate(zip(lats, singles)):
-        fa, fs = _fields(a), _fields(s)
-        for k in fa:
-            assert np.array_equal(fa[k], fs[k]), (i, k)
+    for tuning in ((256, 4, 256, 4), (256, 0, 256, 0)):  # node tiles; row tiles (every nx <= 256)
+        lats = _lattices(chans, "f32_shifted")
+        b = el.Batch(lats, tuning=tuning)
+        b.step(17)
+        b.moments()
+        b.sync()
+        torch.cuda.synchronize()
+        for i, (a, s) in enumerate(zip(lats, singles)):
+            fa, fs = _fields(a), _fields(s)
+            for k in fa:
+                assert np.array_equal(fa[k], fs[k]), (tuning, i, k)
+        b.close()

@@ -97,6 +97,25 @@ def test_ragged_lattice_all_terms_fp64():
         assert rel_l2(lat.get("F"), o.get("F")) < 1e-10
 
 
+@pytest.mark.parametrize("nx,ny", [(300, 4), (37, 11), (64, 5)])
+def test_row_shapes_match_oracle(nx, ny):
+    """The LBM row kernel's block shapes: several short rows per block (37),
+    one row of a whole number of wavefronts (64), one row with idle lanes
+    (300 of 320 threads); FP64 against the oracle, FP32-shifted against
+    FP64 on the GPU."""
+    prob = inputs.channel(nx, ny, 7, inputs.set_a(), g=(2e-6, 1e-6, 0.0), K=2e-3, q0=2 * math.pi / 12,
+                          fd_ratio=2)
+    n0 = inputs.director_tilt(prob, seed=nx, amplitude=0.3)
+    _say(f"rows {nx}x{ny}")
+    lat = _gpu(prob, n0, "f64_shifted", 9)
+    o = _oracle(prob, n0, 9)
+    assert rel_l2(lat.get("q"), o.get("q")) < 1e-11
+    assert rel_l2(lat.get("u"), o.get("u")) < 1e-11
+    assert rel_l2(lat.get("n"), o.get("n")) < 1e-12
+    lat32 = _gpu(prob, n0, "f32_shifted", 9)
+    assert rel_l2(lat32.get("u"), lat.get("u")) < 1e-4
+
+
 def test_step_calls_compose_to_run():
     """el_step_lbm / el_moments / el_step_director in the order of the hybrid
     loop give bitwise the same state as el_run."""
