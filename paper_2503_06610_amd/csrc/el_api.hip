@@ -133,9 +133,9 @@ int launch_force(const el_params* p, el_state* s, hipStream_t st)
     T* sig = sigma_of<T>(s);
     const int grid = grid_for(a.g.N);
     hipLaunchKernelGGL((el::k_fd_stress<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
-                       static_cast<const T*>(s->u), sig, a);
+                       static_cast<const T*>(s->u), sig, a, fd_strip(a.g));
     hipLaunchKernelGGL((el::k_fd_divergence<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(sig),
-                       static_cast<T*>(s->F), a);
+                       static_cast<T*>(s->F), a, fd_strip(a.g));
     return check_launch("force kernels");
 }
 
@@ -146,10 +146,11 @@ int launch_director(const el_params* p, el_state* s, hipStream_t st)
     if (p->flags & EL_FREEZE_DIRECTOR) return launch_force<T>(p, s, st);
     const int grid = grid_for(a.g.N);
     hipLaunchKernelGGL((el::k_fd_predictor<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
-                       static_cast<const T*>(s->u), static_cast<T*>(s->n_pred), static_cast<T*>(s->dndt), a);
+                       static_cast<const T*>(s->u), static_cast<T*>(s->n_pred), static_cast<T*>(s->dndt), a,
+                       fd_strip(a.g));
     hipLaunchKernelGGL((el::k_fd_corrector<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<T*>(s->n),
                        static_cast<const T*>(s->n_pred), static_cast<const T*>(s->u),
-                       static_cast<const T*>(s->dndt), a);
+                       static_cast<const T*>(s->dndt), a, fd_strip(a.g));
     int rc = check_launch("director kernels");
     if (rc != EL_OK) return rc;
     return launch_force<T>(p, s, st);

@@ -175,22 +175,50 @@ __device__ __forceinline__ void corrector_node(T* __restrict__ n, const T* __res
     for (int c = 0; c < 3; ++c) n[c * N + k] = v[c];
 }
 
+// Order in which the single-lattice FD kernels visit the nodes: y-strips of
+// `strip` rows (the last one ragged), each strip plane by plane, x fastest.
+// Consecutive indices then stay within a few strip-planes, so the planes
+// above and below a node are still in L2 when its stencil reads them (with
+// strip = ny this is the plain x-fastest order).  Returns the node index of
+// visit number L < N.
+__device__ __forceinline__ int strip_node(const Geom& g, int strip, int L)
+{
+    const int full = g.nx * strip * g.nzf;
+    const int nfull = g.ny / strip;
+    int s = L / full;
+    int rows = strip;
+    int rem = L - s * full;
+    if (s >= nfull) {
+        s = nfull;
+        rem = L - nfull * full;
+        rows = g.ny - nfull * strip;
+    }
+    const int per_plane = g.nx * rows;
+    const int z = rem / per_plane;
+    const int r2 = rem - z * per_plane;
+    const int yl = r2 / g.nx;
+    const int x = r2 - yl * g.nx;
+    return x + g.nx * ((s * strip + yl) + g.ny * z);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_fd_predictor(const T* __restrict__ n, const T* __restrict__ u,
-                                                     T* __restrict__ nP, T* __restrict__ dndt, FdArgs<T> a)
+                                                     T* __restrict__ nP, T* __restrict__ dndt, FdArgs<T> a, int strip)
 {
-    const int k = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (k >= a.g.N) return;
+    const int L = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (L >= a.g.N) return;
+    const int k = strip_node(a.g, strip, L);
     predictor_node(n, u, nP, dndt, a, k);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_fd_corrector(T* __restrict__ n, const T* __restrict__ nP,
                                                      const T* __restrict__ u, const T* __restrict__ dndt,
-                                                     FdArgs<T> a)
+                                                     FdArgs<T> a, int strip)
 {
-    const int k = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (k >= a.g.N) return;
+    const int L = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (L >= a.g.N) return;
+    const int k = strip_node(a.g, strip, L);
     corrector_node(n, nP, u, dndt, a, k);
 }
 
@@ -277,18 +305,20 @@ __device__ __forceinline__ void divergence_node(const T* __restrict__ sig, T* __
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_fd_stress(const T* __restrict__ n, const T* __restrict__ u,
-                                                  T* __restrict__ sig, FdArgs<T> a)
+                                                  T* __restrict__ sig, FdArgs<T> a, int strip)
 {
-    const int k = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (k >= a.g.N) return;
+    const int L = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (L >= a.g.N) return;
+    const int k = strip_node(a.g, strip, L);
     stress_node(n, u, sig, a, k);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_fd_divergence(const T* __restrict__ sig, T* __restrict__ F, FdArgs<T> a)
+__global__ void __launch_bounds__(256) k_fd_divergence(const T* __restrict__ sig, T* __restrict__ F, FdArgs<T> a, int strip)
 {
-    const int k = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (k >= a.g.N) return;
+    const int L = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (L >= a.g.N) return;
+    const int k = strip_node(a.g, strip, L);
     divergence_node(sig, F, a, k);
 }
 
