@@ -189,10 +189,16 @@ def main():
         n = args.calibrate_copy * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        dst.copy_(src)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
         for _ in range(5):
             dst.copy_(src)
+        b.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_each_way": n * 4, "copies": 5}), flush=True)
+        gbs = 2 * n * 4 * 5 / (a.elapsed_time(b) * 1e-3) / 1e9
+        print(json.dumps({"copy_bytes_each_way": n * 4, "copies": 6, "copy_GBps_read_plus_write": round(gbs, 1)}),
+              flush=True)
         return
     if args.workload == "c4":
         print(json.dumps(bench_batch(args)), flush=True)
