@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(1024) k_batch_lbm(const ChanDesc<T>* __restric
 
 // Row tiles: tile = (channel, first row); the block handles
 // R = blockDim / nx whole rows of the channel (every channel has nx <= blockDim).
-template <typename T, bool SHIFT>
+template <typename T, bool SHIFT, bool NTS>
 __global__ void __launch_bounds__(1024) k_batch_lbm_rows(const ChanDesc<T>* __restrict__ ch,
                                                         const int2* __restrict__ tiles, const int* __restrict__ tdev)
 {
@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(1024) k_batch_lbm_rows(const ChanDesc<T>* __re
     const ChanDesc<T>& c = ch[tl.x];
     const int R = max(1, (int)blockDim.x / c.lbm.g.nx);
     const int par = c.parity0 ^ (t & 1);
-    lbm_rows<T, SHIFT>(c.q[par], c.q[par ^ 1], c.F, c.lbm, tl.y, R, reinterpret_cast<T*>(lbm_smem));
+    lbm_rows<T, SHIFT, false, NTS>(c.q[par], c.q[par ^ 1], c.F, c.lbm, tl.y, R, reinterpret_cast<T*>(lbm_smem));
 }
 
 // Which channels a moments launch covers.
@@ -189,6 +189,7 @@ struct el_batch {
     int cus = 0;
     el_batch_tuning tuning{};
     bool lbm_rows = false;  // LBM tiles are row tiles (one block per tile, whole rows)
+    bool nts = false;       // streaming q stores (all channels' q buffers together > 192 MiB)
     std::vector<el::DueGroup> h_groups;  // host copy of the group table
     int period = 0;  // lcm of the channels' r when <= MAX_PERIOD (one graph per phase), else 0
     std::vector<hipGraph_t> graphs;
@@ -304,9 +305,14 @@ int grid_of(int ntiles, int cus, int bpc) { return std::max(1, bpc == 0 ? ntiles
 template <typename T, bool SHIFT>
 void launch_lbm(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int block, int bpc, bool rows)
 {
-    if (rows)
-        hipLaunchKernelGGL((el::k_batch_lbm_rows<T, SHIFT>), dim3(ntiles), dim3(block), 10 * (size_t)block * sizeof(T),
-                           st, static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, b->d_t);
+    if (rows && b->nts)
+        hipLaunchKernelGGL((el::k_batch_lbm_rows<T, SHIFT, true>), dim3(ntiles), dim3(block),
+                           10 * (size_t)block * sizeof(T), st, static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles,
+                           b->d_t);
+    else if (rows)
+        hipLaunchKernelGGL((el::k_batch_lbm_rows<T, SHIFT, false>), dim3(ntiles), dim3(block),
+                           10 * (size_t)block * sizeof(T), st, static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles,
+                           b->d_t);
     else
         hipLaunchKernelGGL((el::k_batch_lbm<T, SHIFT>), dim3(grid_of(ntiles, b->cus, bpc)), dim3(block), 0, st,
                            static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles, b->d_t);
@@ -540,6 +546,11 @@ template <typename T, bool SHIFT>
 int create_impl(el_batch* b, const el_batch_tuning* tuning, hipStream_t st)
 {
     b->period = period_of(b->params);
+    {
+        size_t qbytes = 0;
+        for (const el_params& p : b->params) qbytes += 19 * (size_t)geom_of(&p).N * sizeof(T);
+        b->nts = streaming_stores(qbytes);
+    }
     int rc = build_table<T>(b);
     if (rc != EL_OK) return rc;
     if (hipMalloc(&b->d_t, sizeof(int)) != hipSuccess) return fail(EL_EDEVICE, "hipMalloc of the step counter failed");

@@ -94,15 +94,22 @@ int launch_lbm_steps(const el_params* p, el_state* s, int nsteps, hipStream_t st
     const int threads = ((R * a.g.nx + 63) / 64) * 64;
     const int nrow = a.g.ny * a.g.nzf;
     const size_t shmem = rows ? 10 * (size_t)R * a.g.nx * sizeof(T) : 0;
+    const bool nts = streaming_stores(19 * (size_t)a.g.N * sizeof(T));
     for (int k = 0; k < nsteps; ++k) {
         const T* qa = static_cast<const T*>(s->q[s->parity]);
         T* qb = static_cast<T*>(s->q[1 - s->parity]);
-        if (rows && threads == a.g.nx)
-            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, true>), dim3(nrow), dim3(threads), shmem, st, qa, qb,
-                               static_cast<const T*>(s->F), a, 1);
+        if (rows && threads == a.g.nx && nts)
+            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, true, true>), dim3(nrow), dim3(threads), shmem, st, qa,
+                               qb, static_cast<const T*>(s->F), a, 1);
+        else if (rows && threads == a.g.nx)
+            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, true, false>), dim3(nrow), dim3(threads), shmem, st, qa,
+                               qb, static_cast<const T*>(s->F), a, 1);
+        else if (rows && nts)
+            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, false, true>), dim3((nrow + R - 1) / R), dim3(threads),
+                               shmem, st, qa, qb, static_cast<const T*>(s->F), a, R);
         else if (rows)
-            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, false>), dim3((nrow + R - 1) / R), dim3(threads), shmem,
-                               st, qa, qb, static_cast<const T*>(s->F), a, R);
+            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, false, false>), dim3((nrow + R - 1) / R), dim3(threads),
+                               shmem, st, qa, qb, static_cast<const T*>(s->F), a, R);
         else
             hipLaunchKernelGGL((el::k_lbm_push<T, SHIFT>), dim3(grid), dim3(BLOCK), 0, st, qa, qb,
                                static_cast<const T*>(s->F), a);

@@ -71,6 +71,14 @@ inline int fd_strip(const el::Geom& g)
     return s < 1 ? 1 : (s > g.ny ? g.ny : s);
 }
 
+// Whether the LBM kernels store q with streaming stores: when one q buffer is
+// larger than 320 MiB.  Measured in the coupled step (LBM launches between FD
+// steps, HIP events): 256x256x48 FP64 (458 MB per buffer) 184 -> 172 us and
+// the 64-channel ensemble (1.4 GB) 2 % faster with streaming stores, but
+// 256x256x48 FP32 (229 MB) 83 -> 90 us and 128x128x64 FP64 (154 MB) 49 -> 57 us
+// slower, so below the threshold ordinary stores stay.
+inline bool streaming_stores(size_t q_buffer_bytes) { return q_buffer_bytes > ((size_t)320 << 20); }
+
 template <typename T>
 el::LbmArgs<T> lbm_args(const el_params* p)
 {

@@ -11,6 +11,26 @@
 
 namespace el {
 
+// q is read once per step: loads do not allocate in the caches.
+template <typename T>
+__device__ __forceinline__ T q_load(const T* p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
+// Stores of the next step's q: streaming (non-temporal) when the q buffers are
+// much larger than the 256 MB Infinity Cache, so they do not evict data that
+// will be reused; ordinary when the state fits there (the next step reads it
+// back from the cache).
+template <bool NT, typename T>
+__device__ __forceinline__ void q_store(T* p, T v)
+{
+    if (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 template <typename T>
 struct LbmArgs {
     Geom g;
@@ -53,7 +73,7 @@ __device__ __forceinline__ void lbm_collide(const T* __restrict__ qa, const T* _
     const size_t N = (size_t)a.g.N;
     T q[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) q[i] = __builtin_nontemporal_load(qa + i * N + k);
+    for (int i = 0; i < 19; ++i) q[i] = q_load(qa + i * N + k);
 
     T rho, drho, jx, jy, jz;
     node_moments<T, SHIFT>(q, rho, drho, jx, jy, jz);
@@ -131,8 +151,9 @@ __device__ __forceinline__ void lbm_node(const T* __restrict__ qa, T* __restrict
 // (lds: [10][R nx], the directions with e_x != 0) to the thread owning their
 // destination column, so every store writes whole rows; the arithmetic is
 // lbm_collide's.  Every thread of the block must call this (barrier).
-// ONE_ROW: R = 1 and blockDim = nx (no idle lanes, no division).
-template <typename T, bool SHIFT, bool ONE_ROW = false>
+// ONE_ROW: R = 1 and blockDim = nx (no idle lanes, no division).  NTS:
+// streaming stores (see q_store).
+template <typename T, bool SHIFT, bool ONE_ROW = false, bool NTS = false>
 __device__ __forceinline__ void lbm_rows(const T* __restrict__ qa, T* __restrict__ qb, const T* __restrict__ Flc,
                                          const LbmArgs<T>& a, int row0, int R, T* lds)
 {
@@ -175,26 +196,26 @@ __device__ __forceinline__ void lbm_rows(const T* __restrict__ qa, T* __restrict
     for (int i = 0; i < 19; ++i) {
         const bool to_wall = (EZ(i) == 1 && wall_p) || (EZ(i) == -1 && wall_m);
         if (to_wall) {
-            qb[OPP(i) * N + k] = post[i];  // bounce-back: own value, own node
+            q_store<NTS>(qb + OPP(i) * N + k, post[i]);  // bounce-back: own value, own node
         } else if (SLOT[i] < 0) {
-            qb[i * N + x + ys[EY(i) + 1] + zs[EZ(i) + 1]] = post[i];
+            q_store<NTS>(qb + i * N + x + ys[EY(i) + 1] + zs[EZ(i) + 1], post[i]);
         } else {
             // the population arriving at column x came from column x - e_x
             int xs = x - EX(i);
             xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
-            qb[i * N + x + ys[EY(i) + 1] + zs[EZ(i) + 1]] = lds[SLOT[i] * span + base + xs];
+            q_store<NTS>(qb + i * N + x + ys[EY(i) + 1] + zs[EZ(i) + 1], lds[SLOT[i] * span + base + xs]);
         }
     }
 }
 
 // Rows of one lattice: block b handles rows b R .. b R + R - 1 (nx <= 1024,
 // blockDim >= R nx; ONE_ROW: R = 1, blockDim = nx); dynamic LDS 10 R nx values.
-template <typename T, bool SHIFT, bool ONE_ROW>
+template <typename T, bool SHIFT, bool ONE_ROW, bool NTS>
 __global__ void __launch_bounds__(1024) k_lbm_push_row(const T* __restrict__ qa, T* __restrict__ qb,
                                                       const T* __restrict__ Flc, LbmArgs<T> a, int R)
 {
     extern __shared__ unsigned char lbm_smem[];
-    lbm_rows<T, SHIFT, ONE_ROW>(qa, qb, Flc, a, (int)blockIdx.x * R, R, reinterpret_cast<T*>(lbm_smem));
+    lbm_rows<T, SHIFT, ONE_ROW, NTS>(qa, qb, Flc, a, (int)blockIdx.x * R, R, reinterpret_cast<T*>(lbm_smem));
 }
 
 template <typename T, bool SHIFT>
