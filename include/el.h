@@ -110,7 +110,7 @@ typedef struct {
     int64_t step;       /* LBM steps taken since el_init_lattice */
 } el_state;
 
-enum { EL_BUF_Q = 0, EL_BUF_VEC3 = 1, EL_BUF_SCRATCH = 2 };
+enum { EL_BUF_Q = 0, EL_BUF_VEC3 = 1, EL_BUF_SCRATCH = 2, EL_BUF_HALO = 3 };
 
 /* FP64 observables (Sec. III error measures are in el_error_norms). */
 typedef struct {
@@ -151,7 +151,8 @@ const char* el_strerror(int status);
 const char* el_last_error(void);
 
 /* Bytes the caller must allocate: EL_BUF_Q for each of q[0], q[1];
- * EL_BUF_VEC3 for each of n, n_pred, dndt, u, F; EL_BUF_SCRATCH for scratch.
+ * EL_BUF_VEC3 for each of n, n_pred, dndt, u, F; EL_BUF_SCRATCH for scratch;
+ * EL_BUF_HALO for one el_halo_pack buffer (2 * 5 * nx * (fluid layers) T).
  * Returns 0 for invalid parameters. */
 size_t el_buffer_bytes(const el_params* p, int32_t which);
 
@@ -209,6 +210,33 @@ int el_force(const el_params* p, el_state* s, void* stream);
  * whose counter t satisfies t % r == 0, the moments, the predictor-corrector
  * and the new force.  u is left holding the velocity of the last step. */
 int el_run(const el_params* p, el_state* s, int64_t T, void* stream);
+
+/* y-slab exchange for a lattice split along y over several devices (the
+ * streaming step of Sec. II C across slab faces).  Each slab is a lattice of
+ * its own (same nx, nz; ny = its rows) stepped with el_step_lbm, which wraps
+ * y inside the slab; after every LBM step each slab packs what left it
+ * through its two y faces, the buffers are exchanged (on one device: plain
+ * device memory; across devices: the collective of the caller's choice),
+ * and each slab unpacks what its neighbours sent.  The LBM state is then
+ * identical to that of the unsplit lattice.  Only the distributions are
+ * exchanged: the finite-difference stencils need one-node halos of n, u,
+ * n_pred and the stress as well, which these calls do not provide, so a
+ * split run is exact for the LBM part (EL_NO_COUPLING, or F^LC given).
+ *
+ * el_halo_pack: out (device, el_buffer_bytes(p, EL_BUF_HALO) bytes) =
+ *   [0][d][zf][x]: q of the five e_y = +1 directions (3, 7, 10, 15, 17) in
+ *                  row y = 0, i.e. this slab's upward outflow (for the slab
+ *                  above);
+ *   [1][d][zf][x]: q of the five e_y = -1 directions (4, 8, 9, 16, 18) in
+ *                  row y = ny - 1 (downward outflow, for the slab below).
+ * el_halo_unpack: row 0, e_y = +1 directions <- lower[0] (the buffer packed
+ *   by the slab below); row ny - 1, e_y = -1 directions <- upper[1] (the
+ *   slab above); except at a node whose source layer z - e_z is a wall,
+ *   where the value is the node's own bounce-back and is kept.  A slab that
+ *   is its own neighbour (lower = upper = its own buffer) is unchanged.
+ * Both act on q[parity]; buffers may not alias q.  EL_EINVAL for NULL. */
+int el_halo_pack(const el_params* p, const el_state* s, void* out, void* stream);
+int el_halo_unpack(const el_params* p, el_state* s, const void* lower, const void* upper, void* stream);
 
 /* FP64 observables of the current state into out (device memory, one el_obs).
  * Uses the first 128 KiB of s->scratch. */

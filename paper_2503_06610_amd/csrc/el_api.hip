@@ -278,6 +278,7 @@ size_t el_buffer_bytes(const el_params* p, int32_t which)
     case EL_BUF_Q: return 19 * N * ts;
     case EL_BUF_VEC3: return 3 * N * ts;
     case EL_BUF_SCRATCH: return REDUCE_BYTES + 9 * N * ts;
+    case EL_BUF_HALO: return 2 * 5 * (size_t)p->nx * (size_t)nzf_of(p) * ts;
     default: fail(EL_EINVAL, "unknown buffer kind %d", which); return 0;
     }
 }
@@ -374,6 +375,42 @@ int el_run(const el_params* p, el_state* s, int64_t T, void* stream)
             if ((rc = el_step_director(p, s, stream)) != EL_OK) return rc;
     }
     return EL_OK;
+}
+
+int el_halo_pack(const el_params* p, const el_state* s, void* out, void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if ((rc = state_checks(p, s)) != EL_OK) return rc;
+    if (!out) return fail(EL_EINVAL, "halo buffer is NULL");
+    const el::Geom g = geom_of(p);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const dim3 grid((5 * g.nx * g.nzf + BLOCK - 1) / BLOCK);
+    if (is_f64(p))
+        hipLaunchKernelGGL(el::k_halo_pack<double>, grid, dim3(BLOCK), 0, st,
+                           static_cast<const double*>(s->q[s->parity]), static_cast<double*>(out), g);
+    else
+        hipLaunchKernelGGL(el::k_halo_pack<float>, grid, dim3(BLOCK), 0, st,
+                           static_cast<const float*>(s->q[s->parity]), static_cast<float*>(out), g);
+    return check_launch("k_halo_pack");
+}
+
+int el_halo_unpack(const el_params* p, el_state* s, const void* lower, const void* upper, void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if ((rc = state_checks(p, s)) != EL_OK) return rc;
+    if (!lower || !upper) return fail(EL_EINVAL, "halo buffer is NULL");
+    const el::Geom g = geom_of(p);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const dim3 grid((5 * g.nx * g.nzf + BLOCK - 1) / BLOCK);
+    if (is_f64(p))
+        hipLaunchKernelGGL(el::k_halo_unpack<double>, grid, dim3(BLOCK), 0, st, static_cast<double*>(s->q[s->parity]),
+                           static_cast<const double*>(lower), static_cast<const double*>(upper), g);
+    else
+        hipLaunchKernelGGL(el::k_halo_unpack<float>, grid, dim3(BLOCK), 0, st, static_cast<float*>(s->q[s->parity]),
+                           static_cast<const float*>(lower), static_cast<const float*>(upper), g);
+    return check_launch("k_halo_unpack");
 }
 
 int el_observables(const el_params* p, const el_state* s, el_obs* out, void* stream)

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libel.so")
 EL_OK, EL_EINVAL, EL_EUNSTABLE, EL_EDEVICE, EL_ENAN, EL_ENOMEM = 0, -1, -2, -3, -4, -5
 EL_F64, EL_F64_SHIFTED, EL_F32, EL_F32_SHIFTED = 0, 1, 2, 3
 EL_PERIODIC_Z, EL_NO_COUPLING, EL_NO_RENORM_PREDICTOR, EL_ALLOW_UNSTABLE, EL_FREEZE_DIRECTOR = 1, 2, 4, 8, 16
-EL_BUF_Q, EL_BUF_VEC3, EL_BUF_SCRATCH = 0, 1, 2
+EL_BUF_Q, EL_BUF_VEC3, EL_BUF_SCRATCH, EL_BUF_HALO = 0, 1, 2, 3
 
 PRECISIONS = {"f64": EL_F64, "f64_shifted": EL_F64_SHIFTED, "f32": EL_F32, "f32_shifted": EL_F32_SHIFTED}
 
@@ -29,7 +29,8 @@ EXPORTED = ("el_version", "el_strerror", "el_last_error", "el_buffer_bytes", "el
             "el_observables", "el_tube_drift", "el_error_norms", "el_batch_create", "el_batch_step", "el_batch_capture",
             "el_batch_moments", "el_batch_observables", "el_batch_sync", "el_batch_get_tuning", "el_batch_destroy",
             "el_nn_input", "el_nn_conv_forward", "el_nn_conv_backward_data", "el_nn_work_bytes",
-            "el_nn_conv_backward_weight", "el_nn_mse", "el_nn_adam", "el_nn_velocity")
+            "el_nn_conv_backward_weight", "el_nn_mse", "el_nn_adam", "el_nn_velocity", "el_halo_pack",
+            "el_halo_unpack")
 
 
 class ElError(RuntimeError):
@@ -103,6 +104,8 @@ def load(path: str = LIB_PATH):
         "el_observables": (C.c_int, [P, S, V, V]),
         "el_error_norms": (C.c_int, [P, V, V, C.c_int32, V, V, V]),
         "el_tube_drift": (C.c_int, [P, S, V, V]),
+        "el_halo_pack": (C.c_int, [P, S, V, V]),
+        "el_halo_unpack": (C.c_int, [P, S, V, V, V]),
         "el_batch_create": (C.c_int, [P, S, C.c_int32, C.POINTER(el_batch_tuning), V, C.POINTER(C.c_void_p)]),
         "el_batch_step": (C.c_int, [V, C.c_int32, V]),
         "el_batch_capture": (C.c_int, [V, V]),
@@ -293,6 +296,20 @@ class Lattice:
 
     def q_current(self):
         return self.q[self.state.parity]
+
+    def halo_buffer(self):
+        """A device buffer for el_halo_pack of this lattice."""
+        import torch
+        n = buffer_bytes(self.params, EL_BUF_HALO)
+        return torch.empty(n, dtype=torch.uint8, device=self.n.device)
+
+    def halo_pack(self, out, stream=None):
+        _check(self.lib.el_halo_pack(C.byref(self.params), C.byref(self.state), C.c_void_p(out.data_ptr()),
+                                     _stream_ptr(stream)), "el_halo_pack")
+
+    def halo_unpack(self, lower, upper, stream=None):
+        _check(self.lib.el_halo_unpack(C.byref(self.params), C.byref(self.state), C.c_void_p(lower.data_ptr()),
+                                       C.c_void_p(upper.data_ptr()), _stream_ptr(stream)), "el_halo_unpack")
 
     def get(self, name: str) -> np.ndarray:
         """Host copy (float64) of a field: q, n, nP, u, F."""

@@ -112,6 +112,7 @@ def test_buffer_bytes():
         assert el.buffer_bytes(p, el.EL_BUF_Q) == 19 * N * ts
         assert el.buffer_bytes(p, el.EL_BUF_VEC3) == 3 * N * ts
         assert el.buffer_bytes(p, el.EL_BUF_SCRATCH) == 131072 + 9 * N * ts
+        assert el.buffer_bytes(p, el.EL_BUF_HALO) == 2 * 5 * prob.nx * prob.nzf * ts
         assert el.buffer_bytes(p, 99) == 0
 
 
@@ -125,4 +126,6 @@ def test_null_arguments_are_rejected_without_device_work():
     assert lib.el_step_director(None, C.byref(s), None) == el.EL_EINVAL
     assert lib.el_observables(C.byref(p), C.byref(s), None, None) == el.EL_EINVAL
     assert lib.el_error_norms(C.byref(p), None, None, 3, None, None, None) == el.EL_EINVAL
+    assert lib.el_halo_pack(C.byref(p), None, None, None) == el.EL_EINVAL
+    assert lib.el_halo_unpack(C.byref(p), C.byref(s), None, None, None) == el.EL_EINVAL
     assert lib.el_strerror(el.EL_EUNSTABLE)
