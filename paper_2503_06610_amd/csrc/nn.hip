@@ -52,6 +52,32 @@ void launch_conv(const VolGeom& g, hipStream_t st, const __bf16* x, const __bf16
                        x, w, bias, mask, y, g, cout_store);
 }
 
+// LDS-tiled 32-input-channel convolution: one block of 512 threads per
+// compute unit (the input box and the weights take 106-134 KB of LDS).
+template <int NT, bool RELU, bool SOA>
+void launch_conv_tiled(const VolGeom& g, hipStream_t st, const __bf16* x, const __bf16* w, const float* bias,
+                       const __bf16* mask, void* y, int cout_store)
+{
+    constexpr int lds = el::nn::conv_tiled_lds_bytes(NT);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&el::nn::k_conv_tiled<NT, RELU, SOA>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        attr = true;
+    }
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    }
+    const long long tiles = (long long)g.nsamples * ((g.nzf + el::nn::CT_Z - 1) / el::nn::CT_Z) *
+                            ((g.ny + el::nn::CT_Y - 1) / el::nn::CT_Y) * ((g.nx + el::nn::CT_X - 1) / el::nn::CT_X);
+    const int grid = (int)std::max(1LL, std::min(tiles, (long long)cus));
+    hipLaunchKernelGGL((el::nn::k_conv_tiled<NT, RELU, SOA>), dim3(grid), dim3(512), lds, st, x, w, bias, mask, y, g,
+                       cout_store);
+}
+
 template <int CIN, int MT>
 void launch_wgrad(const VolGeom& g, hipStream_t st, int nb, const __bf16* x, const __bf16* dy, float* part)
 {
@@ -114,7 +140,7 @@ int el_nn_conv_forward(const el_nn_vol* vol, int32_t cin, int32_t cout, const vo
     if (cout == 3) {
         if (relu) return fail(EL_EINVAL, "the FP32 output layer has no activation");
         if (cin == 32)
-            launch_conv<32, 1, false, true>(g, st, X, W, bias, nullptr, y, 3);
+            launch_conv_tiled<1, false, true>(g, st, X, W, bias, nullptr, y, 3);
         else
             return fail(EL_EINVAL, "output layer needs cin = 32");
     } else if (cout == 32 && cin == 8) {
@@ -124,9 +150,9 @@ int el_nn_conv_forward(const el_nn_vol* vol, int32_t cin, int32_t cout, const vo
             launch_conv<8, 2, false, false>(g, st, X, W, bias, nullptr, y, 32);
     } else if (cout == 32 && cin == 32) {
         if (relu)
-            launch_conv<32, 2, true, false>(g, st, X, W, bias, nullptr, y, 32);
+            launch_conv_tiled<2, true, false>(g, st, X, W, bias, nullptr, y, 32);
         else
-            launch_conv<32, 2, false, false>(g, st, X, W, bias, nullptr, y, 32);
+            launch_conv_tiled<2, false, false>(g, st, X, W, bias, nullptr, y, 32);
     } else {
         return fail(EL_EINVAL, "unsupported conv %d -> %d", cin, cout);
     }
@@ -146,7 +172,7 @@ int el_nn_conv_backward_data(const el_nn_vol* vol, int32_t cin, int32_t cout, co
     const __bf16* WT = static_cast<const __bf16*>(wt);
     const __bf16* M = static_cast<const __bf16*>(mask);
     if (cout == 32)
-        launch_conv<32, 2, false, false>(g, st, DY, WT, nullptr, M, dx, 32);
+        launch_conv_tiled<2, false, false>(g, st, DY, WT, nullptr, M, dx, 32);
     else if (cout == 16)
         launch_conv<16, 2, false, false>(g, st, DY, WT, nullptr, M, dx, 32);
     else

@@ -196,6 +196,174 @@ __global__ void __launch_bounds__(CONV_THREADS) __attribute__((amdgpu_waves_per_
     }
 }
 
+// LDS-tiled convolution for 32 input channels.  A block (512 threads) owns
+// tiles of TX x TY x TZ = 32 x 4 x 4 voxels of one sample; per tile it stages
+// the input box with a one-voxel halo (34 x 6 x 6 voxels x 32 channels,
+// periodic in x and y, the halo planes in z) into LDS once, so the 27 taps
+// read their A fragments from LDS instead of re-reading the activations 27
+// times.  The 16-byte channel group g of box voxel b sits at slot
+// 4 b + (g ^ ((b >> 2) & 3)): the 16 lanes of a quarter-wave read 16
+// consecutive voxels of one group, which this swizzle spreads over all 64
+// banks.  Weights as in k_conv (B fragments in LDS).  Wave w computes rows
+// (ty, tz) = 2w, 2w + 1 of the tile, two 16-voxel halves each (4 M tiles).
+constexpr int CT_X = 32, CT_Y = 4, CT_Z = 4;
+constexpr int CB_X = CT_X + 2, CB_Y = CT_Y + 2, CB_Z = CT_Z + 2;
+constexpr int CB_VOX = CB_X * CB_Y * CB_Z;
+
+__host__ __device__ constexpr int conv_tiled_lds_bytes(int nt) { return CB_VOX * 64 + conv_lds_bytes(32, nt); }
+
+__device__ __forceinline__ int box_slot(int b, int g) { return 4 * b + (g ^ ((b >> 1) & 3)); }
+
+template <int NT, bool RELU, bool OUT_SOA>
+__global__ void __launch_bounds__(512) k_conv_tiled(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
+                                                   const float* __restrict__ bias, const __bf16* __restrict__ mask,
+                                                   void* __restrict__ y, VolGeom g, int cout_store)
+{
+    constexpr int CIN = 32;
+    constexpr int COUT = 16 * NT;
+    constexpr int KTOT = 27 * CIN;
+    extern __shared__ bf16x8 ct_lds[];
+    bf16x8* box = ct_lds;                 // [CB_VOX * 4] swizzled
+    bf16x8* wl = ct_lds + CB_VOX * 4;     // [27][4][COUT]
+
+    for (int i = threadIdx.x; i < 27 * 4 * COUT; i += blockDim.x) {
+        const int co = i % COUT;
+        const int grp = (i / COUT) % 4;
+        const int tap = i / (4 * COUT);
+        wl[i] = *reinterpret_cast<const bf16x8*>(w + (long long)co * KTOT + tap * CIN + 8 * grp);
+    }
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int m = lane & 15;
+    const int grp = lane >> 4;
+    const int tiles_x = (g.nx + CT_X - 1) / CT_X;
+    const int tiles_y = (g.ny + CT_Y - 1) / CT_Y;
+    const int tiles_z = (g.nzf + CT_Z - 1) / CT_Z;
+    const long long per_s = (long long)tiles_z * tiles_y * tiles_x;
+    const long long ntiles = (long long)g.nsamples * per_s;
+    const long long plane = (long long)g.nx * g.ny;
+    const long long per_sample = plane * (g.nzf + 2);
+
+    // Box of a tile, 16-byte chunk c = 4 b + g: loaded into registers by
+    // every thread (NCH chunks each, all in flight together), written to
+    // LDS after the previous tile's MFMAs, so the loads of tile i + 1
+    // overlap the arithmetic of tile i.
+    constexpr int NCH = (CB_VOX * 4 + 511) / 512;
+    bf16x8 stage[NCH];
+    auto load_box = [&](long long tile) {
+        int rest = (int)(tile % per_s);
+        const int s = (int)(tile / per_s);
+        const int x0 = (rest % tiles_x) * CT_X;
+        rest /= tiles_x;
+        const int y0 = (rest % tiles_y) * CT_Y;
+        const int z0 = (rest / tiles_y) * CT_Z;
+        const __bf16* xs = x + (long long)s * per_sample * CIN;
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            const int c = (int)threadIdx.x + 512 * k;
+            const int b = c >> 2;
+            const int gi = c & 3;
+            const int bx = b % CB_X;
+            const int by = (b / CB_X) % CB_Y;
+            const int bz = b / (CB_X * CB_Y);
+            int xx = (x0 - 1 + bx) % g.nx;
+            xx = xx < 0 ? xx + g.nx : xx;
+            int yy = (y0 - 1 + by) % g.ny;
+            yy = yy < 0 ? yy + g.ny : yy;
+            const int zh = z0 + bz;  // halo'd plane: z + 1 with z = z0 - 1 + bz
+            if (c < CB_VOX * 4 && zh <= g.nzf + 1) {
+                stage[k] = *reinterpret_cast<const bf16x8*>(xs + ((zh * plane + (long long)yy * g.nx + xx) * CIN + 8 * gi));
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) stage[k][j] = (__bf16)0.0f;
+            }
+        }
+    };
+    if ((long long)blockIdx.x < ntiles) load_box(blockIdx.x);
+
+    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        int rest = (int)(tile % per_s);
+        const int s = (int)(tile / per_s);
+        const int x0 = (rest % tiles_x) * CT_X;
+        rest /= tiles_x;
+        const int y0 = (rest % tiles_y) * CT_Y;
+        const int z0 = (rest / tiles_y) * CT_Z;
+
+        __syncthreads();  // the previous tile's box reads are done (and the weights are staged)
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            const int c = (int)threadIdx.x + 512 * k;
+            if (c < CB_VOX * 4) box[box_slot(c >> 2, c & 3)] = stage[k];
+        }
+        __syncthreads();
+        if (tile + gridDim.x < ntiles) load_box(tile + gridDim.x);
+
+        f32x4 acc[4][NT];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // box index of this lane's voxel in M tile mt at tap (0, 0, 0) offset
+        int bb[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int row = 2 * wave + (mt >> 1);  // row = ty + CT_Y tz
+            const int ty = row % CT_Y, tz = row / CT_Y;
+            bb[mt] = ((tz + 1) * CB_Y + (ty + 1)) * CB_X + (mt & 1) * 16 + m + 1;
+        }
+        // fragments of tap t + 1 are read from LDS while tap t multiplies
+        auto frags = [&](int tap, bf16x8 (&a)[4], bf16x8 (&b)[NT]) {
+            const int off = ((tap / 9 - 1) * CB_Y + ((tap / 3) % 3 - 1)) * CB_X + (tap % 3 - 1);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) b[nt] = wl[(tap * 4 + grp) * COUT + nt * 16 + m];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) a[mt] = box[box_slot(bb[mt] + off, grp)];
+        };
+        bf16x8 a[4], b[NT], an[4], bn[NT];
+        frags(0, a, b);
+#pragma unroll 3
+        for (int tap = 0; tap < 27; ++tap) {
+            if (tap + 1 < 27) frags(tap + 1, an, bn);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) a[mt] = an[mt];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) b[nt] = bn[nt];
+        }
+
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int row = 2 * wave + (mt >> 1);
+            const int yy = y0 + row % CT_Y, zz = z0 + row / CT_Y;
+            if (yy >= g.ny || zz >= g.nzf) continue;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = nt * 16 + m;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int xx = x0 + (mt & 1) * 16 + 4 * grp + j;
+                    if (xx >= g.nx) continue;
+                    float val = acc[mt][nt][j] + (bias ? bias[co] : 0.0f);
+                    if (RELU) val = fmaxf(val, 0.0f);
+                    const long long vint = (long long)s * g.n_int + ((long long)zz * g.ny + yy) * g.nx + xx;
+                    if (OUT_SOA) {
+                        if (co < cout_store) static_cast<float*>(y)[(long long)co * g.n_all + vint] = val;
+                    } else {
+                        const long long oi = own_index(g, vint) * COUT + co;
+                        if (mask && !((float)mask[oi] > 0.0f)) val = 0.0f;
+                        static_cast<__bf16*>(y)[oi] = (__bf16)val;
+                    }
+                }
+            }
+        }
+    }
+}
+
 // Padded LDS row of the weight-gradient kernel: 32 voxels + 8 (80 bytes, so
 // the 16 rows read by a quarter-wave fall in distinct banks).
 constexpr int WG_ROW = 40;
