@@ -263,22 +263,25 @@ int el_error_norms(const el_params* p, const void* a, const double* ref, int32_t
 
 /* ------------------------------------------------------------------------
  * Batched ensemble: many independent channels of uneven sizes, body forces
- * and FD/LBM step ratios advanced together.  Each step launches persistent
- * kernels over a work list of (channel, tile) pairs; a device step counter
- * decides per channel whether the finite-difference update of Sec. II D is
- * due ((step + 1) % r == 0).  When the least common multiple P of the
- * channels' r is at most 64, el_batch_capture records P graphs, one per
- * phase of the step count, each launching exactly the due tiles; the host
- * replays the one for the current step.
+ * and FD/LBM step ratios advanced together.  Each step launches the LBM
+ * kernel over a work list of (channel, tile) pairs (node tiles, or row tiles
+ * of whole x-rows) and the moments and FD kernels over the tiles whose
+ * channel's finite-difference update of Sec. II D is due ((step + 1) % r ==
+ * 0, decided from a device step counter).  When the least common multiple P
+ * of the channels' r is at most 64, el_batch_capture records P graphs, one
+ * per phase of the step count, each launching exactly the due tiles; the
+ * host replays the one for the current step.
  * Every channel performs the same arithmetic as the single-lattice calls, in
  * the same order, so its state is bitwise equal to an el_run of that channel.
  * ------------------------------------------------------------------------ */
 typedef struct el_batch el_batch;   /* opaque handle owned by the library */
 
 typedef struct {
-    int32_t lbm_block;          /* threads per block = nodes per tile of the LBM kernel (64..1024) */
-    int32_t lbm_blocks_per_cu;  /* 0: one block per tile; 1..64: persistent grid of
-                                   compute units * this blocks looping over the tiles */
+    int32_t lbm_block;          /* threads per block of the LBM kernel (64..1024): nodes per
+                                   node tile, or lbm_block / nx whole rows per row tile */
+    int32_t lbm_blocks_per_cu;  /* 0: one block per tile (row tiles when every channel's
+                                   nx <= lbm_block); 1..64: persistent grid of compute
+                                   units * this blocks looping over node tiles */
     int32_t fd_block;           /* the same for the moments and FD kernels */
     int32_t fd_blocks_per_cu;   /* used only when the least common multiple of the
                                    channels' r exceeds 64 (persistent grid; 0 means 8):
@@ -295,7 +298,7 @@ typedef struct {
  * shapes are timed on `stream` with kernels whose outputs are recomputed
  * before use (the LBM step into the inactive buffer, the moments, the
  * predictor, the stress), so the states are not changed; the choice is cached
- * per (kernel, precision, node-count class, channel-count class, GPU
+ * per (precision, node-count class, channel-count class, period or not, GPU
  * architecture) for the process; n_pred and dndt, the predictor-corrector's
  * intermediates, may be overwritten.  Allocates the small device tables of the
  * handle (hipMalloc, outside the hot path).  EL_EINVAL for a bad channel
