@@ -342,7 +342,10 @@ def time_forward(net, lat, reps=5):
     return ms, FLOPS_PER_VOXEL * n / (ms * 1e-3) / 1e12
 
 
-def warm_start_study(net, prob, n0, tol=1e-4, ref_steps=15000, check_every=100, log=print):
+def warm_start_study(nets, prob, n0, tol=1e-4, ref_steps=15000, check_every=100, log=print):
+    """Steps (and wall time, initialisation included) to reach rel-L2 <= tol
+    against the flow after ref_steps, from rest, from the analytic profile,
+    from an untrained network and from each trained network in `nets`."""
     import torch
     t0 = time.perf_counter()
     ref = el.Lattice(prob, "f32_shifted", freeze_director=True)
@@ -353,7 +356,10 @@ def warm_start_study(net, prob, n0, tol=1e-4, ref_steps=15000, check_every=100, 
     del ref
     torch.cuda.empty_cache()
     out = {}
-    modes = [("cold", None), ("poiseuille", None), ("untrained_net", Surrogate(seed=1234)), ("trained_net", net)]
+    if not isinstance(nets, (list, tuple)):
+        nets = [nets]
+    modes = [("cold", None), ("poiseuille", None), ("untrained_net", Surrogate(seed=1234))]
+    modes += [("trained_net" if len(nets) == 1 else f"trained_net_{k}", nt) for k, nt in enumerate(nets)]
     for mode, model in modes:
         lat = el.Lattice(prob, "f32_shifted", freeze_director=True)
         lat.init_lattice(n0)
@@ -387,6 +393,8 @@ def main(argv=None):
     ap.add_argument("--relax-steps", type=int, default=4000)
     ap.add_argument("--eval-size", type=int, nargs=3, default=[512, 512, 64])
     ap.add_argument("--ref-steps", type=int, default=15000)
+    ap.add_argument("--seeds", type=int, default=1,
+                    help="networks trained on the same pairs from different initial weights and minibatch orders")
     ap.add_argument("--no-study", action="store_true",
                     help="train and time the forward pass, without the time-to-steady comparison")
     ap.add_argument("--out", default="")
@@ -396,10 +404,13 @@ def main(argv=None):
     data = generate_pairs(args.samples, steps=args.relax_steps, log=log)
     t_gen = time.perf_counter() - t0
     max_change = data["max_change"]
-    net = Surrogate(seed=0)
+    nets, hists = [], []
     t0 = time.perf_counter()
-    hist = train(net, data, args.epochs, batch=args.batch, log=log)
-    t_train = time.perf_counter() - t0
+    for seed in range(args.seeds):
+        nets.append(Surrogate(seed=seed))
+        hists.append(train(nets[-1], data, args.epochs, batch=args.batch, log=log, seed=seed))
+    t_train = (time.perf_counter() - t0) / args.seeds
+    net, hist = nets[0], hists[0]
     del data
     torch.cuda.empty_cache()
     prob, n0 = eval_problem(*args.eval_size)
@@ -409,10 +420,11 @@ def main(argv=None):
     log(f"forward on {prob.nx}x{prob.ny}x{prob.nz}: {ms:.2f} ms, {tflops:.1f} TFLOP/s algorithmic")
     del lat
     torch.cuda.empty_cache()
-    study = None if args.no_study else warm_start_study(net, prob, n0, ref_steps=args.ref_steps, log=log)
+    study = None if args.no_study else warm_start_study(nets, prob, n0, ref_steps=args.ref_steps, log=log)
     res = {"train": {"samples": args.samples, "epochs": args.epochs, "batch": args.batch,
                      "generation_s": round(t_gen, 1), "max_last100_change": max_change,
-                     "train_s": round(t_train, 1), "loss_first": hist[0], "loss_last": hist[-1], "loss": hist},
+                     "train_s": round(t_train, 1), "loss_first": hist[0], "loss_last": hist[-1], "loss": hist,
+                     "seeds": args.seeds, "loss_last_per_seed": [h[-1] for h in hists]},
            "inference": {"size": list(args.eval_size), "forward_ms": round(ms, 3),
                          "tflops_algorithmic": round(tflops, 2), "mfma_bf16_peak_tflops": 2500.0,
                          "frac": round(tflops / 2500.0, 4)},
