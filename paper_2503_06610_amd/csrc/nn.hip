@@ -2,6 +2,7 @@
 // director, BF16-MFMA convolutions (forward, backward-data, backward-weight),
 // MSE loss, Adam, and the velocity the flow is initialised from.
 #include <algorithm>
+#include <atomic>
 
 #include "host_common.hpp"
 #include "nn_kernels.hpp"
@@ -28,16 +29,28 @@ int vol_of(const el_nn_vol* v, VolGeom* g)
     return EL_OK;
 }
 
+// Compute units of the current device (queried once per device; the
+// function-local statics are initialised thread-safely).
+int cu_count()
+{
+    constexpr int MAXDEV = 64;
+    static std::atomic<int> cache[MAXDEV] = {};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= MAXDEV) dev = 0;
+    int cus = cache[dev].load(std::memory_order_relaxed);
+    if (cus == 0) {
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+        cache[dev].store(cus, std::memory_order_relaxed);
+    }
+    return cus;
+}
+
 // Persistent grid of the convolution kernels: two blocks of CONV_THREADS
 // per compute unit (their weight copies fit the LDS), fewer for small volumes.
 int conv_blocks(const VolGeom& g)
 {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
-    }
+    const int cus = cu_count();
     const long long items = (g.n_all + 16 * el::nn::CONV_MT - 1) / (16 * el::nn::CONV_MT);
     const long long need = (items + el::nn::CONV_THREADS / 64 - 1) / (el::nn::CONV_THREADS / 64);
     return (int)std::max(1LL, std::min(need, 2LL * cus));
@@ -59,18 +72,10 @@ void launch_conv_tiled(const VolGeom& g, hipStream_t st, const __bf16* x, const 
                        const __bf16* mask, void* y, int cout_store)
 {
     constexpr int lds = el::nn::conv_tiled_lds_bytes(NT);
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&el::nn::k_conv_tiled<NT, RELU, SOA>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        attr = true;
-    }
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
-    }
+    // more than 64 KB of dynamic LDS must be allowed explicitly (idempotent)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&el::nn::k_conv_tiled<NT, RELU, SOA>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    const int cus = cu_count();
     const long long tiles = (long long)g.nsamples * ((g.nzf + el::nn::CT_Z - 1) / el::nn::CT_Z) *
                             ((g.ny + el::nn::CT_Y - 1) / el::nn::CT_Y) * ((g.nx + el::nn::CT_X - 1) / el::nn::CT_X);
     const int grid = (int)std::max(1LL, std::min(tiles, (long long)cus));
@@ -82,12 +87,8 @@ template <int CIN, int MT>
 void launch_wgrad(const VolGeom& g, hipStream_t st, int nb, const __bf16* x, const __bf16* dy, float* part)
 {
     constexpr int lds = el::nn::wgrad_lds_bytes(CIN, 16 * MT);
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&el::nn::k_conv_wgrad<CIN, MT>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        attr = true;
-    }
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&el::nn::k_conv_wgrad<CIN, MT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     hipLaunchKernelGGL((el::nn::k_conv_wgrad<CIN, MT>), dim3(nb), dim3(256), lds, st, x, dy, part, g, NN_CHUNK);
 }
 

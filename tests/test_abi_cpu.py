@@ -129,3 +129,27 @@ def test_null_arguments_are_rejected_without_device_work():
     assert lib.el_halo_pack(C.byref(p), None, None, None) == el.EL_EINVAL
     assert lib.el_halo_unpack(C.byref(p), C.byref(s), None, None, None) == el.EL_EINVAL
     assert lib.el_strerror(el.EL_EUNSTABLE)
+
+
+def test_surrogate_calls_reject_bad_arguments_without_device_work():
+    """The el_nn_* entry points validate volumes, pointers and channel counts
+    before touching the device."""
+    lib = el.load()
+    vol = el.el_nn_vol(10, 7, 5, 2)
+    bad = el.el_nn_vol(2, 7, 5, 2)
+    fake = C.c_void_p(16)  # never dereferenced: every case fails validation first
+    assert lib.el_nn_conv_forward(C.byref(bad), 32, 32, fake, fake, None, 1, fake, None) == el.EL_EINVAL
+    assert lib.el_nn_conv_forward(C.byref(vol), 32, 32, None, fake, None, 1, fake, None) == el.EL_EINVAL
+    assert lib.el_nn_conv_forward(C.byref(vol), 7, 32, fake, fake, None, 1, fake, None) == el.EL_EINVAL
+    assert lib.el_nn_conv_forward(C.byref(vol), 32, 3, fake, fake, None, 1, fake, None) == el.EL_EINVAL  # ReLU on output
+    assert lib.el_nn_conv_backward_data(C.byref(vol), 8, 32, fake, fake, None, fake, None) == el.EL_EINVAL
+    assert lib.el_nn_conv_backward_data(C.byref(vol), 32, 8, fake, fake, None, fake, None) == el.EL_EINVAL
+    assert lib.el_nn_work_bytes(C.byref(bad), 32, 32) == 0
+    need = lib.el_nn_work_bytes(C.byref(vol), 32, 32)
+    assert need > 0
+    assert lib.el_nn_conv_backward_weight(C.byref(vol), 32, 32, fake, fake, fake, need - 1, fake, fake,
+                                          None) == el.EL_ENOMEM
+    assert lib.el_nn_conv_backward_weight(C.byref(vol), 16, 32, fake, fake, fake, need, fake, fake,
+                                          None) == el.EL_EINVAL
+    assert lib.el_nn_adam(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None, None, 32, 32, None) == el.EL_EINVAL
+
