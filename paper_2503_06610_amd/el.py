@@ -86,6 +86,11 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libel.so not found at {path}: build it with paper_2503_06610_amd/build.py")
+    # torch brings its own HIP runtime; loading it before this library's (ROCm's
+    # libamdhip64.so.7) is the order that works: with libel.so loaded first, the
+    # first kernel launch of libel.so reported "no ROCm-capable device" once
+    # torch had initialised the GPU.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     P, S, V = C.POINTER(el_params), C.POINTER(el_state), C.c_void_p
     sig = {

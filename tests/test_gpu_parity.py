@@ -296,3 +296,55 @@ def test_tube_drift_unwraps_across_the_period():
     _say(f"tube displacement {d['displacement']} over {d['steps']} steps")
     assert d["ncalls"] == 12 and d["steps"] == 550
     assert abs(d["displacement"][0]) > 0.05
+
+
+# ---------------------------------------------------------------------------
+def _random_case(seed):
+    """A seeded random lattice within the stability bounds: sizes (ragged tiles
+    and rows), periodic or walled z, r, tau, scaled Leslie coefficients,
+    alpha4', K, q0, W0, g, coupling on or off, tilt or tube director."""
+    rs = np.random.default_rng(1000 + seed)
+    periodic = bool(rs.random() < 0.25)
+    nx, ny = int(rs.integers(5, 71)), int(rs.integers(3, 41))
+    nz = int(rs.integers(4, 15))
+    r = int(rs.integers(1, 6))
+    tau = float(rs.uniform(0.55, 1.4))
+    scale = float(rs.uniform(0.05, 0.4)) / inputs.TABLE1_ALPHA[3]
+    alpha = tuple(a * scale for a in inputs.TABLE1_ALPHA)
+    gamma1 = alpha[2] - alpha[1]
+    K = float(rs.uniform(0.1, 1.0)) * 2 * gamma1 / (12 * r) * 0.9
+    q0 = float(rs.choice([0.0, 2 * math.pi / rs.integers(8, 33)]))
+    prob = inputs.Problem(nx=nx, ny=ny, nz=nz, tau=tau, alpha=alpha, alpha4p=float(rs.uniform(0.0, 0.03)),
+                          g=tuple(float(v) for v in rs.uniform(-3e-6, 3e-6, 3) * (1, 1, periodic)), K=K, q0=q0,
+                          W0=float(rs.choice([0.0, 1e-4])), fd_ratio=r, periodic_z=periodic,
+                          coupling=bool(rs.random() < 0.85))
+    if rs.random() < 0.5:
+        n0 = inputs.director_tilt(prob, seed=seed, amplitude=float(rs.uniform(0.05, 0.4)))
+    else:
+        n0 = inputs.director_tubes(prob, [(nx * rs.random(), ny * rs.random())], min(nx, ny) / 3.0)
+    T = int(rs.integers(r, 4 * r + 6))
+    return prob, n0, T
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_lattices_match_oracle(seed):
+    """Seeded random configurations: FP64 and FP64-shifted against the oracle
+    to rounding, FP32-shifted against FP64-shifted within the targets."""
+    prob, n0, T = _random_case(seed)
+    _say(f"random case {seed}: {prob.nx}x{prob.ny}x{prob.nz} periodic_z={prob.periodic_z} r={prob.fd_ratio} "
+         f"tau={prob.tau:.3f} coupling={prob.coupling} T={T}")
+    assert el.validate(el.make_params(prob, "f64")) == el.EL_OK
+    for precision, shifted in (("f64", False), ("f64_shifted", True)):
+        lat = _gpu(prob, n0, precision, T)
+        o = _oracle(prob, n0, T, shifted=shifted)
+        assert lat.step == o.t == T
+        tol = 1e-9 if not shifted else 1e-11  # unshifted loses max|q|/|u| ulps in the momentum sums
+        assert rel_l2(lat.get("u"), o.get("u")) < tol, precision
+        assert rel_l2(lat.get("n"), o.get("n")) < 1e-12, precision
+        if prob.coupling:
+            assert rel_l2(lat.get("F"), o.get("F")) < 100 * tol, precision
+        assert rel_l2(lat.get("q"), o.get("q")) < tol, precision
+    ref = _gpu(prob, n0, "f64_shifted", T)
+    lat32 = _gpu(prob, n0, "f32_shifted", T)
+    assert rel_l2(lat32.get("u"), ref.get("u")) < 1e-4
+    assert rel_l2(lat32.get("n"), ref.get("n")) < 1e-5
