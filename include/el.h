@@ -144,6 +144,13 @@ typedef struct {
 /* Library version (EL_ABI_VERSION). */
 int el_version(void);
 
+/* Bandwidth reference, not part of the method: copies `bytes` (a multiple of
+ * 16; src and dst 16-byte aligned, not overlapping, device memory) with a
+ * grid-stride loop of 16-byte non-temporal loads and stores, so that the HBM
+ * rate of a plain stream on this device can be measured beside the kernels'
+ * (bench.py --calibrate-copy).  EL_EINVAL for NULL or a bad size. */
+int el_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
 /* Human-readable text of a status code; static storage. */
 const char* el_strerror(int status);
 

@@ -257,6 +257,21 @@ extern "C" {
 
 int el_version(void) { return EL_ABI_VERSION; }
 
+int el_stream_copy(void* dst, const void* src, size_t bytes, void* stream)
+{
+    if (!dst || !src) return fail(EL_EINVAL, "NULL pointer");
+    if (bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16 != 0)
+        return fail(EL_EINVAL, "size and addresses must be multiples of 16 bytes");
+    const size_t n = bytes / 16;
+    if (n == 0) return EL_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t want = (n + BLOCK - 1) / BLOCK;
+    const int grid = (int)std::min<size_t>(want, 256 * 64);
+    hipLaunchKernelGGL(el::k_stream_copy, dim3(grid), dim3(BLOCK), 0, st, static_cast<el::copy_vec*>(dst),
+                       static_cast<const el::copy_vec*>(src), n);
+    return check_launch("k_stream_copy");
+}
+
 const char* el_strerror(int status)
 {
     switch (status) {

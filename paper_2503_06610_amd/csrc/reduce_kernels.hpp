@@ -282,4 +282,15 @@ static __global__ void __launch_bounds__(RED_THREADS) k_err_final(const double* 
         for (int j = 0; j < nout; ++j) out[j] = v[j];
 }
 
+// Plain device copy (bandwidth reference): 16-byte non-temporal loads and
+// stores, grid-stride.
+typedef float copy_vec __attribute__((ext_vector_type(4)));
+
+static __global__ void __launch_bounds__(256) k_stream_copy(copy_vec* __restrict__ dst,
+                                                            const copy_vec* __restrict__ src, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
 }  // namespace el

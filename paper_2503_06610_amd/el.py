@@ -30,7 +30,7 @@ EXPORTED = ("el_version", "el_strerror", "el_last_error", "el_buffer_bytes", "el
             "el_batch_moments", "el_batch_observables", "el_batch_sync", "el_batch_get_tuning", "el_batch_destroy",
             "el_nn_input", "el_nn_conv_forward", "el_nn_conv_backward_data", "el_nn_work_bytes",
             "el_nn_conv_backward_weight", "el_nn_mse", "el_nn_adam", "el_nn_velocity", "el_halo_pack",
-            "el_halo_unpack")
+            "el_halo_unpack", "el_stream_copy")
 
 
 class ElError(RuntimeError):
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH):
         "el_error_norms": (C.c_int, [P, V, V, C.c_int32, V, V, V]),
         "el_tube_drift": (C.c_int, [P, S, V, V]),
         "el_halo_pack": (C.c_int, [P, S, V, V]),
+        "el_stream_copy": (C.c_int, [V, V, C.c_size_t, V]),
         "el_halo_unpack": (C.c_int, [P, S, V, V, V]),
         "el_batch_create": (C.c_int, [P, S, C.c_int32, C.POINTER(el_batch_tuning), V, C.POINTER(C.c_void_p)]),
         "el_batch_step": (C.c_int, [V, C.c_int32, V]),
