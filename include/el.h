@@ -110,7 +110,7 @@ typedef struct {
     int64_t step;       /* LBM steps taken since el_init_lattice */
 } el_state;
 
-enum { EL_BUF_Q = 0, EL_BUF_VEC3 = 1, EL_BUF_SCRATCH = 2, EL_BUF_HALO = 3 };
+enum { EL_BUF_Q = 0, EL_BUF_VEC3 = 1, EL_BUF_SCRATCH = 2, EL_BUF_HALO = 3, EL_BUF_FD_HALO = 4 };
 
 /* FP64 observables (Sec. III error measures are in el_error_norms). */
 typedef struct {
@@ -159,7 +159,8 @@ const char* el_last_error(void);
 
 /* Bytes the caller must allocate: EL_BUF_Q for each of q[0], q[1];
  * EL_BUF_VEC3 for each of n, n_pred, dndt, u, F; EL_BUF_SCRATCH for scratch;
- * EL_BUF_HALO for one el_halo_pack buffer (2 * 5 * nx * (fluid layers) T).
+ * EL_BUF_HALO for one el_halo_pack buffer (2 * 5 * nx * (fluid layers) T);
+ * EL_BUF_FD_HALO for one el_fd_halo_pack buffer (2 * 6 * nx * (fluid layers) T).
  * Returns 0 for invalid parameters. */
 size_t el_buffer_bytes(const el_params* p, int32_t which);
 
@@ -225,10 +226,9 @@ int el_run(const el_params* p, el_state* s, int64_t T, void* stream);
  * through its two y faces, the buffers are exchanged (on one device: plain
  * device memory; across devices: the collective of the caller's choice),
  * and each slab unpacks what its neighbours sent.  The LBM state is then
- * identical to that of the unsplit lattice.  Only the distributions are
- * exchanged: the finite-difference stencils need one-node halos of n, u,
- * n_pred and the stress as well, which these calls do not provide, so a
- * split run is exact for the LBM part (EL_NO_COUPLING, or F^LC given).
+ * identical to that of the unsplit lattice.  The finite-difference step
+ * (Sec. II A, II B) has its own exchange: el_fd_halo_pack / el_fd_stage
+ * below.
  *
  * el_halo_pack: out (device, el_buffer_bytes(p, EL_BUF_HALO) bytes) =
  *   [0][d][zf][x]: q of the five e_y = +1 directions (3, 7, 10, 15, 17) in
@@ -244,6 +244,33 @@ int el_run(const el_params* p, el_state* s, int64_t T, void* stream);
  * Both act on q[parity]; buffers may not alias q.  EL_EINVAL for NULL. */
 int el_halo_pack(const el_params* p, const el_state* s, void* out, void* stream);
 int el_halo_unpack(const el_params* p, el_state* s, const void* lower, const void* upper, void* stream);
+
+/* The finite-difference update of a y-split lattice (Sec. II A Heun step,
+ * Sec. II B force), in four stages; each slab's stencils read the rows of
+ * its neighbours across its y faces instead of wrapping inside the slab:
+ *   stage 0  predictor:  n_pred, dndt <- n, u
+ *   stage 1  corrector:  n <- n_pred, u, dndt (normalised)
+ *   stage 2  stress:     sigma (in scratch) <- n, u
+ *   stage 3  divergence: F <- sigma
+ * For each stage in order: every slab calls el_fd_halo_pack(stage), the
+ * buffers are exchanged, then every slab calls el_fd_stage(stage) with the
+ * buffers of the slabs below (lower) and above (upper).  After el_moments on
+ * every slab, the four stages give the same n, n_pred, dndt and F, bit for
+ * bit, as el_step_director on the unsplit lattice.  A slab that is its own
+ * neighbour (lower = upper = its own buffer) reproduces el_step_director.
+ *
+ * el_fd_halo_pack: out (device, el_buffer_bytes(p, EL_BUF_FD_HALO) bytes) =
+ *   [0][c][zf][x]: row y = 0, [1][c][zf][x]: row y = ny - 1 of the stage's
+ *   inputs read across y: stages 0 and 2: n (c = 0..2) and u (c = 3..5);
+ *   stage 1: n_pred and u; stage 3: sigma_a1, a = 0..2 (c = 0..2; the halves
+ *   are then 3 * nx * (fluid layers) apart).
+ * el_fd_stage: the stage on this slab, with lower[1] (the row below y = 0)
+ *   and upper[0] (the row above y = ny - 1).  EL_FREEZE_DIRECTOR makes
+ *   stages 0 and 1 no-ops; EL_NO_COUPLING makes stage 2 a no-op and stage 3
+ *   clear F.  Buffers may not alias the state.
+ * EL_EINVAL for a stage outside 0..3 or a NULL buffer. */
+int el_fd_halo_pack(const el_params* p, const el_state* s, int32_t stage, void* out, void* stream);
+int el_fd_stage(const el_params* p, el_state* s, int32_t stage, const void* lower, const void* upper, void* stream);
 
 /* FP64 observables of the current state into out (device memory, one el_obs).
  * Uses the first 128 KiB of s->scratch. */

@@ -253,6 +253,62 @@ int error_impl(const el_params* p, const void* a, const double* ref, int ncomp, 
 }  // namespace
 
 // ==========================================================================
+namespace {
+
+// the y-slab finite-difference stages
+template <typename T>
+int fd_face_pack_impl(const el_params* p, const el_state* s, int stage, T* out, hipStream_t st)
+{
+    const el::Geom g = geom_of(p);
+    const T* f0 = stage == 1 ? static_cast<const T*>(s->n_pred) : static_cast<const T*>(s->n);
+    const T* f1 = static_cast<const T*>(s->u);
+    if (stage == 3) {
+        f0 = sigma_of<T>(s);
+        f1 = nullptr;
+    }
+    const int nc = el::fd_face_comps(stage);
+    hipLaunchKernelGGL(el::k_fd_face_pack<T>, dim3((nc * g.nx * g.nzf + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, f0,
+                       f1, out, g, stage);
+    return check_launch("k_fd_face_pack");
+}
+
+template <typename T>
+int fd_stage_impl(const el_params* p, el_state* s, int stage, const T* lower, const T* upper, hipStream_t st)
+{
+    const el::FdArgs<T> a = fd_args<T>(p);
+    if (stage <= 1 && (p->flags & EL_FREEZE_DIRECTOR)) return EL_OK;
+    if (stage >= 2 && !coupling(p)) {
+        if (stage == 2) return EL_OK;
+        hipLaunchKernelGGL((el::k_fill<T>), dim3(grid_for(3 * a.g.N)), dim3(BLOCK), 0, st, static_cast<T*>(s->F),
+                           T(0), 3 * a.g.N);
+        return check_launch("clear F");
+    }
+    // the slab below sent its row ny - 1 in the second half of its buffer,
+    // the slab above its row 0 in the first half
+    const T* lo = lower + (size_t)el::fd_face_comps(stage) * a.g.nx * a.g.nzf;
+    const T* hi = upper;
+    T* n = static_cast<T*>(s->n);
+    T* nP = static_cast<T*>(s->n_pred);
+    T* dndt = static_cast<T*>(s->dndt);
+    const T* u = static_cast<const T*>(s->u);
+    T* sig = sigma_of<T>(s);
+    const dim3 grid(grid_for(a.g.N));
+    const int strip = fd_strip(a.g);
+    switch (stage) {
+    case 0: hipLaunchKernelGGL((el::k_fd_slab<T, 0>), grid, dim3(BLOCK), 0, st, n, u, nP, dndt, a, lo, hi, strip); break;
+    case 1: hipLaunchKernelGGL((el::k_fd_slab<T, 1>), grid, dim3(BLOCK), 0, st, nP, u, n, dndt, a, lo, hi, strip); break;
+    case 2:
+        hipLaunchKernelGGL((el::k_fd_slab<T, 2>), grid, dim3(BLOCK), 0, st, n, u, sig, nullptr, a, lo, hi, strip);
+        break;
+    default:
+        hipLaunchKernelGGL((el::k_fd_slab<T, 3>), grid, dim3(BLOCK), 0, st, sig, nullptr, static_cast<T*>(s->F),
+                           nullptr, a, lo, hi, strip);
+    }
+    return check_launch("k_fd_slab");
+}
+
+}  // namespace
+
 extern "C" {
 
 int el_version(void) { return EL_ABI_VERSION; }
@@ -297,6 +353,7 @@ size_t el_buffer_bytes(const el_params* p, int32_t which)
     case EL_BUF_VEC3: return 3 * N * ts;
     case EL_BUF_SCRATCH: return REDUCE_BYTES + 9 * N * ts;
     case EL_BUF_HALO: return 2 * 5 * (size_t)p->nx * (size_t)nzf_of(p) * ts;
+    case EL_BUF_FD_HALO: return 2 * 6 * (size_t)p->nx * (size_t)nzf_of(p) * ts;
     default: fail(EL_EINVAL, "unknown buffer kind %d", which); return 0;
     }
 }
@@ -429,6 +486,32 @@ int el_halo_unpack(const el_params* p, el_state* s, const void* lower, const voi
         hipLaunchKernelGGL(el::k_halo_unpack<float>, grid, dim3(BLOCK), 0, st, static_cast<float*>(s->q[s->parity]),
                            static_cast<const float*>(lower), static_cast<const float*>(upper), g);
     return check_launch("k_halo_unpack");
+}
+
+int el_fd_halo_pack(const el_params* p, const el_state* s, int32_t stage, void* out, void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if ((rc = state_checks(p, s)) != EL_OK) return rc;
+    if (stage < 0 || stage > 3) return fail(EL_EINVAL, "FD stage %d (0..3)", stage);
+    if (!out) return fail(EL_EINVAL, "halo buffer is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (is_f64(p)) return fd_face_pack_impl<double>(p, s, stage, static_cast<double*>(out), st);
+    return fd_face_pack_impl<float>(p, s, stage, static_cast<float*>(out), st);
+}
+
+int el_fd_stage(const el_params* p, el_state* s, int32_t stage, const void* lower, const void* upper, void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if ((rc = state_checks(p, s)) != EL_OK) return rc;
+    if (stage < 0 || stage > 3) return fail(EL_EINVAL, "FD stage %d (0..3)", stage);
+    if (!lower || !upper) return fail(EL_EINVAL, "halo buffer is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (is_f64(p))
+        return fd_stage_impl<double>(p, s, stage, static_cast<const double*>(lower), static_cast<const double*>(upper),
+                                     st);
+    return fd_stage_impl<float>(p, s, stage, static_cast<const float*>(lower), static_cast<const float*>(upper), st);
 }
 
 int el_observables(const el_params* p, const el_state* s, el_obs* out, void* stream)

@@ -11,6 +11,7 @@
 #include "el.h"
 #include "el_common.hpp"
 #include "fd_kernels.hpp"
+#include "fd_slab.hpp"
 #include "halo_kernels.hpp"
 #include "lbm_kernels.hpp"
 #include "reduce_kernels.hpp"

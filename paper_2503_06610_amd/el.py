@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libel.so")
 EL_OK, EL_EINVAL, EL_EUNSTABLE, EL_EDEVICE, EL_ENAN, EL_ENOMEM = 0, -1, -2, -3, -4, -5
 EL_F64, EL_F64_SHIFTED, EL_F32, EL_F32_SHIFTED = 0, 1, 2, 3
 EL_PERIODIC_Z, EL_NO_COUPLING, EL_NO_RENORM_PREDICTOR, EL_ALLOW_UNSTABLE, EL_FREEZE_DIRECTOR = 1, 2, 4, 8, 16
-EL_BUF_Q, EL_BUF_VEC3, EL_BUF_SCRATCH, EL_BUF_HALO = 0, 1, 2, 3
+EL_BUF_Q, EL_BUF_VEC3, EL_BUF_SCRATCH, EL_BUF_HALO, EL_BUF_FD_HALO = 0, 1, 2, 3, 4
 
 PRECISIONS = {"f64": EL_F64, "f64_shifted": EL_F64_SHIFTED, "f32": EL_F32, "f32_shifted": EL_F32_SHIFTED}
 
@@ -30,7 +30,7 @@ EXPORTED = ("el_version", "el_strerror", "el_last_error", "el_buffer_bytes", "el
             "el_batch_moments", "el_batch_observables", "el_batch_sync", "el_batch_get_tuning", "el_batch_destroy",
             "el_nn_input", "el_nn_conv_forward", "el_nn_conv_backward_data", "el_nn_work_bytes",
             "el_nn_conv_backward_weight", "el_nn_mse", "el_nn_adam", "el_nn_velocity", "el_halo_pack",
-            "el_halo_unpack", "el_stream_copy")
+            "el_halo_unpack", "el_stream_copy", "el_fd_halo_pack", "el_fd_stage")
 
 
 class ElError(RuntimeError):
@@ -112,6 +112,8 @@ def load(path: str = LIB_PATH):
         "el_halo_pack": (C.c_int, [P, S, V, V]),
         "el_stream_copy": (C.c_int, [V, V, C.c_size_t, V]),
         "el_halo_unpack": (C.c_int, [P, S, V, V, V]),
+        "el_fd_halo_pack": (C.c_int, [P, S, C.c_int32, V, V]),
+        "el_fd_stage": (C.c_int, [P, S, C.c_int32, V, V, V]),
         "el_batch_create": (C.c_int, [P, S, C.c_int32, C.POINTER(el_batch_tuning), V, C.POINTER(C.c_void_p)]),
         "el_batch_step": (C.c_int, [V, C.c_int32, V]),
         "el_batch_capture": (C.c_int, [V, V]),
@@ -316,6 +318,21 @@ class Lattice:
     def halo_unpack(self, lower, upper, stream=None):
         _check(self.lib.el_halo_unpack(C.byref(self.params), C.byref(self.state), C.c_void_p(lower.data_ptr()),
                                        C.c_void_p(upper.data_ptr()), _stream_ptr(stream)), "el_halo_unpack")
+
+    def fd_halo_buffer(self):
+        """A device buffer for el_fd_halo_pack of this lattice."""
+        import torch
+        n = buffer_bytes(self.params, EL_BUF_FD_HALO)
+        return torch.empty(n, dtype=torch.uint8, device=self.n.device)
+
+    def fd_halo_pack(self, stage: int, out, stream=None):
+        _check(self.lib.el_fd_halo_pack(C.byref(self.params), C.byref(self.state), int(stage),
+                                        C.c_void_p(out.data_ptr()), _stream_ptr(stream)), "el_fd_halo_pack")
+
+    def fd_stage(self, stage: int, lower, upper, stream=None):
+        _check(self.lib.el_fd_stage(C.byref(self.params), C.byref(self.state), int(stage),
+                                    C.c_void_p(lower.data_ptr()), C.c_void_p(upper.data_ptr()), _stream_ptr(stream)),
+               "el_fd_stage")
 
     def get(self, name: str) -> np.ndarray:
         """Host copy (float64) of a field: q, n, nP, u, F."""

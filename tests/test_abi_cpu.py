@@ -113,6 +113,7 @@ def test_buffer_bytes():
         assert el.buffer_bytes(p, el.EL_BUF_VEC3) == 3 * N * ts
         assert el.buffer_bytes(p, el.EL_BUF_SCRATCH) == 131072 + 9 * N * ts
         assert el.buffer_bytes(p, el.EL_BUF_HALO) == 2 * 5 * prob.nx * prob.nzf * ts
+        assert el.buffer_bytes(p, el.EL_BUF_FD_HALO) == 2 * 6 * prob.nx * prob.nzf * ts
         assert el.buffer_bytes(p, 99) == 0
 
 
@@ -128,6 +129,19 @@ def test_null_arguments_are_rejected_without_device_work():
     assert lib.el_error_norms(C.byref(p), None, None, 3, None, None, None) == el.EL_EINVAL
     assert lib.el_halo_pack(C.byref(p), None, None, None) == el.EL_EINVAL
     assert lib.el_halo_unpack(C.byref(p), C.byref(s), None, None, None) == el.EL_EINVAL
+    assert lib.el_fd_halo_pack(C.byref(p), C.byref(s), 0, None, None) == el.EL_EINVAL
+    assert lib.el_fd_stage(C.byref(p), C.byref(s), 0, None, None, None) == el.EL_EINVAL
+    # a state whose (never dereferenced) buffers are set: the stage number and
+    # the face buffers are checked before any device work
+    fake = C.c_void_p(16)
+    for name in ("n", "n_pred", "dndt", "u", "F", "scratch"):
+        setattr(s, name, 16)
+    s.q[0] = s.q[1] = 16
+    for stage in (-1, 4):
+        assert lib.el_fd_halo_pack(C.byref(p), C.byref(s), stage, fake, None) == el.EL_EINVAL
+        assert lib.el_fd_stage(C.byref(p), C.byref(s), stage, fake, fake, None) == el.EL_EINVAL
+    assert lib.el_fd_halo_pack(C.byref(p), C.byref(s), 0, None, None) == el.EL_EINVAL
+    assert lib.el_fd_stage(C.byref(p), C.byref(s), 3, fake, None, None) == el.EL_EINVAL
     assert lib.el_strerror(el.EL_EUNSTABLE)
 
 

@@ -2,8 +2,10 @@
 the y-face exchange (el_halo_pack / el_halo_unpack), against the unsplit
 lattice: the distributions must be bitwise equal after every step (the
 same per-node arithmetic; only where a value is stored differs).  The
-exchange covers the streaming step, so the runs have no director coupling;
-the FD halos of a split coupled run are not provided."""
+uncoupled cases exercise the streaming exchange alone; the coupled cases add
+the finite-difference exchange (el_fd_halo_pack / el_fd_stage) and compare
+q, u, n, n_pred and F of a whole coupled run."""
+import math
 import sys
 
 import numpy as np
@@ -81,3 +83,70 @@ def test_slab_that_is_its_own_neighbour_is_unchanged():
     lat.halo_unpack(b, b)
     torch.cuda.synchronize()
     assert np.array_equal(lat.get("q"), before)
+
+
+def _fd_exchange(slabs, bufs, stages=range(4)):
+    """The finite-difference update of a split lattice: per stage, every slab
+    packs its face rows, then every slab runs the stage with its neighbours'."""
+    ns = len(slabs)
+    for stage in stages:
+        for s, b in zip(slabs, bufs):
+            s.fd_halo_pack(stage, b)
+        for k, s in enumerate(slabs):
+            s.fd_stage(stage, bufs[(k - 1) % ns], bufs[(k + 1) % ns])
+
+
+def _coupled_problem(coupling=True, r=2):
+    mat = inputs.set_a()
+    gamma1 = mat.alpha[2] - mat.alpha[1]
+    prob = inputs.channel(21, 3 * 8, 10, mat, g=(3e-6, 1e-6, 0.0), K=0.5 * 2 * gamma1 / (12 * r) * 0.9,
+                          q0=2 * math.pi / 16, W0=1e-4, fd_ratio=r, coupling=coupling)
+    # a tube centred near a slab face, so the director bends across the faces
+    n0 = inputs.director_tubes(prob, [(10.3, 7.6)], 7.0)
+    return prob, n0
+
+
+@pytest.mark.parametrize("precision,nslab,coupling", [("f32_shifted", 3, True), ("f64", 3, True),
+                                                       ("f32_shifted", 1, True), ("f32_shifted", 3, False)])
+def test_coupled_slabs_match_unsplit_lattice(precision, nslab, coupling):
+    import torch
+    prob, n0 = _coupled_problem(coupling)
+    r, T = prob.fd_ratio, 11
+    full = el.Lattice(prob, precision)
+    full.init_lattice(n0)
+    ny_s = prob.ny // nslab
+    slabs = []
+    for k in range(nslab):
+        s = el.Lattice(prob.with_(ny=ny_s), precision)
+        s.init_lattice(np.ascontiguousarray(n0[:, :, k * ny_s:(k + 1) * ny_s, :]))
+        slabs.append(s)
+    qb = [s.halo_buffer() for s in slabs]
+    fb = [s.fd_halo_buffer() for s in slabs]
+    # el_init_lattice computed F inside each slab alone; redo it across the faces
+    _fd_exchange(slabs, fb, stages=(2, 3))
+
+    def compare(when):
+        torch.cuda.synchronize()
+        for name in ("q", "u", "n", "nP", "F"):
+            nc = 19 if name == "q" else 3
+            got = np.concatenate([s.get(name).reshape(nc, prob.nzf, ny_s, prob.nx) for s in slabs], axis=2)
+            want = full.get(name).reshape(nc, prob.nzf, prob.ny, prob.nx)
+            assert np.array_equal(got, want), (precision, when, name, np.argwhere(got != want)[:5])
+
+    compare("init")
+    for step in range(1, T + 1):
+        full.run(1)
+        for s in slabs:
+            s.step_lbm(1, write_u=False)
+        for s, b in zip(slabs, qb):
+            s.halo_pack(b)
+        for k, s in enumerate(slabs):
+            s.halo_unpack(qb[(k - 1) % nslab], qb[(k + 1) % nslab])
+        for s in slabs:
+            s.moments()
+        if step % r == 0:
+            _fd_exchange(slabs, fb)
+        compare(step)
+    assert full.step == slabs[0].step == T
+    assert np.abs(full.get("F")).max() > 0 if coupling else True
+    _say(f"coupled slabs {precision} x{nslab} coupling={coupling}: {T} steps bitwise equal")
