@@ -77,8 +77,13 @@ enum {
     EL_NO_COUPLING = 2,           /* F^LC held at zero: plain Guo-forced LBM */
     EL_NO_RENORM_PREDICTOR = 4,   /* do not normalise the Heun predictor */
     EL_ALLOW_UNSTABLE = 8,        /* skip the stability checks of el_validate */
-    EL_FREEZE_DIRECTOR = 16       /* el_step_director only refreshes F^LC (quasi-steady flow
+    EL_FREEZE_DIRECTOR = 16,      /* el_step_director only refreshes F^LC (quasi-steady flow
                                      of a fixed director, used to make surrogate training pairs) */
+    EL_FORCE_ONE_PASS = 32,       /* F^LC by the one-pass kernel: the stress of a tile and its
+                                     one-node ring kept in LDS (same result, bit for bit) */
+    EL_FORCE_TWO_PASS = 64        /* F^LC as stress to scratch, then its divergence.  With
+                                     neither flag: one pass for FP64 on large lattices; both
+                                     flags: EL_EINVAL.  The ensemble calls ignore them */
 };
 
 typedef struct {
@@ -166,7 +171,7 @@ size_t el_buffer_bytes(const el_params* p, int32_t which);
 
 /* Checks the parameters.  EL_EINVAL: sizes (nx, ny >= 3; nz >= 4, or >= 3
  * with EL_PERIODIC_Z), tau <= 1/2, r < 1, gamma1 = alpha3 - alpha2 <= 0 with
- * coupling, unknown precision or flags.  EL_EUNSTABLE (unless
+ * coupling, unknown precision or flags, both force-kernel flags.  EL_EUNSTABLE (unless
  * EL_ALLOW_UNSTABLE): r * 12 K / gamma1 > 2 (the explicit Heun step on the
  * compact Laplacian); r = 1 with coupling and tau > 1.5 (the Leslie force
  * refreshed every LBM step diverges there within a few hundred steps: an

@@ -27,8 +27,11 @@ int basic_checks(const el_params* p)
     if (!p) return fail(EL_EINVAL, "params is NULL");
     if (p->precision < EL_F64 || p->precision > EL_F32_SHIFTED)
         return fail(EL_EINVAL, "unknown precision %d", p->precision);
-    if (p->flags & ~(EL_PERIODIC_Z | EL_NO_COUPLING | EL_NO_RENORM_PREDICTOR | EL_ALLOW_UNSTABLE | EL_FREEZE_DIRECTOR))
+    if (p->flags & ~(EL_PERIODIC_Z | EL_NO_COUPLING | EL_NO_RENORM_PREDICTOR | EL_ALLOW_UNSTABLE | EL_FREEZE_DIRECTOR |
+                     EL_FORCE_ONE_PASS | EL_FORCE_TWO_PASS))
         return fail(EL_EINVAL, "unknown flags 0x%x", p->flags);
+    if ((p->flags & EL_FORCE_ONE_PASS) && (p->flags & EL_FORCE_TWO_PASS))
+        return fail(EL_EINVAL, "EL_FORCE_ONE_PASS and EL_FORCE_TWO_PASS both set");
     if (p->nx < 3 || p->ny < 3 || (periodic_z(p) ? p->nz < 3 : p->nz < 4))
         return fail(EL_EINVAL, "lattice %dx%dx%d too small", p->nx, p->ny, p->nz);
     const long long N = (long long)p->nx * p->ny * nzf_of(p);
@@ -139,6 +142,15 @@ int launch_force(const el_params* p, el_state* s, hipStream_t st)
         hipLaunchKernelGGL((el::k_fill<T>), dim3(grid_for(3 * a.g.N)), dim3(BLOCK), 0, st, static_cast<T*>(s->F),
                            T(0), 3 * a.g.N);
         return check_launch("clear F");
+    }
+    const int tiles_x = (a.g.nx + el::FORCE_TX - 1) / el::FORCE_TX;
+    const int tiles_y = (a.g.ny + el::FORCE_TY - 1) / el::FORCE_TY;
+    const int chunks = (a.g.nzf + el::FORCE_ZC - 1) / el::FORCE_ZC;
+    if (one_pass_force(p, tiles_x * tiles_y * chunks)) {
+        hipLaunchKernelGGL((el::k_fd_force<T, el::FORCE_TY>), dim3(tiles_x * tiles_y * chunks),
+                           dim3(el::FORCE_TX * el::FORCE_TY), 0, st, static_cast<const T*>(s->n),
+                           static_cast<const T*>(s->u), static_cast<T*>(s->F), a, el::FORCE_ZC, tiles_x, tiles_y);
+        return check_launch("k_fd_force");
     }
     T* sig = sigma_of<T>(s);
     const int grid = grid_for(a.g.N);

@@ -11,6 +11,7 @@
 #include "el.h"
 #include "el_common.hpp"
 #include "fd_kernels.hpp"
+#include "fd_force.hpp"
 #include "fd_slab.hpp"
 #include "halo_kernels.hpp"
 #include "lbm_kernels.hpp"
@@ -65,6 +66,21 @@ inline int grid_for(int N) { return (N + BLOCK - 1) / BLOCK; }
 #ifndef EL_FD_STRIP_NODES
 #define EL_FD_STRIP_NODES 4096
 #endif
+
+// Which force kernel el_force / el_step_director run: the one-pass kernel
+// (k_fd_force, stress kept in LDS) or stress then divergence through memory.
+// Unless a flag names one, the one-pass kernel is taken for FP64 when its grid
+// has at least 512 blocks.  Measured, interleaved in one process: 256x256x46
+// fluid nodes FP64 135.5 us against 171.6 us; FP32 53.9 against 54.0; on
+// 128x128x62 the two-pass form is faster (FP32 23.5 against 24.7 us, FP64
+// 44.9 against 47.2), as the one-pass kernel evaluates the stress about 1.5x
+// over (the tile rings and chunk ends) and that evaluation, not HBM, bounds it.
+inline bool one_pass_force(const el_params* p, int blocks)
+{
+    if (p->flags & EL_FORCE_ONE_PASS) return true;
+    if (p->flags & EL_FORCE_TWO_PASS) return false;
+    return is_f64(p) && blocks >= 512;
+}
 
 inline int fd_strip(const el::Geom& g)
 {

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libel.so")
 EL_OK, EL_EINVAL, EL_EUNSTABLE, EL_EDEVICE, EL_ENAN, EL_ENOMEM = 0, -1, -2, -3, -4, -5
 EL_F64, EL_F64_SHIFTED, EL_F32, EL_F32_SHIFTED = 0, 1, 2, 3
 EL_PERIODIC_Z, EL_NO_COUPLING, EL_NO_RENORM_PREDICTOR, EL_ALLOW_UNSTABLE, EL_FREEZE_DIRECTOR = 1, 2, 4, 8, 16
+EL_FORCE_ONE_PASS, EL_FORCE_TWO_PASS = 32, 64
 EL_BUF_Q, EL_BUF_VEC3, EL_BUF_SCRATCH, EL_BUF_HALO, EL_BUF_FD_HALO = 0, 1, 2, 3, 4
 
 PRECISIONS = {"f64": EL_F64, "f64_shifted": EL_F64_SHIFTED, "f32": EL_F32, "f32_shifted": EL_F32_SHIFTED}
@@ -186,7 +187,7 @@ class Lattice:
     """Device buffers of one channel (torch tensors) and the C-ABI calls on them."""
 
     def __init__(self, prob, precision: str = "f32_shifted", device: str = "cuda", allow_unstable: bool = False,
-                 freeze_director: bool = False):
+                 freeze_director: bool = False, force_kernel: str = "auto"):
         import torch
         self.lib = load()
         self.prob = prob
@@ -196,6 +197,7 @@ class Lattice:
             self.params.flags |= EL_ALLOW_UNSTABLE
         if freeze_director:
             self.params.flags |= EL_FREEZE_DIRECTOR
+        self.params.flags |= {"auto": 0, "one_pass": EL_FORCE_ONE_PASS, "two_pass": EL_FORCE_TWO_PASS}[force_kernel]
         _check(self.lib.el_validate(C.byref(self.params)), "el_validate")
         self.dtype = torch.float64 if precision.startswith("f64") else torch.float32
         self.N = prob.fluid_nodes

@@ -70,7 +70,7 @@ def test_validate_accepts_workloads():
     ("nz", 3, el.EL_EINVAL),
     ("fd_ratio", 0, el.EL_EINVAL),
     ("precision", 7, el.EL_EINVAL),
-    ("flags", 64, el.EL_EINVAL),
+    ("flags", 128, el.EL_EINVAL),
     ("K", 0.5, el.EL_EUNSTABLE),
     ("fd_ratio", 2, el.EL_EUNSTABLE),  # C1 with K = 0.01: r*12K/gamma1 = 2.6
     ("tau", 1.9, el.EL_EUNSTABLE),     # r = 1 with tau > 1.5
@@ -95,6 +95,14 @@ def test_validate_rejects_nonpositive_gamma1_and_nan():
     p.flags |= el.EL_ALLOW_UNSTABLE
     p.K = 0.5
     assert el.validate(p) == el.EL_OK
+
+
+def test_validate_rejects_both_force_kernel_flags():
+    p = el.make_params(inputs.workload_c1()[0], "f64")
+    p.flags |= el.EL_FORCE_ONE_PASS
+    assert el.validate(p) == el.EL_OK
+    p.flags |= el.EL_FORCE_TWO_PASS
+    assert el.validate(p) == el.EL_EINVAL
 
 
 def test_validate_rejects_high_mach_and_overflowing_lattice():
