@@ -221,7 +221,11 @@ int el_force(const el_params* p, el_state* s, void* stream);
 
 /* The hybrid loop of Sec. II D for T more LBM steps: after every LBM step
  * whose counter t satisfies t % r == 0, the moments, the predictor-corrector
- * and the new force.  u is left holding the velocity of the last step. */
+ * and the new force.  u is left holding the velocity of the last step.
+ * Kernel launches only (no allocation, copy, memset or synchronisation), so
+ * a caller may capture it into a graph; the host-side counter s->step and
+ * parity then advance at capture, not at replay, and are the caller's to
+ * keep (a capture of an even number of steps leaves parity unchanged). */
 int el_run(const el_params* p, el_state* s, int64_t T, void* stream);
 
 /* y-slab exchange for a lattice split along y over several devices (the

@@ -132,6 +132,38 @@ def test_step_calls_compose_to_run():
         assert np.array_equal(a.get(name), b.get(name)), name
 
 
+@pytest.mark.parametrize("r,precision", [(1, "f32_shifted"), (3, "f64_shifted"), (4, "f32_shifted")])
+def test_el_run_captured_in_a_graph(r, precision):
+    """el_run launches kernels only, so a caller can capture it: one period
+    (r steps with the FD step, 2r when r is odd) captured into a graph and
+    replayed three times, with eager work and synchronisations between the
+    replays, equals el_run over the same steps after every replay, bit for bit."""
+    import torch
+    prob = inputs.workload_c1()[0].with_(nx=20, ny=9, nz=10, fd_ratio=r, K=1e-3)
+    n0 = inputs.director_tilt(prob, seed=6)
+    period = r if r % 2 == 0 else 2 * r
+    a = el.Lattice(prob, precision)
+    a.init_lattice(n0)
+    b = el.Lattice(prob, precision)
+    b.init_lattice(n0)
+    a.run(r)
+    b.run(r)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.run(period)  # recorded, not run: the device state stays at step r
+    parity = b.state.parity
+    for k in range(1, 4):
+        graph.replay()
+        a.run(period)
+        torch.cuda.synchronize()
+        b.state.step = r + k * period
+        assert b.state.parity == parity == a.state.parity
+        for name in ("q", "n", "nP", "u", "F"):
+            assert np.array_equal(a.get(name), b.get(name)), (k, name)
+        b.observables()  # eager work on the same buffers between replays
+
+
 def test_repeat_runs_are_bitwise_identical():
     prob, n0, _ = inputs.workload_c1()
     a = _gpu(prob, n0, "f32_shifted", 50)
