@@ -213,16 +213,20 @@ def main():
         from paper_2503_06610_amd import el
         lib = el.load()
         st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-        cp = lambda: lib.el_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), n * 4, st)
-        assert cp() == 0
+        # ping-pong between the two buffers, as the LBM alternates its two q
+        # buffers, so a working set that fits the Infinity Cache stays there
+        cp = lambda d, s: lib.el_stream_copy(ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(s.data_ptr()), n * 4, st)
+        for _ in range(3):
+            assert cp(dst, src) == 0 and cp(src, dst) == 0
         a.record()
-        for _ in range(5):
-            cp()
+        for _ in range(20):
+            cp(dst, src)
+            cp(src, dst)
         b.record()
         torch.cuda.synchronize()
-        gbs_el = 2 * n * 4 * 5 / (a.elapsed_time(b) * 1e-3) / 1e9
-        print(json.dumps({"copy_bytes_each_way": n * 4, "copies": 6, "copy_GBps_read_plus_write": round(gbs, 1),
-                          "el_stream_copy_GBps_read_plus_write": round(gbs_el, 1)}), flush=True)
+        gbs_el = 2 * n * 4 * 40 / (a.elapsed_time(b) * 1e-3) / 1e9
+        print(json.dumps({"copy_bytes_each_way": n * 4, "torch_copy_GBps_read_plus_write": round(gbs, 1),
+                          "el_stream_copy_pingpong_GBps_read_plus_write": round(gbs_el, 1)}), flush=True)
         return
     if args.workload == "c4":
         print(json.dumps(bench_batch(args)), flush=True)

@@ -151,9 +151,10 @@ int el_version(void);
 
 /* Bandwidth reference, not part of the method: copies `bytes` (a multiple of
  * 16; src and dst 16-byte aligned, not overlapping, device memory) with a
- * grid-stride loop of 16-byte non-temporal loads and stores, so that the HBM
- * rate of a plain stream on this device can be measured beside the kernels'
- * (bench.py --calibrate-copy).  EL_EINVAL for NULL or a bad size. */
+ * grid-stride loop of 16-byte non-temporal loads and ordinary stores (the
+ * LBM kernel's access mode), so that the rate of a plain stream over the same
+ * working set can be measured beside the kernels' (bench.py
+ * --calibrate-copy).  EL_EINVAL for NULL or a bad size. */
 int el_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
 
 /* Human-readable text of a status code; static storage. */

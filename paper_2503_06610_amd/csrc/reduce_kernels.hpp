@@ -282,15 +282,16 @@ static __global__ void __launch_bounds__(RED_THREADS) k_err_final(const double* 
         for (int j = 0; j < nout; ++j) out[j] = v[j];
 }
 
-// Plain device copy (bandwidth reference): 16-byte non-temporal loads and
-// stores, grid-stride.
+// Plain device copy (bandwidth reference), with the LBM kernel's access mode
+// below its streaming-store threshold: 16-byte non-temporal loads, ordinary
+// 16-byte stores, grid-stride.
 typedef float copy_vec __attribute__((ext_vector_type(4)));
 
 static __global__ void __launch_bounds__(256) k_stream_copy(copy_vec* __restrict__ dst,
                                                             const copy_vec* __restrict__ src, size_t n)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+        dst[i] = __builtin_nontemporal_load(src + i);
 }
 
 }  // namespace el
