@@ -187,8 +187,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (see DESIGN.md, "
-              "'How the path would shard').", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path; a lattice would shard "
+              "into y-slabs joined by el_halo_pack/el_halo_unpack and el_fd_halo_pack/el_fd_stage.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -6,7 +6,7 @@ velocity u_P (both as network input channels) to the residual
 (u - u_P x-hat)/V0 of the quasi-steady velocity of a frozen director.  The
 flow is then started from the equilibrium at that velocity instead of rest,
 and the solver finishes the transient; the solver is both the fallback (cold
-start) and the judge of the surrogate's error.
+start) and the reference against which the surrogate's error is measured.
 
 Everything that touches the data runs in libel.so's kernels (BF16 MFMA
 convolutions with FP32 accumulation, loss, Adam); this module allocates the
