@@ -62,13 +62,19 @@ __device__ inline void grad(const Stencil3<T>& s, T (&G)[3][3])
 
 // Molecular field of the one-constant energy f = K/2 (d n)^2 + K q0 n.curl n
 // - W0/2 n_z^2: h = K lap n - 2 K q0 curl n + W0 n_z z-hat, compact Laplacian.
+// The Laplacian is summed as differences to the centre value: a component
+// near 1 (n_z of a nearly uniform director) then loses nothing to
+// cancellation, where the neighbour sum minus 6 times the centre would lose
+// the rounding of a sum near 6 in single precision.
 template <typename T>
 __device__ inline void molecular_field(const Stencil3<T>& m, const T (&G)[3][3], const FdArgs<T>& a, T (&h)[3])
 {
     const T curl[3] = {G[1][2] - G[2][1], G[2][0] - G[0][2], G[0][1] - G[1][0]};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const T lap = ((m.v[1][c] + m.v[2][c]) + (m.v[3][c] + m.v[4][c]) + (m.v[5][c] + m.v[6][c])) - T(6) * m.v[0][c];
+        const T mc = m.v[0][c];
+        const T lap = ((m.v[1][c] - mc) + (m.v[2][c] - mc)) + ((m.v[3][c] - mc) + (m.v[4][c] - mc)) +
+                      ((m.v[5][c] - mc) + (m.v[6][c] - mc));
         h[c] = a.K * lap - a.Kq0x2 * curl[c];
     }
     h[2] += a.W0 * m.v[0][2];
