@@ -96,28 +96,32 @@ def _fd_exchange(slabs, bufs, stages=range(4)):
             s.fd_stage(stage, bufs[(k - 1) % ns], bufs[(k + 1) % ns])
 
 
-def _coupled_problem(coupling=True, r=2):
+def _coupled_problem(coupling=True, r=2, periodic_z=False):
     mat = inputs.set_a()
     gamma1 = mat.alpha[2] - mat.alpha[1]
-    prob = inputs.channel(21, 3 * 8, 10, mat, g=(3e-6, 1e-6, 0.0), K=0.5 * 2 * gamma1 / (12 * r) * 0.9,
-                          q0=2 * math.pi / 16, W0=1e-4, fd_ratio=r, coupling=coupling)
+    prob = inputs.channel(21, 3 * 8, 10, mat, g=(3e-6, 1e-6, 2e-6 if periodic_z else 0.0),
+                          K=0.5 * 2 * gamma1 / (12 * r) * 0.9, q0=2 * math.pi / 16, W0=1e-4, fd_ratio=r,
+                          coupling=coupling, periodic_z=periodic_z)
     # a tube centred near a slab face, so the director bends across the faces
     n0 = inputs.director_tubes(prob, [(10.3, 7.6)], 7.0)
     return prob, n0
 
 
-@pytest.mark.parametrize("precision,nslab,coupling", [("f32_shifted", 3, True), ("f64", 3, True),
-                                                       ("f32_shifted", 1, True), ("f32_shifted", 3, False)])
-def test_coupled_slabs_match_unsplit_lattice(precision, nslab, coupling):
+@pytest.mark.parametrize("precision,nslab,coupling,periodic_z,freeze",
+                         [("f32_shifted", 3, True, False, False), ("f64", 3, True, False, False),
+                          ("f32_shifted", 1, True, False, False), ("f32_shifted", 3, False, False, False),
+                          ("f64_shifted", 3, True, True, False), ("f32_shifted", 3, True, False, True)])
+def test_coupled_slabs_match_unsplit_lattice(precision, nslab, coupling, periodic_z, freeze):
+    """freeze: EL_FREEZE_DIRECTOR on both sides (stages 0 and 1 are no-ops)."""
     import torch
-    prob, n0 = _coupled_problem(coupling)
+    prob, n0 = _coupled_problem(coupling, periodic_z=periodic_z)
     r, T = prob.fd_ratio, 11
-    full = el.Lattice(prob, precision)
+    full = el.Lattice(prob, precision, freeze_director=freeze)
     full.init_lattice(n0)
     ny_s = prob.ny // nslab
     slabs = []
     for k in range(nslab):
-        s = el.Lattice(prob.with_(ny=ny_s), precision)
+        s = el.Lattice(prob.with_(ny=ny_s), precision, freeze_director=freeze)
         s.init_lattice(np.ascontiguousarray(n0[:, :, k * ny_s:(k + 1) * ny_s, :]))
         slabs.append(s)
     qb = [s.halo_buffer() for s in slabs]
@@ -149,4 +153,8 @@ def test_coupled_slabs_match_unsplit_lattice(precision, nslab, coupling):
         compare(step)
     assert full.step == slabs[0].step == T
     assert np.abs(full.get("F")).max() > 0 if coupling else True
-    _say(f"coupled slabs {precision} x{nslab} coupling={coupling}: {T} steps bitwise equal")
+    if freeze:  # the director never moved
+        dt = np.float32 if precision.startswith("f32") else np.float64
+        assert np.array_equal(full.get("n"), np.asarray(n0, dtype=dt).astype(np.float64))
+    _say(f"coupled slabs {precision} x{nslab} coupling={coupling} periodic_z={periodic_z} freeze={freeze}: "
+          f"{T} steps bitwise equal")
