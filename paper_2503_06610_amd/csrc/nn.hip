@@ -83,6 +83,18 @@ void launch_conv_tiled(const VolGeom& g, hipStream_t st, const __bf16* x, const 
                        cout_store);
 }
 
+// LDS-tiled 8-input-channel convolution (about 34 KB of LDS per block):
+// two blocks per compute unit, persistent over the tiles.
+template <int NT, bool RELU>
+void launch_conv_tiled8(const VolGeom& g, hipStream_t st, const __bf16* x, const __bf16* w, const float* bias, void* y)
+{
+    constexpr int lds = el::nn::conv_tiled8_lds_bytes(NT);
+    const long long tiles = (long long)g.nsamples * ((g.nzf + el::nn::CT_Z - 1) / el::nn::CT_Z) *
+                            ((g.ny + el::nn::CT_Y - 1) / el::nn::CT_Y) * ((g.nx + el::nn::CT_X - 1) / el::nn::CT_X);
+    const int grid = (int)std::max(1LL, std::min(tiles, 2LL * cu_count()));
+    hipLaunchKernelGGL((el::nn::k_conv_tiled8<NT, RELU>), dim3(grid), dim3(512), lds, st, x, w, bias, y, g);
+}
+
 template <int CIN, int MT>
 void launch_wgrad(const VolGeom& g, hipStream_t st, int nb, const __bf16* x, const __bf16* dy, float* part)
 {
@@ -146,9 +158,9 @@ int el_nn_conv_forward(const el_nn_vol* vol, int32_t cin, int32_t cout, const vo
             return fail(EL_EINVAL, "output layer needs cin = 32");
     } else if (cout == 32 && cin == 8) {
         if (relu)
-            launch_conv<8, 2, true, false>(g, st, X, W, bias, nullptr, y, 32);
+            launch_conv_tiled8<2, true>(g, st, X, W, bias, y);
         else
-            launch_conv<8, 2, false, false>(g, st, X, W, bias, nullptr, y, 32);
+            launch_conv_tiled8<2, false>(g, st, X, W, bias, y);
     } else if (cout == 32 && cin == 32) {
         if (relu)
             launch_conv_tiled<2, true, false>(g, st, X, W, bias, nullptr, y, 32);

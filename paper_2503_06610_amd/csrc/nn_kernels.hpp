@@ -364,6 +364,158 @@ __global__ void __launch_bounds__(512) k_conv_tiled(const __bf16* __restrict__ x
     }
 }
 
+// LDS-tiled convolution for 8 input channels (the network's input layer: 4
+// real channels padded to 8).  Same tiles as k_conv_tiled (32 x 4 x 4 voxels,
+// 8 waves of 4 M tiles); a voxel of the box is one 16-byte chunk, and the
+// four k-groups of an MFMA are four taps (k-step s covers taps 4 s .. 4 s + 3,
+// tap 27 is zero), so a lane reads its A fragment from the box at its own
+// tap's offset.  Box 34 x 6 x 6 x 16 B plus 7 x 4 x COUT B fragments of
+// weights: about 34 KB of LDS, several blocks per compute unit.
+__host__ __device__ constexpr int conv_tiled8_lds_bytes(int nt) { return CB_VOX * 16 + conv_lds_bytes(8, nt); }
+
+template <int NT, bool RELU>
+__global__ void __launch_bounds__(512) k_conv_tiled8(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
+                                                    const float* __restrict__ bias, void* __restrict__ y,
+                                                    VolGeom g)
+{
+    constexpr int CIN = 8;
+    constexpr int COUT = 16 * NT;
+    constexpr int KTOT = 27 * CIN;
+    constexpr int NSTEP = conv_steps(CIN);  // 7
+    extern __shared__ bf16x8 c8_lds[];
+    bf16x8* box = c8_lds;               // [CB_VOX]
+    bf16x8* wl = c8_lds + CB_VOX;       // [NSTEP][4][COUT]
+
+    for (int i = threadIdx.x; i < NSTEP * 4 * COUT; i += blockDim.x) {
+        const int co = i % COUT;
+        const int tap = i / COUT;  // = 4 s + group
+        bf16x8 v;
+        if (tap < 27) {
+            v = *reinterpret_cast<const bf16x8*>(w + (long long)co * KTOT + tap * CIN);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.0f;
+        }
+        wl[i] = v;
+    }
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int m = lane & 15;
+    const int grp = lane >> 4;
+    const int tiles_x = (g.nx + CT_X - 1) / CT_X;
+    const int tiles_y = (g.ny + CT_Y - 1) / CT_Y;
+    const int tiles_z = (g.nzf + CT_Z - 1) / CT_Z;
+    const long long per_s = (long long)tiles_z * tiles_y * tiles_x;
+    const long long ntiles = (long long)g.nsamples * per_s;
+    const long long plane = (long long)g.nx * g.ny;
+    const long long per_sample = plane * (g.nzf + 2);
+
+    constexpr int NCH = (CB_VOX + 511) / 512;
+    bf16x8 stage[NCH];
+    auto load_box = [&](long long tile) {
+        int rest = (int)(tile % per_s);
+        const int s = (int)(tile / per_s);
+        const int x0 = (rest % tiles_x) * CT_X;
+        rest /= tiles_x;
+        const int y0 = (rest % tiles_y) * CT_Y;
+        const int z0 = (rest / tiles_y) * CT_Z;
+        const __bf16* xs = x + (long long)s * per_sample * CIN;
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            const int b = (int)threadIdx.x + 512 * k;
+            const int bx = b % CB_X;
+            const int by = (b / CB_X) % CB_Y;
+            const int bz = b / (CB_X * CB_Y);
+            int xx = (x0 - 1 + bx) % g.nx;
+            xx = xx < 0 ? xx + g.nx : xx;
+            int yy = (y0 - 1 + by) % g.ny;
+            yy = yy < 0 ? yy + g.ny : yy;
+            const int zh = z0 + bz;
+            if (b < CB_VOX && zh <= g.nzf + 1) {
+                stage[k] = *reinterpret_cast<const bf16x8*>(xs + (zh * plane + (long long)yy * g.nx + xx) * CIN);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) stage[k][j] = (__bf16)0.0f;
+            }
+        }
+    };
+    if ((long long)blockIdx.x < ntiles) load_box(blockIdx.x);
+
+    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        int rest = (int)(tile % per_s);
+        const int s = (int)(tile / per_s);
+        const int x0 = (rest % tiles_x) * CT_X;
+        rest /= tiles_x;
+        const int y0 = (rest % tiles_y) * CT_Y;
+        const int z0 = (rest / tiles_y) * CT_Z;
+
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+            const int b = (int)threadIdx.x + 512 * k;
+            if (b < CB_VOX) box[b] = stage[k];
+        }
+        __syncthreads();
+        if (tile + gridDim.x < ntiles) load_box(tile + gridDim.x);
+
+        f32x4 acc[4][NT];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        int bb[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int row = 2 * wave + (mt >> 1);
+            const int ty = row % CT_Y, tz = row / CT_Y;
+            bb[mt] = ((tz + 1) * CB_Y + (ty + 1)) * CB_X + (mt & 1) * 16 + m + 1;
+        }
+#pragma unroll
+        for (int st = 0; st < NSTEP; ++st) {
+            const int tap = 4 * st + grp;
+            bf16x8 a[4], b[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) b[nt] = wl[(st * 4 + grp) * COUT + nt * 16 + m];
+            if (tap < 27) {
+                const int off = ((tap / 9 - 1) * CB_Y + ((tap / 3) % 3 - 1)) * CB_X + (tap % 3 - 1);
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) a[mt] = box[bb[mt] + off];
+            } else {
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) a[mt][j] = (__bf16)0.0f;
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
+        }
+
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int row = 2 * wave + (mt >> 1);
+            const int yy = y0 + row % CT_Y, zz = z0 + row / CT_Y;
+            if (yy >= g.ny || zz >= g.nzf) continue;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int co = nt * 16 + m;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int xx = x0 + (mt & 1) * 16 + 4 * grp + j;
+                    if (xx >= g.nx) continue;
+                    float val = acc[mt][nt][j] + (bias ? bias[co] : 0.0f);
+                    if (RELU) val = fmaxf(val, 0.0f);
+                    const long long vint = (long long)s * g.n_int + ((long long)zz * g.ny + yy) * g.nx + xx;
+                    static_cast<__bf16*>(y)[own_index(g, vint) * COUT + co] = (__bf16)val;
+                }
+            }
+        }
+    }
+}
+
 // Padded LDS row of the weight-gradient kernel: 32 voxels + 8 (80 bytes, so
 // the 16 rows read by a quarter-wave fall in distinct banks).
 constexpr int WG_ROW = 40;

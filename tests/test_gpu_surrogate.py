@@ -94,6 +94,29 @@ def test_conv_forward_matches_reference(cin_real, cin, cout_real, cout, relu):
         assert np.all(raw[:, 0] == 0) and np.all(raw[:, -1] == 0)
 
 
+@pytest.mark.parametrize("cin_real,cin", [(4, 8), (32, 32)])
+def test_conv_forward_several_full_tiles(cin_real, cin):
+    """The LDS-tiled forward kernels (32 x 4 x 4 voxel tiles) on a volume of
+    several whole tiles plus ragged ones in x, y and z, two samples."""
+    import torch
+    s, z, y, x = 2, 9, 9, 70
+    vol = el.el_nn_vol(x, y, z, s)
+    xv = _bf(RNG.normal(size=(s, cin_real, z, y, x)))
+    zpad = _bf(RNG.normal(size=cin_real))
+    w = _bf(RNG.normal(scale=0.2, size=(32, 27, cin_real)))
+    b = RNG.normal(scale=0.1, size=32).astype(np.float32)
+    wf, _ = _wpad(w, 32, cin)
+    xa = _to_act(xv, cin, zpad)
+    bt = torch.as_tensor(b).cuda()
+    ref = co.conv_forward(xv, w, b.astype(np.float64), zpad, True)
+    yt = torch.zeros(s * (z + 2) * y * x * 32, dtype=torch.bfloat16, device="cuda")
+    assert _lib().el_nn_conv_forward(C.byref(vol), cin, 32, _vp(xa), _vp(wf), _vp(bt), 1, _vp(yt), None) == 0
+    got = _from_act(yt, s, 32, z, y, x)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
+    raw = yt.to(torch.float32).cpu().numpy().reshape(s, z + 2, y, x, 32)
+    assert np.all(raw[:, 0] == 0) and np.all(raw[:, -1] == 0)
+
+
 @pytest.mark.parametrize("cout_real,cout", [(32, 32), (3, 16)])
 def test_conv_backward_data_matches_reference(cout_real, cout):
     import torch
