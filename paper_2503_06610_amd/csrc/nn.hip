@@ -61,30 +61,42 @@ void launch_conv(const VolGeom& g, hipStream_t st, const __bf16* x, const __bf16
                  const __bf16* mask, void* y, int cout_store)
 {
     constexpr int lds = el::nn::conv_lds_bytes(CIN, NT);
-    hipLaunchKernelGGL((el::nn::k_conv<CIN, NT, RELU, SOA>), dim3(conv_blocks(g)), dim3(el::nn::CONV_THREADS), lds, st,
-                       x, w, bias, mask, y, g, cout_store);
+    if (mask)
+        hipLaunchKernelGGL((el::nn::k_conv<CIN, NT, RELU, SOA, true>), dim3(conv_blocks(g)),
+                           dim3(el::nn::CONV_THREADS), lds, st, x, w, bias, mask, y, g, cout_store);
+    else
+        hipLaunchKernelGGL((el::nn::k_conv<CIN, NT, RELU, SOA, false>), dim3(conv_blocks(g)),
+                           dim3(el::nn::CONV_THREADS), lds, st, x, w, bias, mask, y, g, cout_store);
 }
 
 // LDS-tiled 32-input-channel convolution: one block of 512 threads per
 // compute unit (the input box and the weights take 106-134 KB of LDS).
-template <int NT, bool RELU, bool SOA>
-void launch_conv_tiled(const VolGeom& g, hipStream_t st, const __bf16* x, const __bf16* w, const float* bias,
-                       const __bf16* mask, void* y, int cout_store)
+template <int NT, bool RELU, bool SOA, bool MASK>
+void launch_conv_tiled_k(const VolGeom& g, hipStream_t st, const __bf16* x, const __bf16* w, const float* bias,
+                         const __bf16* mask, void* y, int cout_store)
 {
     constexpr int lds = el::nn::conv_tiled_lds_bytes(NT);
     // more than 64 KB of dynamic LDS must be allowed explicitly (idempotent)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&el::nn::k_conv_tiled<NT, RELU, SOA>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&el::nn::k_conv_tiled<NT, RELU, SOA, MASK>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     const int cus = cu_count();
     const long long tiles = (long long)g.nsamples * ((g.nzf + el::nn::CT_Z - 1) / el::nn::CT_Z) *
                             ((g.ny + el::nn::CT_Y - 1) / el::nn::CT_Y) * ((g.nx + el::nn::CT_X - 1) / el::nn::CT_X);
     const int grid = (int)std::max(1LL, std::min(tiles, (long long)cus));
-    hipLaunchKernelGGL((el::nn::k_conv_tiled<NT, RELU, SOA>), dim3(grid), dim3(512), lds, st, x, w, bias, mask, y, g,
-                       cout_store);
+    hipLaunchKernelGGL((el::nn::k_conv_tiled<NT, RELU, SOA, MASK>), dim3(grid), dim3(512), lds, st, x, w, bias, mask,
+                       y, g, cout_store);
 }
 
-// LDS-tiled 8-input-channel convolution (about 34 KB of LDS per block):
-// two blocks per compute unit, persistent over the tiles.
+template <int NT, bool RELU, bool SOA>
+void launch_conv_tiled(const VolGeom& g, hipStream_t st, const __bf16* x, const __bf16* w, const float* bias,
+                       const __bf16* mask, void* y, int cout_store)
+{
+    if (mask)
+        launch_conv_tiled_k<NT, RELU, SOA, true>(g, st, x, w, bias, mask, y, cout_store);
+    else
+        launch_conv_tiled_k<NT, RELU, SOA, false>(g, st, x, w, bias, mask, y, cout_store);
+}
+
 template <int NT, bool RELU>
 void launch_conv_tiled8(const VolGeom& g, hipStream_t st, const __bf16* x, const __bf16* w, const float* bias, void* y)
 {

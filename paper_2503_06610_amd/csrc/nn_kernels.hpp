@@ -87,7 +87,7 @@ __host__ __device__ constexpr int conv_lds_bytes(int cin, int nt) { return conv_
 // CIN in {8, 16, 32}; NT = output channels / 16 (COUT = 16 NT stored).
 // OUT_SOA: write FP32 channel-major y[co * n_all + v] for co < cout_store
 // (no halo) instead of channels-last BF16.
-template <int CIN, int NT, bool RELU, bool OUT_SOA>
+template <int CIN, int NT, bool RELU, bool OUT_SOA, bool MASK>
 __global__ void __launch_bounds__(CONV_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_conv(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
                                                       const float* __restrict__ bias, const __bf16* __restrict__ mask,
                                                       void* __restrict__ y, VolGeom g, int cout_store)
@@ -123,6 +123,9 @@ __global__ void __launch_bounds__(CONV_THREADS) __attribute__((amdgpu_waves_per_
     const int m = lane & 15;
     const int grp = lane >> 4;
     const long long nitem = (g.n_all + 16 * MT - 1) / (16 * MT);
+    float bco[NT];  // this lane's biases, loaded once
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) bco[nt] = bias ? bias[nt * 16 + m] : 0.0f;
     for (long long it = (long long)blockIdx.x * nwave + wave; it < nitem; it += (long long)gridDim.x * nwave) {
         const long long base = it * 16 * MT;
         VoxPos pos[MT];
@@ -171,9 +174,25 @@ __global__ void __launch_bounds__(CONV_THREADS) __attribute__((amdgpu_waves_per_
             for (int mt = 0; mt < MT; ++mt) a[mt] = an[mt];
         }
 
+        // Epilogue.  Stores and loads share one completion counter, so a load
+        // issued after stores makes its use wait for all of them: the bias
+        // is in registers, and with a mask (MASK) the 8 mask values of an M
+        // tile are loaded before that tile's 8 stores (unconditionally, at an
+        // in-bounds index for voxels past the end, whose stores are skipped).
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             const long long bm = base + mt * 16;
+            __bf16 mv[NT][4];
+            if (MASK) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const long long vv = bm + 4 * grp + j;
+                        mv[nt][j] = mask[own_index(g, vv < g.n_all ? vv : 0) * COUT + nt * 16 + m];
+                    }
+                asm volatile("" ::: "memory");
+            }
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int co = nt * 16 + m;
@@ -181,13 +200,13 @@ __global__ void __launch_bounds__(CONV_THREADS) __attribute__((amdgpu_waves_per_
                 for (int j = 0; j < 4; ++j) {
                     const long long vv = bm + 4 * grp + j;
                     if (vv >= g.n_all) continue;
-                    float val = acc[mt][nt][j] + (bias ? bias[co] : 0.0f);
+                    float val = acc[mt][nt][j] + bco[nt];
                     if (RELU) val = fmaxf(val, 0.0f);
                     if (OUT_SOA) {
                         if (co < cout_store) static_cast<float*>(y)[(long long)co * g.n_all + vv] = val;
                     } else {
                         const long long oi = own_index(g, vv) * COUT + co;
-                        if (mask && !((float)mask[oi] > 0.0f)) val = 0.0f;
+                        if (MASK && !((float)mv[nt][j] > 0.0f)) val = 0.0f;
                         static_cast<__bf16*>(y)[oi] = (__bf16)val;
                     }
                 }
@@ -214,7 +233,7 @@ __host__ __device__ constexpr int conv_tiled_lds_bytes(int nt) { return CB_VOX *
 
 __device__ __forceinline__ int box_slot(int b, int g) { return 4 * b + (g ^ ((b >> 1) & 3)); }
 
-template <int NT, bool RELU, bool OUT_SOA>
+template <int NT, bool RELU, bool OUT_SOA, bool MASK>
 __global__ void __launch_bounds__(512) k_conv_tiled(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
                                                    const float* __restrict__ bias, const __bf16* __restrict__ mask,
                                                    void* __restrict__ y, VolGeom g, int cout_store)
@@ -244,6 +263,9 @@ __global__ void __launch_bounds__(512) k_conv_tiled(const __bf16* __restrict__ x
     const long long ntiles = (long long)g.nsamples * per_s;
     const long long plane = (long long)g.nx * g.ny;
     const long long per_sample = plane * (g.nzf + 2);
+    float bco[NT];  // this lane's biases, loaded once
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) bco[nt] = bias ? bias[nt * 16 + m] : 0.0f;
 
     // Box of a tile, 16-byte chunk c = 4 b + g: loaded into registers by
     // every thread (NCH chunks each, all in flight together), written to
@@ -336,11 +358,26 @@ __global__ void __launch_bounds__(512) k_conv_tiled(const __bf16* __restrict__ x
             for (int nt = 0; nt < NT; ++nt) b[nt] = bn[nt];
         }
 
+        // epilogue as in k_conv (bias in registers; with MASK the mask values of
+        // an M tile before its stores)
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             const int row = 2 * wave + (mt >> 1);
             const int yy = y0 + row % CT_Y, zz = z0 + row / CT_Y;
             if (yy >= g.ny || zz >= g.nzf) continue;
+            __bf16 mv[NT][4];
+            if (MASK) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int xx = x0 + (mt & 1) * 16 + 4 * grp + j;
+                        const long long vint =
+                            xx < g.nx ? (long long)s * g.n_int + ((long long)zz * g.ny + yy) * g.nx + xx : 0;
+                        mv[nt][j] = mask[own_index(g, vint) * COUT + nt * 16 + m];
+                    }
+                asm volatile("" ::: "memory");
+            }
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int co = nt * 16 + m;
@@ -348,14 +385,14 @@ __global__ void __launch_bounds__(512) k_conv_tiled(const __bf16* __restrict__ x
                 for (int j = 0; j < 4; ++j) {
                     const int xx = x0 + (mt & 1) * 16 + 4 * grp + j;
                     if (xx >= g.nx) continue;
-                    float val = acc[mt][nt][j] + (bias ? bias[co] : 0.0f);
+                    float val = acc[mt][nt][j] + bco[nt];
                     if (RELU) val = fmaxf(val, 0.0f);
                     const long long vint = (long long)s * g.n_int + ((long long)zz * g.ny + yy) * g.nx + xx;
                     if (OUT_SOA) {
                         if (co < cout_store) static_cast<float*>(y)[(long long)co * g.n_all + vint] = val;
                     } else {
                         const long long oi = own_index(g, vint) * COUT + co;
-                        if (mask && !((float)mask[oi] > 0.0f)) val = 0.0f;
+                        if (MASK && !((float)mv[nt][j] > 0.0f)) val = 0.0f;
                         static_cast<__bf16*>(y)[oi] = (__bf16)val;
                     }
                 }
@@ -410,6 +447,9 @@ __global__ void __launch_bounds__(512) k_conv_tiled8(const __bf16* __restrict__ 
     const long long ntiles = (long long)g.nsamples * per_s;
     const long long plane = (long long)g.nx * g.ny;
     const long long per_sample = plane * (g.nzf + 2);
+    float bco[NT];  // this lane's biases, loaded once (no load between the epilogue's stores)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) bco[nt] = bias ? bias[nt * 16 + m] : 0.0f;
 
     constexpr int NCH = (CB_VOX + 511) / 512;
     bf16x8 stage[NCH];
@@ -506,7 +546,7 @@ __global__ void __launch_bounds__(512) k_conv_tiled8(const __bf16* __restrict__ 
                 for (int j = 0; j < 4; ++j) {
                     const int xx = x0 + (mt & 1) * 16 + 4 * grp + j;
                     if (xx >= g.nx) continue;
-                    float val = acc[mt][nt][j] + (bias ? bias[co] : 0.0f);
+                    float val = acc[mt][nt][j] + bco[nt];
                     if (RELU) val = fmaxf(val, 0.0f);
                     const long long vint = (long long)s * g.n_int + ((long long)zz * g.ny + yy) * g.nx + xx;
                     static_cast<__bf16*>(y)[own_index(g, vint) * COUT + co] = (__bf16)val;
