@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(CONV_THREADS) __attribute__((amdgpu_waves_per_
     }
 }
 
-// LDS-tiled convolution for 32 input channels.  A block (512 threads) owns
+// LDS-tiled convolution for 32 input channels.  A block (64 WAVES threads) owns
 // tiles of TX x TY x TZ = 32 x 4 x 4 voxels of one sample; per tile it stages
 // the input box with a one-voxel halo (34 x 6 x 6 voxels x 32 channels,
 // periodic in x and y, the halo planes in z) into LDS once, so the 27 taps
@@ -223,8 +223,8 @@ __global__ void __launch_bounds__(CONV_THREADS) __attribute__((amdgpu_waves_per_
 // times.  The 16-byte channel group g of box voxel b sits at slot
 // 4 b + (g ^ ((b >> 2) & 3)): the 16 lanes of a quarter-wave read 16
 // consecutive voxels of one group, which this swizzle spreads over all 64
-// banks.  Weights as in k_conv (B fragments in LDS).  Wave w computes rows
-// (ty, tz) = 2w, 2w + 1 of the tile, two 16-voxel halves each (4 M tiles).
+// banks.  Weights as in k_conv (B fragments in LDS).  Wave w computes 16 / WAVES
+// rows (ty, tz) of the tile from row 16 w / WAVES on, two 16-voxel halves each.
 constexpr int CT_X = 32, CT_Y = 4, CT_Z = 4;
 constexpr int CB_X = CT_X + 2, CB_Y = CT_Y + 2, CB_Z = CT_Z + 2;
 constexpr int CB_VOX = CB_X * CB_Y * CB_Z;
@@ -233,12 +233,16 @@ __host__ __device__ constexpr int conv_tiled_lds_bytes(int nt) { return CB_VOX *
 
 __device__ __forceinline__ int box_slot(int b, int g) { return 4 * b + (g ^ ((b >> 1) & 3)); }
 
-template <int NT, bool RELU, bool OUT_SOA, bool MASK>
-__global__ void __launch_bounds__(512) k_conv_tiled(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
-                                                   const float* __restrict__ bias, const __bf16* __restrict__ mask,
-                                                   void* __restrict__ y, VolGeom g, int cout_store)
+template <int NT, bool RELU, bool OUT_SOA, bool MASK, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_conv_tiled(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
+                                                          const float* __restrict__ bias,
+                                                          const __bf16* __restrict__ mask, void* __restrict__ y,
+                                                          VolGeom g, int cout_store)
 {
     constexpr int CIN = 32;
+    constexpr int NTHR = 64 * WAVES;
+    constexpr int RPW = 16 / WAVES;  // tile rows (ty, tz) per wave
+    constexpr int MTW = 2 * RPW;     // 16-voxel M tiles per wave
     constexpr int COUT = 16 * NT;
     constexpr int KTOT = 27 * CIN;
     extern __shared__ bf16x8 ct_lds[];
@@ -271,7 +275,7 @@ __global__ void __launch_bounds__(512) k_conv_tiled(const __bf16* __restrict__ x
     // every thread (NCH chunks each, all in flight together), written to
     // LDS after the previous tile's MFMAs, so the loads of tile i + 1
     // overlap the arithmetic of tile i.
-    constexpr int NCH = (CB_VOX * 4 + 511) / 512;
+    constexpr int NCH = (CB_VOX * 4 + NTHR - 1) / NTHR;
     bf16x8 stage[NCH];
     auto load_box = [&](long long tile) {
         int rest = (int)(tile % per_s);
@@ -283,7 +287,7 @@ __global__ void __launch_bounds__(512) k_conv_tiled(const __bf16* __restrict__ x
         const __bf16* xs = x + (long long)s * per_sample * CIN;
 #pragma unroll
         for (int k = 0; k < NCH; ++k) {
-            const int c = (int)threadIdx.x + 512 * k;
+            const int c = (int)threadIdx.x + NTHR * k;
             const int b = c >> 2;
             const int gi = c & 3;
             const int bx = b % CB_X;
@@ -315,45 +319,45 @@ __global__ void __launch_bounds__(512) k_conv_tiled(const __bf16* __restrict__ x
         __syncthreads();  // the previous tile's box reads are done (and the weights are staged)
 #pragma unroll
         for (int k = 0; k < NCH; ++k) {
-            const int c = (int)threadIdx.x + 512 * k;
+            const int c = (int)threadIdx.x + NTHR * k;
             if (c < CB_VOX * 4) box[box_slot(c >> 2, c & 3)] = stage[k];
         }
         __syncthreads();
         if (tile + gridDim.x < ntiles) load_box(tile + gridDim.x);
 
-        f32x4 acc[4][NT];
+        f32x4 acc[MTW][NT];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+        for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
         // box index of this lane's voxel in M tile mt at tap (0, 0, 0) offset
-        int bb[4];
+        int bb[MTW];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const int row = 2 * wave + (mt >> 1);  // row = ty + CT_Y tz
+        for (int mt = 0; mt < MTW; ++mt) {
+            const int row = RPW * wave + (mt >> 1);  // row = ty + CT_Y tz
             const int ty = row % CT_Y, tz = row / CT_Y;
             bb[mt] = ((tz + 1) * CB_Y + (ty + 1)) * CB_X + (mt & 1) * 16 + m + 1;
         }
         // fragments of tap t + 1 are read from LDS while tap t multiplies
-        auto frags = [&](int tap, bf16x8 (&a)[4], bf16x8 (&b)[NT]) {
+        auto frags = [&](int tap, bf16x8 (&a)[MTW], bf16x8 (&b)[NT]) {
             const int off = ((tap / 9 - 1) * CB_Y + ((tap / 3) % 3 - 1)) * CB_X + (tap % 3 - 1);
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) b[nt] = wl[(tap * 4 + grp) * COUT + nt * 16 + m];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) a[mt] = box[box_slot(bb[mt] + off, grp)];
+            for (int mt = 0; mt < MTW; ++mt) a[mt] = box[box_slot(bb[mt] + off, grp)];
         };
-        bf16x8 a[4], b[NT], an[4], bn[NT];
+        bf16x8 a[MTW], b[NT], an[MTW], bn[NT];
         frags(0, a, b);
 #pragma unroll 3
         for (int tap = 0; tap < 27; ++tap) {
             if (tap + 1 < 27) frags(tap + 1, an, bn);
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
+            for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) a[mt] = an[mt];
+            for (int mt = 0; mt < MTW; ++mt) a[mt] = an[mt];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) b[nt] = bn[nt];
         }
@@ -361,8 +365,8 @@ __global__ void __launch_bounds__(512) k_conv_tiled(const __bf16* __restrict__ x
         // epilogue as in k_conv (bias in registers; with MASK the mask values of
         // an M tile before its stores)
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const int row = 2 * wave + (mt >> 1);
+        for (int mt = 0; mt < MTW; ++mt) {
+            const int row = RPW * wave + (mt >> 1);
             const int yy = y0 + row % CT_Y, zz = z0 + row / CT_Y;
             if (yy >= g.ny || zz >= g.nzf) continue;
             __bf16 mv[NT][4];
