@@ -153,6 +153,16 @@ def test_null_arguments_are_rejected_without_device_work():
     assert lib.el_strerror(el.EL_EUNSTABLE)
 
 
+def test_stream_copy_rejects_bad_arguments_without_device_work():
+    lib = el.load()
+    fake = C.c_void_p(256)  # never dereferenced: every case fails validation first
+    assert lib.el_stream_copy(None, fake, 16, None) == el.EL_EINVAL
+    assert lib.el_stream_copy(fake, None, 16, None) == el.EL_EINVAL
+    assert lib.el_stream_copy(fake, fake, 24, None) == el.EL_EINVAL          # not a multiple of 16 bytes
+    assert lib.el_stream_copy(C.c_void_p(264), fake, 16, None) == el.EL_EINVAL  # misaligned destination
+    assert lib.el_stream_copy(fake, fake, 0, None) == el.EL_OK               # nothing to copy
+
+
 def test_surrogate_calls_reject_bad_arguments_without_device_work():
     """The el_nn_* entry points validate volumes, pointers and channel counts
     before touching the device."""

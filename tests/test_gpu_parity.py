@@ -405,3 +405,18 @@ def test_random_lattices_match_oracle(seed):
     lat32 = _gpu(prob, n0, "f32_shifted", T)
     assert rel_l2(lat32.get("u"), ref.get("u")) < 1e-4
     assert rel_l2(lat32.get("n"), ref.get("n")) < 1e-5
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 * 16 + 48, 3 * (1 << 20) + 16 * 7])
+def test_stream_copy_copies_exactly(nbytes):
+    """el_stream_copy (the bandwidth reference): byte-exact copy, nothing
+    written beyond the requested bytes."""
+    import ctypes
+    import torch
+    src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros(nbytes + 64, dtype=torch.uint8, device="cuda")
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert el.load().el_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes, st) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:nbytes], src)
+    assert int(dst[nbytes:].count_nonzero()) == 0
