@@ -611,7 +611,9 @@ int el_batch_create(const el_params* params, el_state* states, int32_t nchan, co
     b->precision = params[0].precision;
     b->params.assign(params, params + nchan);
     b->states0.assign(states, states + nchan);
-    (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, 0);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (b->cus <= 0) b->cus = 256;
     hipStream_t st = static_cast<hipStream_t>(stream);
     int rc;
@@ -635,7 +637,7 @@ int el_batch_step(el_batch* b, int32_t nsteps, void* stream)
     if (nsteps < 0) return fail(EL_EINVAL, "nsteps = %d", nsteps);
     hipStream_t st = static_cast<hipStream_t>(stream);
     for (int i = 0; i < nsteps; ++i) {
-        if (!b->execs.empty()) {
+        if (b->execs.size() == (size_t)(b->period > 0 ? b->period : 1)) {
             const hipGraphExec_t e = b->execs[b->period > 0 ? (size_t)(b->h_t % b->period) : 0];
             if (hipGraphLaunch(e, st) != hipSuccess) return fail(EL_EDEVICE, "hipGraphLaunch failed");
         } else {
@@ -647,6 +649,19 @@ int el_batch_step(el_batch* b, int32_t nsteps, void* stream)
     return EL_OK;
 }
 
+namespace {
+
+// Destroys every captured graph: the batch steps eagerly again.
+void drop_graphs(el_batch* b)
+{
+    for (hipGraphExec_t e : b->execs) (void)hipGraphExecDestroy(e);
+    for (hipGraph_t g : b->graphs) (void)hipGraphDestroy(g);
+    b->execs.clear();
+    b->graphs.clear();
+}
+
+}  // namespace
+
 int el_batch_capture(el_batch* b, void* stream)
 {
     if (!b) return fail(EL_EINVAL, "batch is NULL");
@@ -655,27 +670,33 @@ int el_batch_capture(el_batch* b, void* stream)
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
         return fail(EL_EINVAL, "the stream is already capturing");
-    for (hipGraphExec_t e : b->execs) (void)hipGraphExecDestroy(e);
-    for (hipGraph_t g : b->graphs) (void)hipGraphDestroy(g);
-    b->execs.clear();
-    b->graphs.clear();
-    // one graph per phase of the period (graph k replays steps t = k mod period)
+    drop_graphs(b);
+    // one graph per phase of the period (graph k replays steps t = k mod period);
+    // on any failure every graph is dropped, so the batch never holds a partial set
     const int ngraphs = b->period > 0 ? b->period : 1;
     for (int k = 0; k < ngraphs; ++k) {
-        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            drop_graphs(b);
             return fail(EL_EDEVICE, "hipStreamBeginCapture failed (is the stream already capturing?)");
+        }
         const int rc = dispatch_step(b, st, k);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(st, &g);
         if (rc != EL_OK) {
             if (g) (void)hipGraphDestroy(g);
+            drop_graphs(b);
             return rc;
         }
-        if (e != hipSuccess || !g) return fail(EL_EDEVICE, "hipStreamEndCapture failed");
+        if (e != hipSuccess || !g) {
+            drop_graphs(b);
+            return fail(EL_EDEVICE, "hipStreamEndCapture failed");
+        }
         b->graphs.push_back(g);
         hipGraphExec_t ex = nullptr;
-        if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess)
+        if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+            drop_graphs(b);
             return fail(EL_EDEVICE, "hipGraphInstantiate failed");
+        }
         b->execs.push_back(ex);
     }
     return EL_OK;
