@@ -23,10 +23,14 @@
  *     calling thread is returned by el_last_error().
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Work is enqueued asynchronously on it; no entry point synchronises
- *     the host with the device.
- *   - All device buffers are allocated and freed by the caller.  The library
- *     never allocates device memory on the hot path and keeps no state
- *     between calls apart from the caller-owned el_state.
+ *     the host with the device, except el_batch_create (it uploads the
+ *     ensemble's tables and times the autotuner's candidates) and
+ *     el_batch_destroy.
+ *   - All device buffers of the method are allocated and freed by the
+ *     caller.  The library never allocates device memory on the hot path;
+ *     between calls it keeps only the caller-owned el_state, the ensemble
+ *     handles of el_batch_* (their tile tables, allocated at creation) and a
+ *     per-device cache of the compute-unit count.
  *   - Layout: structure of arrays over FLUID nodes only, x fastest:
  *       element (c, x, y, zf) of a field with C components lives at
  *       c*N + x + nx*(y + ny*zf),  N = nx*ny*nzf,
@@ -355,9 +359,11 @@ int el_batch_create(const el_params* params, el_state* states, int32_t nchan, co
  * step's phase). */
 int el_batch_step(el_batch* b, int32_t nsteps, void* stream);
 
-/* Captures one batched step into a hipGraph on `stream`, a created stream
- * (not the null stream, which cannot be captured; EL_EINVAL) that is not
- * capturing already; later el_batch_step calls replay it. */
+/* Captures the batched step into hipGraphs (one per phase, see above) on
+ * `stream`, a created stream (not the null stream, which cannot be captured;
+ * EL_EINVAL) that is not capturing already; later el_batch_step calls replay
+ * them.  If any capture or instantiation fails, every graph is dropped
+ * (EL_EDEVICE) and the batch keeps stepping without graphs. */
 int el_batch_capture(el_batch* b, void* stream);
 
 /* Leaves u of every channel as el_run would: the velocity after the last LBM
