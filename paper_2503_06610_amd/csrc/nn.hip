@@ -100,6 +100,13 @@ void launch_conv_tiled(const VolGeom& g, hipStream_t st, const __bf16* x, const 
         launch_conv_tiled_k<NT, RELU, SOA, false>(g, st, x, w, bias, mask, y, cout_store);
 }
 
+void launch_conv_out3(const VolGeom& g, hipStream_t st, const __bf16* x, const __bf16* w, const float* bias, float* y)
+{
+    const long long blocks = (long long)g.nsamples * ((g.nzf + el::nn::CO_ZC - 1) / el::nn::CO_ZC) *
+                             ((g.ny + el::nn::CO_TY - 1) / el::nn::CO_TY) * ((g.nx + el::nn::CO_TX - 1) / el::nn::CO_TX);
+    hipLaunchKernelGGL(el::nn::k_conv_out3, dim3((unsigned)blocks), dim3(256), 0, st, x, w, bias, y, g);
+}
+
 template <int NT, bool RELU>
 void launch_conv_tiled8(const VolGeom& g, hipStream_t st, const __bf16* x, const __bf16* w, const float* bias, void* y)
 {
@@ -168,7 +175,7 @@ int el_nn_conv_forward(const el_nn_vol* vol, int32_t cin, int32_t cout, const vo
     if (cout == 3) {
         if (relu) return fail(EL_EINVAL, "the FP32 output layer has no activation");
         if (cin == 32)
-            launch_conv_tiled<1, false, true>(g, st, X, W, bias, nullptr, y, 3);
+            launch_conv_out3(g, st, X, W, bias, static_cast<float*>(y));
         else
             return fail(EL_EINVAL, "output layer needs cin = 32");
     } else if (cout == 32 && cin == 8) {

@@ -405,6 +405,161 @@ __global__ void __launch_bounds__(64 * WAVES) k_conv_tiled(const __bf16* __restr
     }
 }
 
+// Output layer (32 -> 3 channels, FP32 channel-major output, no activation)
+// as a product per tap followed by a shift-and-add.  With P_t(u)[c] =
+// sum_ci w[c][t][ci] x(u)[ci], the layer is y(v)[c] = bias[c] + sum_t
+// P_t(v + d_t)[c]: one MFMA k-step (32 input channels) per 16 voxels gives
+// 16 of the 27 (tap, channel) columns of one z-offset, so a voxel costs
+// 3 x 2 MFMA column tiles instead of the 27 k-steps of a 16-column tile, and
+// its activations are read once instead of once per tap.
+//
+// A block of 256 threads owns a 32 x 8 column tile and CO_ZC output planes
+// of one sample.  For output plane z and z-offset dz it multiplies the
+// activations of input plane z + dz over the tile plus a one-voxel ring
+// (34 x 10 voxels, 22 M tiles) with the 27 columns of that offset, writes
+// the partials to LDS ([voxel][CO_PS] FP32), and each thread adds the nine
+// (dx, dy) partials of its output voxel.  The taps are summed in ascending
+// order and the bias added last.  The A fragments of the three input planes
+// in use stay in registers (the next one is loaded while the current plane
+// is computed), so each input plane is read once per block.
+constexpr int CO_TX = 32, CO_TY = 8, CO_ZC = 8;
+constexpr int CO_BX = CO_TX + 2, CO_BY = CO_TY + 2;
+constexpr int CO_BV = CO_BX * CO_BY;      // ring'd plane tile: 340 voxels
+constexpr int CO_MT = (CO_BV + 15) / 16;  // 22 M tiles
+constexpr int CO_MW = (CO_MT + 3) / 4;    // M tiles per wave (4 waves)
+constexpr int CO_PS = 29;                 // LDS row of the partials: 27 used, odd stride
+
+__device__ __forceinline__ int wrap_mod(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Grid: nsamples * ceil(nzf / CO_ZC) * ceil(ny / CO_TY) * ceil(nx / CO_TX)
+// blocks of 256 threads.  w: [16][27][32] (rows 3..15 unused); y: [3][n_all].
+__global__ void __launch_bounds__(256) k_conv_out3(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
+                                                  const float* __restrict__ bias, float* __restrict__ y,
+                                                  VolGeom g)
+{
+    constexpr int CIN = 32;
+    __shared__ float P[CO_MT * 16 * CO_PS];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int m = lane & 15;
+    const int grp = lane >> 4;
+
+    long long bid = blockIdx.x;
+    const int tiles_x = (g.nx + CO_TX - 1) / CO_TX;
+    const int tiles_y = (g.ny + CO_TY - 1) / CO_TY;
+    const int chunks = (g.nzf + CO_ZC - 1) / CO_ZC;
+    const int x0 = (int)(bid % tiles_x) * CO_TX;
+    bid /= tiles_x;
+    const int y0 = (int)(bid % tiles_y) * CO_TY;
+    bid /= tiles_y;
+    const int z0 = (int)(bid % chunks) * CO_ZC;
+    const int s = (int)(bid / chunks);
+    const int z1 = min(z0 + CO_ZC, g.nzf);
+    const long long plane = (long long)g.nx * g.ny;
+    const __bf16* xs = x + (long long)s * plane * (g.nzf + 2) * CIN + 8 * grp;
+
+    // B fragments of z-offset d, column tile nt: column col = 16 nt + m is
+    // (j, c) = (col / 3, col % 3), tap 9 d + j; columns 27..31 are zero.
+    bf16x8 bw[3][2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const int col = 16 * nt + m;
+            if (col < 27) {
+                bw[d][nt] = *reinterpret_cast<const bf16x8*>(w + ((long long)(col % 3) * 27 + 9 * d + col / 3) * CIN +
+                                                             8 * grp);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) bw[d][nt][k] = (__bf16)0.0f;
+            }
+        }
+    // this lane's A rows: voxel b = 16 mt + m of the ring'd tile, mt = wave + 4 i
+    int aoff[CO_MW];
+#pragma unroll
+    for (int i = 0; i < CO_MW; ++i) {
+        const int b = 16 * (wave + 4 * i) + m;
+        if (b < CO_BV) {
+            const int xx = wrap_mod(x0 - 1 + b % CO_BX, g.nx);
+            const int yy = wrap_mod(y0 - 1 + b / CO_BX, g.ny);
+            aoff[i] = yy * g.nx + xx;
+        } else {
+            aoff[i] = -1;
+        }
+    }
+    auto load_plane = [&](int zh, bf16x8 (&a)[CO_MW]) {
+        const __bf16* xp = xs + (long long)zh * plane * CIN;
+#pragma unroll
+        for (int i = 0; i < CO_MW; ++i) {
+            if (aoff[i] >= 0) {
+                a[i] = *reinterpret_cast<const bf16x8*>(xp + (long long)aoff[i] * CIN);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) a[i][k] = (__bf16)0.0f;
+            }
+        }
+    };
+    const int tx = (int)threadIdx.x % CO_TX, ty = (int)threadIdx.x / CO_TX;
+    const bool own = x0 + tx < g.nx && y0 + ty < g.ny;
+    float bc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bc[c] = bias ? bias[c] : 0.0f;
+
+    // halo'd input plane of interior z + dz is z + dz + 1 = z + d
+    bf16x8 a0[CO_MW], a1[CO_MW], a2[CO_MW], an[CO_MW];
+    load_plane(z0, a0);
+    load_plane(z0 + 1, a1);
+    load_plane(z0 + 2, a2);
+    for (int z = z0; z < z1; ++z) {
+        if (z + 1 < z1) load_plane(z + 3, an);
+        float acc[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const bf16x8(&a)[CO_MW] = d == 0 ? a0 : (d == 1 ? a1 : a2);
+            __syncthreads();  // the partials of the previous offset are read
+#pragma unroll
+            for (int i = 0; i < CO_MW; ++i) {
+                const int mt = wave + 4 * i;
+                if (mt >= CO_MT) continue;
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                    const f32x4 r =
+                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bw[d][nt], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                    const int col = 16 * nt + m;
+                    if (col < 27) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) P[(16 * mt + 4 * grp + j) * CO_PS + col] = r[j];
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const float* p = P + ((ty + dy) * CO_BX + tx + dx) * CO_PS + 3 * (3 * dy + dx);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[c] += p[c];
+                }
+        }
+        if (own) {
+            const long long vint = (long long)s * g.n_int + ((long long)z * g.ny + y0 + ty) * g.nx + x0 + tx;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) y[(long long)c * g.n_all + vint] = acc[c] + bc[c];
+        }
+#pragma unroll
+        for (int i = 0; i < CO_MW; ++i) {
+            a0[i] = a1[i];
+            a1[i] = a2[i];
+            a2[i] = an[i];
+        }
+    }
+}
+
 // LDS-tiled convolution for 8 input channels (the network's input layer: 4
 // real channels padded to 8).  Same tiles as k_conv_tiled (32 x 4 x 4 voxels,
 // 8 waves of 4 M tiles); a voxel of the box is one 16-byte chunk, and the

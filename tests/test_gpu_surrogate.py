@@ -117,6 +117,28 @@ def test_conv_forward_several_full_tiles(cin_real, cin):
     assert np.all(raw[:, 0] == 0) and np.all(raw[:, -1] == 0)
 
 
+def test_output_layer_several_full_tiles():
+    """The 32 -> 3 output layer (per-tap products over 32 x 8 column tiles and
+    8-plane chunks, then a shift-and-add) on a volume of several whole tiles
+    and ragged ones in x, y and z, two samples, nonzero halo planes."""
+    import torch
+    s, z, y, x = 2, 19, 19, 70
+    vol = el.el_nn_vol(x, y, z, s)
+    xv = _bf(RNG.normal(size=(s, 32, z, y, x)))
+    zpad = _bf(RNG.normal(size=32))
+    w = _bf(RNG.normal(scale=0.2, size=(3, 27, 32)))
+    b = RNG.normal(scale=0.1, size=16).astype(np.float32)
+    wf, _ = _wpad(w, 16, 32)
+    xa = _to_act(xv, 32, zpad)
+    bt = torch.as_tensor(b).cuda()
+    ref = co.conv_forward(xv, w, b[:3].astype(np.float64), zpad, False)
+    yt = torch.full((3 * s * z * y * x,), float("nan"), dtype=torch.float32, device="cuda")
+    assert _lib().el_nn_conv_forward(C.byref(vol), 32, 3, _vp(xa), _vp(wf), _vp(bt), 0, _vp(yt), None) == 0
+    got = yt.cpu().numpy().reshape(3, s, z, y, x).transpose(1, 0, 2, 3, 4)
+    assert np.all(np.isfinite(got))
+    assert np.abs(got - ref).max() < 1e-5 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("cout_real,cout", [(32, 32), (3, 16)])
 def test_conv_backward_data_matches_reference(cout_real, cout):
     import torch
