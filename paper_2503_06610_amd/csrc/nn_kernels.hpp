@@ -417,17 +417,17 @@ __global__ void __launch_bounds__(64 * WAVES) k_conv_tiled(const __bf16* __restr
 // of one sample.  For output plane z and z-offset dz it multiplies the
 // activations of input plane z + dz over the tile plus a one-voxel ring
 // (34 x 10 voxels, 22 M tiles) with the 27 columns of that offset, writes
-// the partials to LDS ([voxel][CO_PS] FP32), and each thread adds the nine
-// (dx, dy) partials of its output voxel.  The taps are summed in ascending
-// order and the bias added last.  The A fragments of the three input planes
-// in use stay in registers (the next one is loaded while the current plane
-// is computed), so each input plane is read once per block.
+// the partials to LDS ([column][CO_VS] FP32: a lane's four rows are one
+// 16-byte write), and each thread adds the nine (dx, dy) partials of its
+// output voxel.  The taps are summed in ascending order and the bias added
+// last.  The A fragments of the three input planes in use stay in
+// registers, so each input plane is read once per block.
 constexpr int CO_TX = 32, CO_TY = 8, CO_ZC = 8;
 constexpr int CO_BX = CO_TX + 2, CO_BY = CO_TY + 2;
 constexpr int CO_BV = CO_BX * CO_BY;      // ring'd plane tile: 340 voxels
 constexpr int CO_MT = (CO_BV + 15) / 16;  // 22 M tiles
 constexpr int CO_MW = (CO_MT + 3) / 4;    // M tiles per wave (4 waves)
-constexpr int CO_PS = 29;                 // LDS row of the partials: 27 used, odd stride
+constexpr int CO_VS = 16 * CO_MT + 4;     // LDS column of the partials (16 rows conflict-free)
 
 __device__ __forceinline__ int wrap_mod(int v, int n)
 {
@@ -442,7 +442,7 @@ __global__ void __launch_bounds__(256) k_conv_out3(const __bf16* __restrict__ x,
                                                   VolGeom g)
 {
     constexpr int CIN = 32;
-    __shared__ float P[CO_MT * 16 * CO_PS];
+    __shared__ float P[27 * CO_VS];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int m = lane & 15;
@@ -510,12 +510,11 @@ __global__ void __launch_bounds__(256) k_conv_out3(const __bf16* __restrict__ x,
     for (int c = 0; c < 3; ++c) bc[c] = bias ? bias[c] : 0.0f;
 
     // halo'd input plane of interior z + dz is z + dz + 1 = z + d
-    bf16x8 a0[CO_MW], a1[CO_MW], a2[CO_MW], an[CO_MW];
+    bf16x8 a0[CO_MW], a1[CO_MW], a2[CO_MW];
     load_plane(z0, a0);
     load_plane(z0 + 1, a1);
     load_plane(z0 + 2, a2);
     for (int z = z0; z < z1; ++z) {
-        if (z + 1 < z1) load_plane(z + 3, an);
         float acc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -530,10 +529,7 @@ __global__ void __launch_bounds__(256) k_conv_out3(const __bf16* __restrict__ x,
                     const f32x4 r =
                         __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bw[d][nt], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
                     const int col = 16 * nt + m;
-                    if (col < 27) {
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) P[(16 * mt + 4 * grp + j) * CO_PS + col] = r[j];
-                    }
+                    if (col < 27) *reinterpret_cast<f32x4*>(P + col * CO_VS + 16 * mt + 4 * grp) = r;
                 }
             }
             __syncthreads();
@@ -541,9 +537,9 @@ __global__ void __launch_bounds__(256) k_conv_out3(const __bf16* __restrict__ x,
             for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx) {
-                    const float* p = P + ((ty + dy) * CO_BX + tx + dx) * CO_PS + 3 * (3 * dy + dx);
+                    const float* p = P + 3 * (3 * dy + dx) * CO_VS + (ty + dy) * CO_BX + tx + dx;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) acc[c] += p[c];
+                    for (int c = 0; c < 3; ++c) acc[c] += p[c * CO_VS];
                 }
         }
         if (own) {
@@ -555,8 +551,8 @@ __global__ void __launch_bounds__(256) k_conv_out3(const __bf16* __restrict__ x,
         for (int i = 0; i < CO_MW; ++i) {
             a0[i] = a1[i];
             a1[i] = a2[i];
-            a2[i] = an[i];
         }
+        if (z + 1 < z1) load_plane(z + 3, a2);
     }
 }
 
