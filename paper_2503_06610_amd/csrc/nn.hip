@@ -114,6 +114,8 @@ void launch_conv_tiled8(const VolGeom& g, hipStream_t st, const __bf16* x, const
     const long long tiles = (long long)g.nsamples * ((g.nzf + el::nn::CT_Z - 1) / el::nn::CT_Z) *
                             ((g.ny + el::nn::CT_Y - 1) / el::nn::CT_Y) * ((g.nx + el::nn::CT_X - 1) / el::nn::CT_X);
     const int grid = (int)std::max(1LL, std::min(tiles, 2LL * cu_count()));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&el::nn::k_conv_tiled8<NT, RELU>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     hipLaunchKernelGGL((el::nn::k_conv_tiled8<NT, RELU>), dim3(grid), dim3(512), lds, st, x, w, bias, y, g);
 }
 

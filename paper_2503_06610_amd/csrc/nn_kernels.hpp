@@ -562,8 +562,15 @@ __global__ void __launch_bounds__(256) k_conv_out3(const __bf16* __restrict__ x,
 // four k-groups of an MFMA are four taps (k-step s covers taps 4 s .. 4 s + 3,
 // tap 27 is zero), so a lane reads its A fragment from the box at its own
 // tap's offset.  Box 34 x 6 x 6 x 16 B plus 7 x 4 x COUT B fragments of
-// weights: about 34 KB of LDS, several blocks per compute unit.
-__host__ __device__ constexpr int conv_tiled8_lds_bytes(int nt) { return CB_VOX * 16 + conv_lds_bytes(8, nt); }
+// weights, and per wave 64 output rows of 16 NT + 8 BF16 values (the
+// epilogue's transpose: the MFMA leaves a lane one channel of four voxels,
+// the stores take 16-byte channel groups of one voxel): about 75 KB of LDS
+// at NT = 2, two blocks per compute unit.
+__host__ __device__ constexpr int ep_row(int nt) { return 16 * nt + 8; }
+__host__ __device__ constexpr int conv_tiled8_lds_bytes(int nt)
+{
+    return CB_VOX * 16 + conv_lds_bytes(8, nt) + 8 * 64 * ep_row(nt) * 2;
+}
 
 template <int NT, bool RELU>
 __global__ void __launch_bounds__(512) k_conv_tiled8(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
@@ -577,6 +584,7 @@ __global__ void __launch_bounds__(512) k_conv_tiled8(const __bf16* __restrict__ 
     extern __shared__ bf16x8 c8_lds[];
     bf16x8* box = c8_lds;               // [CB_VOX]
     bf16x8* wl = c8_lds + CB_VOX;       // [NSTEP][4][COUT]
+    constexpr int EPR = ep_row(NT);
 
     for (int i = threadIdx.x; i < NSTEP * 4 * COUT; i += blockDim.x) {
         const int co = i % COUT;
@@ -689,24 +697,34 @@ __global__ void __launch_bounds__(512) k_conv_tiled8(const __bf16* __restrict__ 
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b[nt], acc[mt][nt], 0, 0, 0);
         }
 
+        // epilogue: bias, ReLU and BF16 rounding per value into this wave's
+        // LDS rows [voxel 16 mt + r][channel], then 16-byte stores of whole
+        // channel groups (the same values as element-wise stores)
+        __bf16* ep = reinterpret_cast<__bf16*>(wl + NSTEP * 4 * COUT) + wave * 64 * EPR;
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const int row = 2 * wave + (mt >> 1);
-            const int yy = y0 + row % CT_Y, zz = z0 + row / CT_Y;
-            if (yy >= g.ny || zz >= g.nzf) continue;
+        for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int co = nt * 16 + m;
+            for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int xx = x0 + (mt & 1) * 16 + 4 * grp + j;
-                    if (xx >= g.nx) continue;
                     float val = acc[mt][nt][j] + bco[nt];
                     if (RELU) val = fmaxf(val, 0.0f);
-                    const long long vint = (long long)s * g.n_int + ((long long)zz * g.ny + yy) * g.nx + xx;
-                    static_cast<__bf16*>(y)[own_index(g, vint) * COUT + co] = (__bf16)val;
+                    ep[(16 * mt + 4 * grp + j) * EPR + nt * 16 + m] = (__bf16)val;
                 }
-            }
+        __syncthreads();
+        constexpr int GPV = COUT / 8;  // 16-byte channel groups per voxel
+#pragma unroll
+        for (int k = 0; k < GPV; ++k) {
+            const int c = lane + 64 * k;
+            const int r = c / GPV, part = c % GPV;
+            const int mt = r >> 4;
+            const int row = 2 * wave + (mt >> 1);
+            const int xx = x0 + (mt & 1) * 16 + (r & 15);
+            const int yy = y0 + row % CT_Y, zz = z0 + row / CT_Y;
+            if (xx >= g.nx || yy >= g.ny || zz >= g.nzf) continue;
+            const long long vint = (long long)s * g.n_int + ((long long)zz * g.ny + yy) * g.nx + xx;
+            *reinterpret_cast<bf16x8*>(static_cast<__bf16*>(y) + own_index(g, vint) * COUT + 8 * part) =
+                *reinterpret_cast<const bf16x8*>(ep + r * EPR + 8 * part);
         }
     }
 }
