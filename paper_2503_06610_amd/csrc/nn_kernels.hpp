@@ -362,44 +362,68 @@ __global__ void __launch_bounds__(64 * WAVES) k_conv_tiled(const __bf16* __restr
             for (int nt = 0; nt < NT; ++nt) b[nt] = bn[nt];
         }
 
-        // epilogue as in k_conv (bias in registers; with MASK the mask values of
-        // an M tile before its stores)
+        if (OUT_SOA) {
+            // FP32 channel-major output (element-wise stores of cout_store channels)
 #pragma unroll
-        for (int mt = 0; mt < MTW; ++mt) {
-            const int row = RPW * wave + (mt >> 1);
-            const int yy = y0 + row % CT_Y, zz = z0 + row / CT_Y;
-            if (yy >= g.ny || zz >= g.nzf) continue;
-            __bf16 mv[NT][4];
-            if (MASK) {
+            for (int mt = 0; mt < MTW; ++mt) {
+                const int row = RPW * wave + (mt >> 1);
+                const int yy = y0 + row % CT_Y, zz = z0 + row / CT_Y;
+                if (yy >= g.ny || zz >= g.nzf) continue;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int co = nt * 16 + m;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int xx = x0 + (mt & 1) * 16 + 4 * grp + j;
+                        if (xx >= g.nx || co >= cout_store) continue;
+                        float val = acc[mt][nt][j] + bco[nt];
+                        if (RELU) val = fmaxf(val, 0.0f);
+                        const long long vint = (long long)s * g.n_int + ((long long)zz * g.ny + yy) * g.nx + xx;
+                        static_cast<float*>(y)[(long long)co * g.n_all + vint] = val;
+                    }
+                }
+            }
+        } else {
+            // BF16 channels-last output: bias, ReLU and rounding per value into
+            // this wave's rows of LDS (the box's space, once every wave is done
+            // with the box), then 16-byte stores of whole channel groups, with
+            // MASK zeroing the values whose mask is not positive
+            constexpr int EPR = COUT + 8;  // padded row: 16 lanes of a group in distinct banks
+            static_assert(WAVES * 16 * MTW * EPR * 2 <= CB_VOX * 64, "epilogue rows exceed the box");
+            __bf16* ep = reinterpret_cast<__bf16*>(box) + wave * 16 * MTW * EPR;
+            __syncthreads();
+#pragma unroll
+            for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const int xx = x0 + (mt & 1) * 16 + 4 * grp + j;
-                        const long long vint =
-                            xx < g.nx ? (long long)s * g.n_int + ((long long)zz * g.ny + yy) * g.nx + xx : 0;
-                        mv[nt][j] = mask[own_index(g, vint) * COUT + nt * 16 + m];
+                        float val = acc[mt][nt][j] + bco[nt];
+                        if (RELU) val = fmaxf(val, 0.0f);
+                        ep[(16 * mt + 4 * grp + j) * EPR + nt * 16 + m] = (__bf16)val;
                     }
-                asm volatile("" ::: "memory");
-            }
+            __syncthreads();
+            constexpr int GPV = COUT / 8;            // 16-byte channel groups per voxel
+            constexpr int PER = 16 * MTW * GPV / 64;  // groups per lane
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int co = nt * 16 + m;
+            for (int k = 0; k < PER; ++k) {
+                const int c = lane + 64 * k;
+                const int r = c / GPV, part = c % GPV;
+                const int mt = r >> 4;
+                const int row = RPW * wave + (mt >> 1);
+                const int xx = x0 + (mt & 1) * 16 + (r & 15);
+                const int yy = y0 + row % CT_Y, zz = z0 + row / CT_Y;
+                if (xx >= g.nx || yy >= g.ny || zz >= g.nzf) continue;
+                const long long vint = (long long)s * g.n_int + ((long long)zz * g.ny + yy) * g.nx + xx;
+                const long long oi = own_index(g, vint) * COUT + 8 * part;
+                bf16x8 v = *reinterpret_cast<const bf16x8*>(ep + r * EPR + 8 * part);
+                if (MASK) {
+                    const bf16x8 mv = *reinterpret_cast<const bf16x8*>(mask + oi);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int xx = x0 + (mt & 1) * 16 + 4 * grp + j;
-                    if (xx >= g.nx) continue;
-                    float val = acc[mt][nt][j] + bco[nt];
-                    if (RELU) val = fmaxf(val, 0.0f);
-                    const long long vint = (long long)s * g.n_int + ((long long)zz * g.ny + yy) * g.nx + xx;
-                    if (OUT_SOA) {
-                        if (co < cout_store) static_cast<float*>(y)[(long long)co * g.n_all + vint] = val;
-                    } else {
-                        const long long oi = own_index(g, vint) * COUT + co;
-                        if (MASK && !((float)mv[nt][j] > 0.0f)) val = 0.0f;
-                        static_cast<__bf16*>(y)[oi] = (__bf16)val;
-                    }
+                    for (int e = 0; e < 8; ++e)
+                        if (!((float)mv[e] > 0.0f)) v[e] = (__bf16)0.0f;
                 }
+                *reinterpret_cast<bf16x8*>(static_cast<__bf16*>(y) + oi) = v;
             }
         }
     }
