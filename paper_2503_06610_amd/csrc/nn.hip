@@ -60,7 +60,11 @@ template <int CIN, int NT, bool RELU, bool SOA>
 void launch_conv(const VolGeom& g, hipStream_t st, const __bf16* x, const __bf16* w, const float* bias,
                  const __bf16* mask, void* y, int cout_store)
 {
-    constexpr int lds = el::nn::conv_lds_bytes(CIN, NT);
+    constexpr int lds = el::nn::conv_generic_lds_bytes(CIN, NT);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&el::nn::k_conv<CIN, NT, RELU, SOA, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&el::nn::k_conv<CIN, NT, RELU, SOA, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (mask)
         hipLaunchKernelGGL((el::nn::k_conv<CIN, NT, RELU, SOA, true>), dim3(conv_blocks(g)),
                            dim3(el::nn::CONV_THREADS), lds, st, x, w, bias, mask, y, g, cout_store);

@@ -74,8 +74,15 @@ constexpr int CONV_MT = 4;
 // or 4/(CIN/8) taps x CIN channels.
 __host__ __device__ constexpr int conv_steps(int cin) { return (27 + 4 / (cin / 8) - 1) / (4 / (cin / 8)); }
 
-// LDS bytes of k_conv: the B fragments of every k-step, k-group and column.
+// LDS bytes of the B fragments of every k-step, k-group and column.
 __host__ __device__ constexpr int conv_lds_bytes(int cin, int nt) { return conv_steps(cin) * 4 * 16 * nt * 16; }
+
+// LDS bytes of k_conv: the B fragments and, per wave, 16 CONV_MT output rows
+// of 16 nt + 8 BF16 values for the epilogue's transpose.
+__host__ __device__ constexpr int conv_generic_lds_bytes(int cin, int nt)
+{
+    return conv_lds_bytes(cin, nt) + (CONV_THREADS / 64) * 16 * CONV_MT * (16 * nt + 8) * 2;
+}
 
 // y = act(conv(x, w) + bias) [* (mask > 0)].  Persistent blocks: the layer's
 // weights are staged once per block into LDS in B-fragment order
@@ -174,43 +181,64 @@ __global__ void __launch_bounds__(CONV_THREADS) __attribute__((amdgpu_waves_per_
             for (int mt = 0; mt < MT; ++mt) a[mt] = an[mt];
         }
 
-        // Epilogue.  Stores and loads share one completion counter, so a load
-        // issued after stores makes its use wait for all of them: the bias
-        // is in registers, and with a mask (MASK) the 8 mask values of an M
-        // tile are loaded before that tile's 8 stores (unconditionally, at an
-        // in-bounds index for voxels past the end, whose stores are skipped).
+        if (OUT_SOA) {
+            // FP32 channel-major output (element-wise stores of cout_store channels)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const long long bm = base + mt * 16;
-            __bf16 mv[NT][4];
-            if (MASK) {
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int co = nt * 16 + m;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const long long vv = base + mt * 16 + 4 * grp + j;
+                        if (vv >= g.n_all || co >= cout_store) continue;
+                        float val = acc[mt][nt][j] + bco[nt];
+                        if (RELU) val = fmaxf(val, 0.0f);
+                        static_cast<float*>(y)[(long long)co * g.n_all + vv] = val;
+                    }
+                }
+        } else {
+            // BF16 channels-last output: bias, ReLU and rounding per value into
+            // this wave's LDS rows [voxel][channel], then 16-byte stores of whole
+            // channel groups of one voxel, with MASK zeroing the values whose
+            // mask is not positive.  Only this wave uses its rows: a wave-level
+            // fence orders the writes before the reads of other lanes.
+            constexpr int EPR = COUT + 8;
+            __bf16* ep = reinterpret_cast<__bf16*>(wl + NSTEP * 4 * COUT) + wave * 16 * MT * EPR;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const long long vv = bm + 4 * grp + j;
-                        mv[nt][j] = mask[own_index(g, vv < g.n_all ? vv : 0) * COUT + nt * 16 + m];
+                        float val = acc[mt][nt][j] + bco[nt];
+                        if (RELU) val = fmaxf(val, 0.0f);
+                        ep[(16 * mt + 4 * grp + j) * EPR + nt * 16 + m] = (__bf16)val;
                     }
-                asm volatile("" ::: "memory");
-            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            constexpr int GPV = COUT / 8;            // 16-byte channel groups per voxel
+            constexpr int PER = 16 * MT * GPV / 64;  // groups per lane
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int co = nt * 16 + m;
+            for (int k = 0; k < PER; ++k) {
+                const int c = lane + 64 * k;
+                const int r = c / GPV, part = c % GPV;
+                const long long vv = base + r;
+                if (vv >= g.n_all) continue;
+                const long long oi = own_index(g, vv) * COUT + 8 * part;
+                bf16x8 v = *reinterpret_cast<const bf16x8*>(ep + r * EPR + 8 * part);
+                if (MASK) {
+                    const bf16x8 mv = *reinterpret_cast<const bf16x8*>(mask + oi);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const long long vv = bm + 4 * grp + j;
-                    if (vv >= g.n_all) continue;
-                    float val = acc[mt][nt][j] + bco[nt];
-                    if (RELU) val = fmaxf(val, 0.0f);
-                    if (OUT_SOA) {
-                        if (co < cout_store) static_cast<float*>(y)[(long long)co * g.n_all + vv] = val;
-                    } else {
-                        const long long oi = own_index(g, vv) * COUT + co;
-                        if (MASK && !((float)mv[nt][j] > 0.0f)) val = 0.0f;
-                        static_cast<__bf16*>(y)[oi] = (__bf16)val;
-                    }
+                    for (int e = 0; e < 8; ++e)
+                        if (!((float)mv[e] > 0.0f)) v[e] = (__bf16)0.0f;
                 }
+                *reinterpret_cast<bf16x8*>(static_cast<__bf16*>(y) + oi) = v;
             }
+            // the next item's rows are written after these reads (in order within the wave)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
     }
 }
