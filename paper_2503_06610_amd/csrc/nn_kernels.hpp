@@ -928,25 +928,47 @@ static __global__ void __launch_bounds__(256) k_sum_partials(const float* __rest
 }
 
 // Bias gradient partials: part[block][co] = sum over the block's chunk of dy[v][co].
+// A thread reads 16-byte channel groups (8 channels of one voxel) of every
+// (256 / groups-per-voxel)-th voxel of the chunk and keeps 8 sums; the
+// block then adds them per channel in a fixed order (deterministic).  The
+// sample of a voxel (for the halo offset) is tracked, not divided out.
 template <int COUT>
 __global__ void __launch_bounds__(256) k_bias_grad(const __bf16* __restrict__ dy, float* __restrict__ part,
                                                   VolGeom g, int chunk)
 {
-    __shared__ float red[256];
+    constexpr int GPV = COUT / 8;       // channel groups per voxel
+    constexpr int GROUPS = 256 / GPV;   // voxels read together
+    __shared__ float red[8][256];
     const long long v0 = (long long)blockIdx.x * chunk;
     long long v1 = v0 + chunk;
     if (v1 > g.n_all) v1 = g.n_all;
-    const int co = threadIdx.x % COUT;
-    const int lane_group = threadIdx.x / COUT;
-    constexpr int GROUPS = 256 / COUT;
-    float s = 0.0f;
-    for (long long v = v0 + lane_group; v < v1; v += GROUPS) s += (float)dy[own_index(g, v) * COUT + co];
-    red[threadIdx.x] = s;
+    const int gi = threadIdx.x % GPV;
+    const int lane_group = threadIdx.x / GPV;
+    const long long plane = (long long)g.nx * g.ny;
+    float s[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] = 0.0f;
+    long long v = v0 + lane_group;
+    int smp = (int)(v / g.n_int);
+    long long next = (long long)(smp + 1) * g.n_int;  // first voxel of the next sample
+    for (; v < v1; v += GROUPS) {
+        while (v >= next) {
+            ++smp;
+            next += g.n_int;
+        }
+        const long long oi = v + (2LL * smp + 1) * plane;
+        const bf16x8 d = *reinterpret_cast<const bf16x8*>(dy + oi * COUT + 8 * gi);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[e] += (float)d[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[e][threadIdx.x] = s[e];
     __syncthreads();
     if (threadIdx.x < COUT) {
+        const int co = threadIdx.x, cg = co / 8, e = co % 8;
         float t = 0.0f;
-        for (int k = 0; k < GROUPS; ++k) t += red[k * COUT + threadIdx.x];
-        part[(long long)blockIdx.x * COUT + threadIdx.x] = t;
+        for (int k = 0; k < GROUPS; ++k) t += red[e][k * GPV + cg];
+        part[(long long)blockIdx.x * COUT + co] = t;
     }
 }
 
