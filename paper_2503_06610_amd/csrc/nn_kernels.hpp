@@ -979,20 +979,26 @@ template <int COUT_PAD>
 __global__ void __launch_bounds__(256) k_mse(const float* __restrict__ pred, const float* __restrict__ target,
                                             __bf16* __restrict__ dy, double* __restrict__ part, VolGeom g)
 {
+    static_assert(COUT_PAD % 8 == 0 && COUT_PAD >= 8, "whole 16-byte channel groups");
     __shared__ double red[256];
     double s = 0.0;
     const double inv = 1.0 / (3.0 * (double)g.n_all);
     for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < g.n_all;
          v += (long long)gridDim.x * blockDim.x) {
         const long long oi = own_index(g, v) * COUT_PAD;
+        bf16x8 o[COUT_PAD / 8];  // the voxel's gradient, stored as whole 16-byte groups
+#pragma unroll
+        for (int k = 0; k < COUT_PAD / 8; ++k)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) o[k][e] = (__bf16)0.0f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float d = pred[c * g.n_all + v] - target[c * g.n_all + v];
             s += (double)d * d;
-            dy[oi + c] = (__bf16)(float)(2.0 * inv * d);
+            o[0][c] = (__bf16)(float)(2.0 * inv * d);
         }
 #pragma unroll
-        for (int c = 3; c < COUT_PAD; ++c) dy[oi + c] = (__bf16)0.0f;
+        for (int k = 0; k < COUT_PAD / 8; ++k) *reinterpret_cast<bf16x8*>(dy + oi + 8 * k) = o[k];
     }
     red[threadIdx.x] = s;
     __syncthreads();
