@@ -52,6 +52,14 @@ MUTATIONS = [
     ("no_corrector_normalisation", "normalise(v);\n                /* n(x) is read only", "/* n(x) is read only"),
     ("checkerboard_projection_sign", "ufull[(int64_t)a * s->N + idx(p, x, y, z)] -= amp * sign;",
      "ufull[(int64_t)a * s->N + idx(p, x, y, z)] += amp * sign;"),
+    # the hybrid loop of Sec. II D
+    ("fd_before_lbm", "or_step_lbm(s, 1);\n        if (s->t % s->p.fd_ratio == 0) or_step_director(s);",
+     "if (s->t % s->p.fd_ratio == 0) or_step_director(s);\n        or_step_lbm(s, 1);"),
+    ("fd_on_next_step", "if (s->t % s->p.fd_ratio == 0) or_step_director(s);",
+     "if ((s->t + 1) % s->p.fd_ratio == 0) or_step_director(s);"),
+    ("no_initial_force", "or_force(s); /* R10: initial force from n0 with u = 0 */", "/* no initial force */"),
+    ("no_force_after_fd", "    or_force(s);\n}\n\n/* Hybrid loop", "}\n\n/* Hybrid loop"),
+    ("no_moments_after_stream", "        lbm_step(s);\n        or_moments(s);", "        lbm_step(s);"),
 ]
 
 PINS = [
@@ -79,6 +87,9 @@ PINS = [
     pins.test_viscous_stress_power_identity,
     pins.test_checkerboard_velocity_mode_is_undamped,
     pins.test_warm_start_converges_back_to_steady_flow,
+    lambda: pins.test_hybrid_loop_matches_numpy_step(4, 4, 6, 2, True),
+    lambda: pins.test_hybrid_loop_matches_numpy_step(3, 5, 6, 3, False),
+    pins.test_hybrid_loop_variants_match_numpy_step,
 ]
 
 

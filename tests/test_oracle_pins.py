@@ -639,3 +639,69 @@ def test_warm_start_converges_back_to_steady_flow():
     o.step_lbm(3000)
     ref.step_lbm(3000)
     assert rel_l2(o.get("u"), ref.get("u")) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# The hybrid loop [HYB]: the oracle's or_run against a second, independently
+# written whole-array implementation of the coupled step (tests/numpy_step.py):
+# LBM step, moments after streaming, predictor-corrector and the new force when
+# t % dt_FD == 0, the initial force from n0.  Every term is on.
+
+def _whole_step_case(nx, ny, nz, r, shifted, renorm=True, periodic=False, seed=0):
+    from tests.numpy_step import Step
+    mat = inputs.set_b()
+    prob = inputs.channel(nx, ny, nz, mat, g=(2e-4, -1e-4, 5e-5), K=0.04, q0=0.45, W0=0.03, fd_ratio=r,
+                          renorm_predictor=renorm, periodic_z=periodic)
+    prob = prob.with_(alpha4p=0.06)
+    rng = np.random.default_rng(seed)
+    n0 = inputs.director_tilt(prob, seed=seed + 20, amplitude=0.5)
+    dq = rng.uniform(-4e-3, 4e-3, prob.shape(19))
+    o = oracle_for(prob, shifted)
+    o.init(n0)
+    ref = Step(prob, shifted)
+    ref.init(n0)
+    # a non-equilibrium start, so that every term of the collision and a velocity
+    # of order 1e-2 enter the first steps
+    o.set("q", o.get("q") + dq)
+    ref.q = ref.q + dq
+    return prob, o, ref
+
+
+def _rel(a, b):
+    return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(4, 4, 6), (3, 5, 6)])
+@pytest.mark.parametrize("r", [1, 2, 3])
+@pytest.mark.parametrize("shifted", [True, False])
+def test_hybrid_loop_matches_numpy_step(nx, ny, nz, r, shifted):
+    prob, o, ref = _whole_step_case(nx, ny, nz, r, shifted)
+    F0 = o.get("F")
+    assert _rel(F0, ref.F) < 1e-13 and np.abs(F0).max() > 1e-4  # the initial force from n0, u = 0
+    for T in (1, 2, 2):  # 5 steps, compared after steps 1, 3 and 5 (mid-interval for r = 2, 3)
+        o.run(T)
+        ref.run(T)
+        assert o.t == ref.t
+        for name, want in (("q", ref.q), ("u", ref.u), ("n", ref.n), ("nP", ref.nP), ("F", ref.F)):
+            if name == "q" and not shifted:
+                got = o.get("q") - np.asarray(inputs_weights())[:, None, None, None]
+                want = want - np.asarray(inputs_weights())[:, None, None, None]
+            else:
+                got = o.get(name)
+            assert _rel(got, want) < 1e-13, (name, T, _rel(got, want))
+    assert np.abs(ref.u).max() > 1e-3
+
+
+def inputs_weights():
+    from tests.numpy_step import WEIGHT
+    return WEIGHT
+
+
+def test_hybrid_loop_variants_match_numpy_step():
+    """Periodic z and an unnormalised predictor: the same loop."""
+    for periodic, renorm in ((True, True), (False, False)):
+        prob, o, ref = _whole_step_case(4, 5, 6, 2, True, renorm=renorm, periodic=periodic, seed=3)
+        o.run(4)
+        ref.run(4)
+        for name, want in (("q", ref.q), ("u", ref.u), ("n", ref.n), ("nP", ref.nP), ("F", ref.F)):
+            assert _rel(o.get(name), want) < 1e-13, (periodic, renorm, name)
