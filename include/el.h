@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define EL_ABI_VERSION 1
+#define EL_ABI_VERSION 2
 
 /* status codes */
 enum {
@@ -121,6 +121,18 @@ typedef struct {
 
 enum { EL_BUF_Q = 0, EL_BUF_VEC3 = 1, EL_BUF_SCRATCH = 2, EL_BUF_HALO = 3, EL_BUF_FD_HALO = 4 };
 
+/* Skyrmion tubes followed by the observables (Sec. III B follows one tube
+ * carried by the flow and a system of many).  A node with tube weight
+ * w = max(0, -n_z) > 0 belongs to the tube whose seed is nearest to it in the
+ * periodic (x, y) plane (minimum image; the lower index on a tie). */
+#define EL_MAX_TUBES 8
+
+typedef struct {
+    int32_t ntubes;         /* 1..EL_MAX_TUBES */
+    int32_t reserved;
+    double seed[EL_MAX_TUBES][2];   /* (x, y) in lattice units, 0 <= x < nx, 0 <= y < ny */
+} el_tubes;
+
 /* FP64 observables (Sec. III error measures are in el_error_norms). */
 typedef struct {
     double mass;            /* sum over fluid nodes of rho */
@@ -128,26 +140,31 @@ typedef struct {
     double mom_phys[3];     /* mom + 1/2 sum of the total force rho g + F^LC */
     double max_u;           /* max |u| */
     double max_unit_dev;    /* max | |n| - 1 | */
-    double tube_weight;     /* sum of w = max(0, -n_z) */
-    double tube_centroid[2];/* periodic circular mean of (x, y) weighted by w */
-    double tube_cs[4];      /* sums of w cos, w sin of 2 pi x/nx and 2 pi y/ny */
     int32_t nonfinite;      /* 1 if any q, n, u or F^LC is not finite */
-    int32_t reserved;
+    int32_t ntubes;         /* tubes the sums below are split over */
+    double tube_weight[EL_MAX_TUBES];       /* sum of w over the tube's nodes */
+    double tube_centroid[EL_MAX_TUBES][2];  /* periodic circular mean of (x, y) weighted by w
+                                               (the seed when the tube has no weight) */
+    double tube_cs[EL_MAX_TUBES][4];        /* sums of w cos, w sin of 2 pi x/nx and of 2 pi y/ny */
 } el_obs;
 
-/* Tube drift tracker (device memory, zero-filled by the caller before the
- * first call): the observables of the last call, the centroid of the first
- * call (origin), the periodically unwrapped centroid, the displacement
- * unwrapped - origin, all in FP64, and the steps of the first and last call. */
+/* Tube drift tracker (device memory).  Before the first call the caller
+ * zero-fills it and sets ntubes and seed[] (the tubes' starting positions);
+ * every call then assigns the nodes to the nearest seed, computes the
+ * observables into obs, and replaces each seed by its tube's new centroid, so
+ * that the assignment follows the tubes.  Per tube, all in FP64: the centroid
+ * of the first call (origin), the periodically unwrapped centroid and the
+ * displacement unwrapped - origin; the steps of the first and the last call. */
 typedef struct {
     el_obs obs;
-    double origin[2];
-    double unwrapped[2];
-    double displacement[2];
+    int32_t ntubes;
+    int32_t ncalls;
+    double seed[EL_MAX_TUBES][2];
+    double origin[EL_MAX_TUBES][2];
+    double unwrapped[EL_MAX_TUBES][2];
+    double displacement[EL_MAX_TUBES][2];
     int64_t step0;
     int64_t step;
-    int32_t ncalls;
-    int32_t reserved;
 } el_drift;
 
 /* Library version (EL_ABI_VERSION). */
@@ -287,16 +304,20 @@ int el_fd_halo_pack(const el_params* p, const el_state* s, int32_t stage, void* 
 int el_fd_stage(const el_params* p, el_state* s, int32_t stage, const void* lower, const void* upper, void* stream);
 
 /* FP64 observables of the current state into out (device memory, one el_obs).
- * Uses the first 128 KiB of s->scratch. */
-int el_observables(const el_params* p, const el_state* s, el_obs* out, void* stream);
+ * tubes (host memory) names the tubes the tube sums are split over; NULL is
+ * one tube that takes every node.  EL_EINVAL for ntubes outside
+ * 1..EL_MAX_TUBES.  Uses the first 128 KiB of s->scratch. */
+int el_observables(const el_params* p, const el_state* s, const el_tubes* tubes, el_obs* out, void* stream);
 
 /* Tube drift (Sec. III follows skyrmion tubes carried by the flow): computes
- * the observables of the current state into d->obs and advances the FP64
- * unwrapped centroid by the periodic minimum-image change since the previous
- * call (so displacements beyond one period accumulate correctly; the tube
- * must move less than half a period between calls).  The mean drift
- * velocity is d->displacement / (d->step - d->step0).  Uses the first
- * 128 KiB of s->scratch. */
+ * the observables of the current state into d->obs with the tubes seeded at
+ * d->seed, and advances each tube's FP64 unwrapped centroid by the periodic
+ * minimum-image change since the previous call (so displacements beyond one
+ * period accumulate correctly; a tube must move less than half a period, and
+ * less than half its distance to the next tube, between calls).  The mean
+ * drift velocity of tube k is d->displacement[k] / (d->step - d->step0).
+ * Everything stays on the device (capturable).  d->ntubes outside
+ * 1..EL_MAX_TUBES gives all-zero sums.  Uses the first 128 KiB of s->scratch. */
 int el_tube_drift(const el_params* p, const el_state* s, el_drift* d, void* stream);
 
 /* Error sums of a field a (device, ncomp*N T) against ref (device, ncomp*N
@@ -371,8 +392,9 @@ int el_batch_capture(el_batch* b, void* stream);
  * interval already hold it; the others get el_moments). */
 int el_batch_moments(el_batch* b, void* stream);
 
-/* FP64 observables of every channel into out (device, nchan el_obs). */
-int el_batch_observables(el_batch* b, el_obs* out, void* stream);
+/* FP64 observables of every channel into out (device, nchan el_obs); tubes
+ * (host) holds nchan tube sets, one per channel, or is NULL (one tube each). */
+int el_batch_observables(el_batch* b, const el_tubes* tubes, el_obs* out, void* stream);
 
 /* Writes each channel's parity and step back into states[0..nchan-1]. */
 int el_batch_sync(const el_batch* b, el_state* states, int32_t nchan);

@@ -740,3 +740,49 @@ void or_observables(const or_state* s, or_obs* out)
                 if (dev > out->max_unit_dev) out->max_unit_dev = dev;
             }
 }
+
+/* Tube centroids (R14): nearest-seed assignment, then per tube the circular
+ * mean angle atan2(sum w sin a, sum w cos a) of a = 2 pi x/nx (and of y),
+ * mapped back to [0, nx). */
+void or_tube_centroids(const or_state* s, int32_t ntubes, const double* seeds, double* weight, double* centroid)
+{
+    const or_params* p = &s->p;
+    const double two_pi = 6.283185307179586476925286766559;
+    double sums[64][5];
+    memset(sums, 0, sizeof(sums));
+    for (int z = z_lo(p); z < z_hi(p); ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                double w = -s->n[2 * s->N + idx(p, x, y, z)];
+                if (!(w > 0.0)) continue;
+                int best = 0;
+                double best_d2 = 0.0;
+                for (int t = 0; t < ntubes; ++t) {
+                    double dx = x - seeds[2 * t], dy = y - seeds[2 * t + 1];
+                    dx -= p->nx * floor(dx / p->nx + 0.5);
+                    dy -= p->ny * floor(dy / p->ny + 0.5);
+                    double d2 = dx * dx + dy * dy;
+                    if (t == 0 || d2 < best_d2) {
+                        best_d2 = d2;
+                        best = t;
+                    }
+                }
+                sums[best][0] += w;
+                sums[best][1] += w * cos(two_pi * x / p->nx);
+                sums[best][2] += w * sin(two_pi * x / p->nx);
+                sums[best][3] += w * cos(two_pi * y / p->ny);
+                sums[best][4] += w * sin(two_pi * y / p->ny);
+            }
+    for (int t = 0; t < ntubes; ++t) {
+        weight[t] = sums[t][0];
+        if (sums[t][0] > 0.0) {
+            double cx = atan2(sums[t][2], sums[t][1]) * p->nx / two_pi;
+            double cy = atan2(sums[t][4], sums[t][3]) * p->ny / two_pi;
+            centroid[2 * t] = cx < 0.0 ? cx + p->nx : cx;
+            centroid[2 * t + 1] = cy < 0.0 ? cy + p->ny : cy;
+        } else {
+            centroid[2 * t] = seeds[2 * t];
+            centroid[2 * t + 1] = seeds[2 * t + 1];
+        }
+    }
+}

@@ -120,6 +120,14 @@ typedef struct {
 
 void or_observables(const or_state* s, or_obs* out);
 
+/* Tube centroids [SP: skyrmion tubes carried by the flow; R14]: every fluid
+ * node with weight w = max(0, -n_z) > 0 joins the tube whose seed
+ * (seeds[2k], seeds[2k+1]) is nearest in the periodic (x, y) plane (minimum
+ * image, the lower index on a tie); per tube the weight sum (weight[k]) and the
+ * periodic circular mean of x and y weighted by w (centroid[2k], [2k+1]; the
+ * seed itself when the tube has no weight). */
+void or_tube_centroids(const or_state* s, int32_t ntubes, const double* seeds, double* weight, double* centroid);
+
 #ifdef __cplusplus
 }
 #endif

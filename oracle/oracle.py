@@ -78,6 +78,7 @@ def load_library(path: str):
     lib.or_stress.argtypes = [C.c_void_p, C.c_int32, D]
     lib.or_force_masked.argtypes = [C.c_void_p, C.c_int32, D]
     lib.or_observables.argtypes = [C.c_void_p, C.POINTER(_Obs)]
+    lib.or_tube_centroids.argtypes = [C.c_void_p, C.c_int32, D, D, D]
     lib.or_lattice.argtypes = [D, D, C.POINTER(C.c_int32)]
     lib.or_equilibrium.argtypes = [C.c_double, C.c_double, D, C.c_int32, D]
     lib.or_guo_source.argtypes = [D, D, D]
@@ -253,3 +254,14 @@ class Oracle:
         self.lib.or_observables(self.h, C.byref(o))
         return {"mass": o.mass, "mom": np.array(o.mom[:]), "mom_phys": np.array(o.mom_phys[:]),
                 "max_u": o.max_u, "max_unit_dev": o.max_unit_dev, "nonfinite": int(o.nonfinite)}
+
+    def tube_centroids(self, seeds):
+        """Per-tube weight sums and circular-mean centroids of the stored director
+        for tube seeds [(x, y), ...] (at most 64)."""
+        sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.float64).reshape(-1, 2))
+        nt = sd.shape[0]
+        assert 1 <= nt <= 64
+        w = np.zeros(nt)
+        c = np.zeros((nt, 2))
+        self.lib.or_tube_centroids(self.h, nt, _dp(sd), _dp(w), _dp(c))
+        return w, c

@@ -728,13 +728,13 @@ int el_batch_sync(const el_batch* b, el_state* states, int32_t nchan)
     return EL_OK;
 }
 
-int el_batch_observables(el_batch* b, el_obs* out, void* stream)
+int el_batch_observables(el_batch* b, const el_tubes* tubes, el_obs* out, void* stream)
 {
     if (!b || !out) return fail(EL_EINVAL, "NULL argument");
     std::vector<el_state> cur(b->nchan);
     el_batch_sync(b, cur.data(), b->nchan);
     for (int c = 0; c < b->nchan; ++c) {
-        const int rc = el_observables(&b->params[c], &cur[c], out + c, stream);
+        const int rc = el_observables(&b->params[c], &cur[c], tubes ? tubes + c : nullptr, out + c, stream);
         if (rc != EL_OK) return rc;
     }
     return EL_OK;

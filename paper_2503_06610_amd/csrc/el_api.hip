@@ -219,7 +219,8 @@ int init_flow_impl(const el_params* p, el_state* s, const void* u0, hipStream_t 
 }
 
 template <typename T>
-int observables_impl(const el_params* p, const el_state* s, el_obs* out, el_drift* drift, hipStream_t st)
+int observables_impl(const el_params* p, const el_state* s, const el::TubeSeeds& ts, el_obs* out, el_drift* drift,
+                     hipStream_t st)
 {
     el::ObsArgs<T> a;
     a.g = geom_of(p);
@@ -229,13 +230,13 @@ int observables_impl(const el_params* p, const el_state* s, el_obs* out, el_drif
     a.gy = p->g[1];
     a.gz = p->g[2];
     int blocks = grid_for(a.g.N);
-    if (blocks > el::RED_MAX_BLOCKS) blocks = el::RED_MAX_BLOCKS;
+    if (blocks > el::OBS_MAX_BLOCKS) blocks = el::OBS_MAX_BLOCKS;
     double* partial = static_cast<double*>(s->scratch);
     hipLaunchKernelGGL((el::k_obs_partial<T>), dim3(blocks), dim3(el::RED_THREADS), 0, st,
                        static_cast<const T*>(s->q[s->parity]), static_cast<const T*>(s->n),
-                       static_cast<const T*>(s->u), static_cast<const T*>(s->F), partial, a);
+                       static_cast<const T*>(s->u), static_cast<const T*>(s->F), partial, a, ts);
     hipLaunchKernelGGL(el::k_obs_final, dim3(1), dim3(el::RED_THREADS), 0, st, static_cast<const double*>(partial),
-                       blocks, out, p->nx, p->ny, drift, (long long)s->step);
+                       blocks, out, p->nx, p->ny, drift, (long long)s->step, ts);
     return check_launch("observables kernels");
 }
 
@@ -526,15 +527,26 @@ int el_fd_stage(const el_params* p, el_state* s, int32_t stage, const void* lowe
     return fd_stage_impl<float>(p, s, stage, static_cast<const float*>(lower), static_cast<const float*>(upper), st);
 }
 
-int el_observables(const el_params* p, const el_state* s, el_obs* out, void* stream)
+int el_observables(const el_params* p, const el_state* s, const el_tubes* tubes, el_obs* out, void* stream)
 {
     int rc = basic_checks(p);
     if (rc != EL_OK) return rc;
     if ((rc = state_checks(p, s)) != EL_OK) return rc;
     if (!out) return fail(EL_EINVAL, "out is NULL");
+    el::TubeSeeds ts = {};
+    ts.ntubes = 1;
+    if (tubes) {
+        if (tubes->ntubes < 1 || tubes->ntubes > EL_MAX_TUBES)
+            return fail(EL_EINVAL, "ntubes = %d (1..%d)", tubes->ntubes, EL_MAX_TUBES);
+        ts.ntubes = tubes->ntubes;
+        for (int t = 0; t < tubes->ntubes; ++t) {
+            ts.s[t][0] = tubes->seed[t][0];
+            ts.s[t][1] = tubes->seed[t][1];
+        }
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (is_f64(p)) return observables_impl<double>(p, s, out, nullptr, st);
-    return observables_impl<float>(p, s, out, nullptr, st);
+    if (is_f64(p)) return observables_impl<double>(p, s, ts, out, nullptr, st);
+    return observables_impl<float>(p, s, ts, out, nullptr, st);
 }
 
 int el_tube_drift(const el_params* p, const el_state* s, el_drift* d, void* stream)
@@ -543,9 +555,11 @@ int el_tube_drift(const el_params* p, const el_state* s, el_drift* d, void* stre
     if (rc != EL_OK) return rc;
     if ((rc = state_checks(p, s)) != EL_OK) return rc;
     if (!d) return fail(EL_EINVAL, "drift tracker is NULL");
+    el::TubeSeeds ts = {};
+    ts.drift = d;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (is_f64(p)) return observables_impl<double>(p, s, nullptr, d, st);
-    return observables_impl<float>(p, s, nullptr, d, st);
+    if (is_f64(p)) return observables_impl<double>(p, s, ts, nullptr, d, st);
+    return observables_impl<float>(p, s, ts, nullptr, d, st);
 }
 
 int el_error_norms(const el_params* p, const void* a, const double* ref, int32_t ncomp, void* work, double* out,

@@ -14,9 +14,12 @@ namespace el {
 
 constexpr int RED_THREADS = 256;
 constexpr int RED_MAX_BLOCKS = 1024;
-constexpr int OBS_NSUM = 12;    // mass, mom[3], Fsum[3], w, w cos x, w sin x, w cos y, w sin y
+constexpr int OBS_NT = EL_MAX_TUBES;
+constexpr int OBS_NBASE = 7;     // mass, mom[3], Fsum[3]
+constexpr int OBS_NSUM = OBS_NBASE + 5 * OBS_NT;  // + per tube: w, w cos x, w sin x, w cos y, w sin y
 constexpr int OBS_NMAX = 3;     // max |u|, max ||n| - 1|, nonfinite
 constexpr int OBS_NQ = OBS_NSUM + OBS_NMAX;
+constexpr int OBS_MAX_BLOCKS = 256;  // partial rows of the observables: 256 * 50 doubles
 constexpr int ERR_NQ = 10;      // up to 4 + 2*3 sums
 
 __device__ inline double wave_sum(double v)
@@ -60,12 +63,52 @@ struct ObsArgs {
     double gx, gy, gz;
 };
 
+// The tube seeds of one observables call: by value (el_observables) or read
+// from a drift tracker in device memory (el_tube_drift).
+struct TubeSeeds {
+    int ntubes;
+    double s[EL_MAX_TUBES][2];
+    const el_drift* drift;  // when set, ntubes and the seeds are read from it
+};
+
+// Index of the tube whose seed is nearest to (x, y) in the periodic plane
+// (minimum image; the lower index on a tie).
+__device__ inline int nearest_tube(double x, double y, int nx, int ny, int ntubes, const double (*seed)[2])
+{
+    int best = 0;
+    double bd = 0.0;
+    for (int t = 0; t < ntubes; ++t) {
+        double dx = x - seed[t][0];
+        double dy = y - seed[t][1];
+        dx -= nx * floor(dx / nx + 0.5);
+        dy -= ny * floor(dy / ny + 0.5);
+        const double d2 = dx * dx + dy * dy;
+        if (t == 0 || d2 < bd) {
+            bd = d2;
+            best = t;
+        }
+    }
+    return best;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(RED_THREADS) k_obs_partial(const T* __restrict__ q, const T* __restrict__ n,
                                                             const T* __restrict__ u, const T* __restrict__ Flc,
-                                                            double* __restrict__ partial, ObsArgs<T> a)
+                                                            double* __restrict__ partial, ObsArgs<T> a, TubeSeeds ts)
 {
     __shared__ double lds[RED_THREADS / 64][OBS_NQ];
+    __shared__ double seed[EL_MAX_TUBES][2];
+    __shared__ int s_ntubes;
+    if (threadIdx.x == 0) {
+        int nt = ts.drift ? ts.drift->ntubes : ts.ntubes;
+        s_ntubes = (nt >= 1 && nt <= EL_MAX_TUBES) ? nt : 0;
+    }
+    if (threadIdx.x < 2 * EL_MAX_TUBES) {
+        const int t = threadIdx.x >> 1, c = threadIdx.x & 1;
+        seed[t][c] = ts.drift ? ts.drift->seed[t][c] : ts.s[t][c];
+    }
+    __syncthreads();
+    const int ntubes = s_ntubes;
     double v[OBS_NQ];
 #pragma unroll
     for (int j = 0; j < OBS_NQ; ++j) v[j] = 0.0;
@@ -97,9 +140,6 @@ __global__ void __launch_bounds__(RED_THREADS) k_obs_partial(const T* __restrict
             nn += nc * nc;
             if (c == 2) nz = nc;
         }
-        const int x = k % a.g.nx;
-        const int y = (k / a.g.nx) % a.g.ny;
-        const double w = fmax(0.0, -nz);
         v[0] += rho;
         v[1] += jx;
         v[2] += jy;
@@ -107,16 +147,27 @@ __global__ void __launch_bounds__(RED_THREADS) k_obs_partial(const T* __restrict
         v[4] += F[0];
         v[5] += F[1];
         v[6] += F[2];
-        v[7] += w;
-        if (w > 0.0) {
-            v[8] += w * cos(two_pi * x / a.g.nx);
-            v[9] += w * sin(two_pi * x / a.g.nx);
-            v[10] += w * cos(two_pi * y / a.g.ny);
-            v[11] += w * sin(two_pi * y / a.g.ny);
+        const double w = fmax(0.0, -nz);
+        if (w > 0.0 && ntubes > 0) {
+            const int x = k % a.g.nx;
+            const int y = (k / a.g.nx) % a.g.ny;
+            const int tube = nearest_tube((double)x, (double)y, a.g.nx, a.g.ny, ntubes, seed);
+            const double cx = cos(two_pi * x / a.g.nx), sx = sin(two_pi * x / a.g.nx);
+            const double cy = cos(two_pi * y / a.g.ny), sy = sin(two_pi * y / a.g.ny);
+            // unrolled selection keeps the per-tube sums in registers
+#pragma unroll
+            for (int t = 0; t < OBS_NT; ++t)
+                if (t == tube) {
+                    v[OBS_NBASE + 5 * t + 0] += w;
+                    v[OBS_NBASE + 5 * t + 1] += w * cx;
+                    v[OBS_NBASE + 5 * t + 2] += w * sx;
+                    v[OBS_NBASE + 5 * t + 3] += w * cy;
+                    v[OBS_NBASE + 5 * t + 4] += w * sy;
+                }
         }
-        v[12] = fmax(v[12], sqrt(uu));
-        v[13] = fmax(v[13], fabs(sqrt(nn) - 1.0));
-        if (bad) v[14] = 1.0;
+        v[OBS_NSUM + 0] = fmax(v[OBS_NSUM + 0], sqrt(uu));
+        v[OBS_NSUM + 1] = fmax(v[OBS_NSUM + 1], fabs(sqrt(nn) - 1.0));
+        if (bad) v[OBS_NSUM + 2] = 1.0;
     }
     block_reduce<OBS_NQ, OBS_NSUM>(v, lds);
     if (threadIdx.x == 0)
@@ -125,10 +176,12 @@ __global__ void __launch_bounds__(RED_THREADS) k_obs_partial(const T* __restrict
 }
 
 // Adds the block rows in order and fills an el_obs; with a drift tracker,
-// also advances its unwrapped centroid (FP64).
+// also advances each tube's unwrapped centroid (FP64) and moves its seed to
+// the new centroid.
 static __global__ void __launch_bounds__(RED_THREADS) k_obs_final(const double* __restrict__ partial, int nblocks,
                                                           el_obs* __restrict__ out, int nx, int ny,
-                                                          el_drift* __restrict__ drift, long long step)
+                                                          el_drift* __restrict__ drift, long long step,
+                                                          TubeSeeds ts)
 {
     __shared__ double lds[RED_THREADS / 64][OBS_NQ];
     double v[OBS_NQ];
@@ -142,6 +195,8 @@ static __global__ void __launch_bounds__(RED_THREADS) k_obs_final(const double* 
     block_reduce<OBS_NQ, OBS_NSUM>(v, lds);
     if (threadIdx.x == 0) {
         const double two_pi = 6.283185307179586476925286766559;
+        int nt = drift ? drift->ntubes : ts.ntubes;
+        if (nt < 1 || nt > EL_MAX_TUBES) nt = 0;
         el_obs o;
         o.mass = v[0];
         o.mom[0] = v[1];
@@ -150,44 +205,52 @@ static __global__ void __launch_bounds__(RED_THREADS) k_obs_final(const double* 
         o.mom_phys[0] = v[1] + 0.5 * v[4];
         o.mom_phys[1] = v[2] + 0.5 * v[5];
         o.mom_phys[2] = v[3] + 0.5 * v[6];
-        o.max_u = v[12];
-        o.max_unit_dev = v[13];
-        o.tube_weight = v[7];
-        o.tube_cs[0] = v[8];
-        o.tube_cs[1] = v[9];
-        o.tube_cs[2] = v[10];
-        o.tube_cs[3] = v[11];
-        double cx = atan2(v[9], v[8]) * nx / two_pi;
-        double cy = atan2(v[11], v[10]) * ny / two_pi;
-        if (cx < 0) cx += nx;
-        if (cy < 0) cy += ny;
-        o.tube_centroid[0] = v[7] > 0.0 ? cx : 0.0;
-        o.tube_centroid[1] = v[7] > 0.0 ? cy : 0.0;
-        o.nonfinite = v[14] > 0.0 ? 1 : 0;
-        o.reserved = 0;
+        o.max_u = v[OBS_NSUM + 0];
+        o.max_unit_dev = v[OBS_NSUM + 1];
+        o.nonfinite = v[OBS_NSUM + 2] > 0.0 ? 1 : 0;
+        o.ntubes = nt;
+        for (int t = 0; t < EL_MAX_TUBES; ++t) {
+            const double* tv = v + OBS_NBASE + 5 * t;
+            o.tube_weight[t] = tv[0];
+            for (int j = 0; j < 4; ++j) o.tube_cs[t][j] = tv[1 + j];
+            const double s0 = t < nt ? (drift ? drift->seed[t][0] : ts.s[t][0]) : 0.0;
+            const double s1 = t < nt ? (drift ? drift->seed[t][1] : ts.s[t][1]) : 0.0;
+            if (tv[0] > 0.0) {
+                double cx = atan2(tv[2], tv[1]) * nx / two_pi;
+                double cy = atan2(tv[4], tv[3]) * ny / two_pi;
+                if (cx < 0) cx += nx;
+                if (cy < 0) cy += ny;
+                o.tube_centroid[t][0] = cx;
+                o.tube_centroid[t][1] = cy;
+            } else {
+                o.tube_centroid[t][0] = s0;
+                o.tube_centroid[t][1] = s1;
+            }
+        }
         if (out) *out = o;
         if (drift) {
             drift->obs = o;
-            const double c[2] = {o.tube_centroid[0], o.tube_centroid[1]};
             const double L[2] = {(double)nx, (double)ny};
-            if (drift->ncalls == 0) {
+            for (int t = 0; t < nt; ++t) {
+                const double c[2] = {o.tube_centroid[t][0], o.tube_centroid[t][1]};
                 for (int a = 0; a < 2; ++a) {
-                    drift->origin[a] = c[a];
-                    drift->unwrapped[a] = c[a];
-                    drift->displacement[a] = 0.0;
-                }
-                drift->step0 = step;
-            } else {
-                for (int a = 0; a < 2; ++a) {
-                    // minimum-image change of the centroid since the last call
-                    double last = fmod(drift->unwrapped[a], L[a]);
-                    if (last < 0) last += L[a];
-                    double d = c[a] - last;
-                    d -= L[a] * floor(d / L[a] + 0.5);
-                    drift->unwrapped[a] += d;
-                    drift->displacement[a] = drift->unwrapped[a] - drift->origin[a];
+                    if (drift->ncalls == 0) {
+                        drift->origin[t][a] = c[a];
+                        drift->unwrapped[t][a] = c[a];
+                        drift->displacement[t][a] = 0.0;
+                    } else {
+                        // minimum-image change of the centroid since the last call
+                        double last = fmod(drift->unwrapped[t][a], L[a]);
+                        if (last < 0) last += L[a];
+                        double d = c[a] - last;
+                        d -= L[a] * floor(d / L[a] + 0.5);
+                        drift->unwrapped[t][a] += d;
+                        drift->displacement[t][a] = drift->unwrapped[t][a] - drift->origin[t][a];
+                    }
+                    drift->seed[t][a] = c[a];
                 }
             }
+            if (drift->ncalls == 0) drift->step0 = step;
             drift->step = step;
             drift->ncalls += 1;
         }

@@ -53,20 +53,46 @@ class el_state(C.Structure):
                 ("reserved", C.c_int32), ("step", C.c_int64)]
 
 
+EL_MAX_TUBES = 8
+_XY = (C.c_double * 2) * EL_MAX_TUBES
+
+
+class el_tubes(C.Structure):
+    _fields_ = [("ntubes", C.c_int32), ("reserved", C.c_int32), ("seed", _XY)]
+
+
 class el_obs(C.Structure):
     _fields_ = [("mass", C.c_double), ("mom", C.c_double * 3), ("mom_phys", C.c_double * 3),
-                ("max_u", C.c_double), ("max_unit_dev", C.c_double), ("tube_weight", C.c_double),
-                ("tube_centroid", C.c_double * 2), ("tube_cs", C.c_double * 4), ("nonfinite", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("max_u", C.c_double), ("max_unit_dev", C.c_double), ("nonfinite", C.c_int32),
+                ("ntubes", C.c_int32), ("tube_weight", C.c_double * EL_MAX_TUBES), ("tube_centroid", _XY),
+                ("tube_cs", (C.c_double * 4) * EL_MAX_TUBES)]
 
 
 OBS_DOUBLES = C.sizeof(el_obs) // 8
 
 
 class el_drift(C.Structure):
-    _fields_ = [("obs", el_obs), ("origin", C.c_double * 2), ("unwrapped", C.c_double * 2),
-                ("displacement", C.c_double * 2), ("step0", C.c_int64), ("step", C.c_int64),
-                ("ncalls", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("obs", el_obs), ("ntubes", C.c_int32), ("ncalls", C.c_int32), ("seed", _XY), ("origin", _XY),
+                ("unwrapped", _XY), ("displacement", _XY), ("step0", C.c_int64), ("step", C.c_int64)]
+
+
+def make_tubes(seeds) -> el_tubes:
+    """el_tubes from a list of (x, y) seeds (1..EL_MAX_TUBES)."""
+    t = el_tubes()
+    t.ntubes = len(seeds)
+    for k, (x, y) in enumerate(seeds):
+        t.seed[k][0], t.seed[k][1] = float(x), float(y)
+    return t
+
+
+def obs_dict(o: el_obs) -> dict:
+    """Plain-Python view of an el_obs (per-tube arrays cut to ntubes)."""
+    nt = int(o.ntubes)
+    return {"mass": o.mass, "mom": np.array(o.mom[:]), "mom_phys": np.array(o.mom_phys[:]),
+            "max_u": o.max_u, "max_unit_dev": o.max_unit_dev, "nonfinite": int(o.nonfinite), "ntubes": nt,
+            "tube_weight": np.array(o.tube_weight[:nt]),
+            "tube_centroid": np.array([o.tube_centroid[k][:] for k in range(nt)]).reshape(nt, 2),
+            "tube_cs": np.array([o.tube_cs[k][:] for k in range(nt)]).reshape(nt, 4)}
 
 
 class el_batch_tuning(C.Structure):
@@ -107,7 +133,7 @@ def load(path: str = LIB_PATH):
         "el_step_director": (C.c_int, [P, S, V]),
         "el_force": (C.c_int, [P, S, V]),
         "el_run": (C.c_int, [P, S, C.c_int64, V]),
-        "el_observables": (C.c_int, [P, S, V, V]),
+        "el_observables": (C.c_int, [P, S, C.POINTER(el_tubes), V, V]),
         "el_error_norms": (C.c_int, [P, V, V, C.c_int32, V, V, V]),
         "el_tube_drift": (C.c_int, [P, S, V, V]),
         "el_halo_pack": (C.c_int, [P, S, V, V]),
@@ -119,7 +145,7 @@ def load(path: str = LIB_PATH):
         "el_batch_step": (C.c_int, [V, C.c_int32, V]),
         "el_batch_capture": (C.c_int, [V, V]),
         "el_batch_moments": (C.c_int, [V, V]),
-        "el_batch_observables": (C.c_int, [V, V, V]),
+        "el_batch_observables": (C.c_int, [V, C.POINTER(el_tubes), V, V]),
         "el_batch_sync": (C.c_int, [V, S, C.c_int32]),
         "el_batch_get_tuning": (C.c_int, [V, C.POINTER(el_batch_tuning)]),
         "el_batch_destroy": (C.c_int, [V]),
@@ -253,33 +279,39 @@ class Lattice:
     def run(self, T: int, stream=None):
         _check(self.lib.el_run(C.byref(self.params), C.byref(self.state), int(T), _stream_ptr(stream)), "el_run")
 
-    def observables_to(self, ptr: int, stream=None):
+    def observables_to(self, ptr: int, seeds=None, stream=None):
         """Device-side observables into the el_obs at device address ptr; no
         host synchronisation (read it later with decode_obs)."""
-        _check(self.lib.el_observables(C.byref(self.params), C.byref(self.state), C.c_void_p(ptr),
+        tb = C.byref(make_tubes(seeds)) if seeds is not None else None
+        _check(self.lib.el_observables(C.byref(self.params), C.byref(self.state), tb, C.c_void_p(ptr),
                                        _stream_ptr(stream)), "el_observables")
 
-    def observables(self, stream=None) -> dict:
-        import torch
-        _check(self.lib.el_observables(C.byref(self.params), C.byref(self.state),
-                                       C.c_void_p(self.obs_buf.data_ptr()), _stream_ptr(stream)), "el_observables")
+    def observables(self, seeds=None, stream=None) -> dict:
+        """FP64 observables; seeds: the tubes' (x, y) seeds (None: one tube)."""
+        self.observables_to(self.obs_buf.data_ptr(), seeds, stream)
         raw = self.obs_buf.cpu().numpy().tobytes()
-        o = el_obs.from_buffer_copy(raw)
-        return {"mass": o.mass, "mom": np.array(o.mom[:]), "mom_phys": np.array(o.mom_phys[:]),
-                "max_u": o.max_u, "max_unit_dev": o.max_unit_dev, "tube_weight": o.tube_weight,
-                "tube_centroid": np.array(o.tube_centroid[:]), "tube_cs": np.array(o.tube_cs[:]),
-                "nonfinite": int(o.nonfinite)}
+        return obs_dict(el_obs.from_buffer_copy(raw))
 
-    def track_drift(self, stream=None) -> dict:
-        """Advance this lattice's FP64 tube-drift tracker (el_tube_drift)."""
+    def track_drift(self, seeds=None, stream=None) -> dict:
+        """Advance this lattice's FP64 tube-drift tracker (el_tube_drift); the
+        first call sets the tubes' seeds (default: one tube at the centre)."""
         import torch
         if not hasattr(self, "drift_buf"):
-            self.drift_buf = torch.zeros((C.sizeof(el_drift) + 7) // 8, dtype=torch.float64, device=self.n.device)
+            d0 = el_drift()
+            seeds = seeds if seeds is not None else [(self.prob.nx / 2.0, self.prob.ny / 2.0)]
+            d0.ntubes = len(seeds)
+            for k, (x, y) in enumerate(seeds):
+                d0.seed[k][0], d0.seed[k][1] = float(x), float(y)
+            host = np.frombuffer(bytes(d0) + b"\0" * (-C.sizeof(el_drift) % 8), dtype=np.float64).copy()
+            self.drift_buf = torch.from_numpy(host).to(self.n.device)
         _check(self.lib.el_tube_drift(C.byref(self.params), C.byref(self.state), C.c_void_p(self.drift_buf.data_ptr()),
                                       _stream_ptr(stream)), "el_tube_drift")
         d = el_drift.from_buffer_copy(self.drift_buf.cpu().numpy().tobytes()[:C.sizeof(el_drift)])
-        return {"centroid": np.array(d.obs.tube_centroid[:]), "unwrapped": np.array(d.unwrapped[:]),
-                "displacement": np.array(d.displacement[:]), "steps": int(d.step - d.step0), "ncalls": d.ncalls}
+        nt = int(d.ntubes)
+        xy = lambda a: np.array([a[k][:] for k in range(nt)]).reshape(nt, 2)
+        return {"centroid": xy(d.obs.tube_centroid), "unwrapped": xy(d.unwrapped), "displacement": xy(d.displacement),
+                "seed": xy(d.seed), "weight": np.array(d.obs.tube_weight[:nt]), "steps": int(d.step - d.step0),
+                "ncalls": d.ncalls}
 
     def error_norms(self, a, ref, stream=None) -> dict:
         """Error sums of a device field `a` (this lattice's dtype) against an
@@ -405,12 +437,14 @@ class Batch:
             lat.state.parity = st.parity
             lat.state.step = st.step
 
-    def observables(self):
+    def observables(self, seeds=None):
+        """Per-channel el_obs; seeds: one list of (x, y) tube seeds per channel, or None."""
         import torch
         n = len(self.lattices)
         buf = torch.zeros(n * OBS_DOUBLES, dtype=torch.float64, device=self.lattices[0].n.device)
+        tubes = (el_tubes * n)(*[make_tubes(sd) for sd in seeds]) if seeds is not None else None
         self._enter()
-        _check(self.lib.el_batch_observables(self.handle, C.c_void_p(buf.data_ptr()), _stream_ptr(self.stream)),
+        _check(self.lib.el_batch_observables(self.handle, tubes, C.c_void_p(buf.data_ptr()), _stream_ptr(self.stream)),
                "el_batch_observables")
         self._leave()
         raw = buf.cpu().numpy().tobytes()

@@ -199,12 +199,13 @@ def workload_c3(r: int = 10) -> tuple:
 
 
 def workload_c4(seed: int = 4, nchan: int = 64, material: str = "set_a", K: float = 1e-3,
-                ratios: tuple = (2, 5, 10)) -> list:
+                ratios: tuple = (2, 5, 10), with_centres: bool = False) -> list:
     """Batched ensemble: nchan channels with Nx, Ny ~ U{48..160}, Nz ~ U{16..48}
     (walls included), 1-4 skyrmion tubes (pitch 32, R = 16, periodic separation
     >= 2R, fewer when they do not fit), g_x log-uniform in [1e-7, 1e-5], r drawn
     from `ratios`; Leslie `material` (set_a: tau = 0.8; set_b: tau = 1.8977),
-    elastic constant K, q0 = 2 pi/32.  Returns a list of (Problem, n0).
+    elastic constant K, q0 = 2 pi/32.  Returns a list of (Problem, n0), or of
+    (Problem, n0, tube centres) with with_centres.
 
     The defaults (set A, K = 1e-3, r in {2, 5, 10}) keep every channel bounded
     over 25,000 steps.  With the force held over an odd number of LBM steps the
@@ -224,5 +225,6 @@ def workload_c4(seed: int = 4, nchan: int = 64, material: str = "set_a", K: floa
         ntubes = 1 + int(v[5] * 4)
         prob = channel(nx, ny, nz, mat, g=(gx, 0.0, 0.0), K=K, q0=2.0 * math.pi / 32.0, fd_ratio=r)
         centres = place_tubes(nx, ny, ntubes, 16.0, seed=seed * 1000 + c)
-        out.append((prob, director_tubes(prob, centres, 16.0)))
+        n0 = director_tubes(prob, centres, 16.0)
+        out.append((prob, n0, centres) if with_centres else (prob, n0))
     return out

@@ -58,12 +58,12 @@ def tube_drift(steps=100000, every=1000, precisions=("f32_shifted", "f64_shifted
         lat.init_lattice(n0)
         series = []
         t0 = time.perf_counter()
-        d = lat.track_drift()
-        series.append((0, d["displacement"].tolist(), d["centroid"].tolist()))
+        d = lat.track_drift(seeds=[(prob.nx / 2.0, prob.ny / 2.0)])
+        series.append((0, d["displacement"][0].tolist(), d["centroid"][0].tolist()))
         for k in range(steps // every):
             lat.run(every)
             d = lat.track_drift()
-            series.append((lat.step, d["displacement"].tolist(), d["centroid"].tolist()))
+            series.append((lat.step, d["displacement"][0].tolist(), d["centroid"][0].tolist()))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         half = len(series) // 2

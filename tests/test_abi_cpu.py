@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared_functions():
         assert name in exported, name
         assert hasattr(lib, name)
-    assert lib.el_version() == 1
+    assert lib.el_version() == 2
 
 
 def test_struct_sizes_match_header():
@@ -40,9 +40,10 @@ def test_struct_sizes_match_header():
     #include <stddef.h>
     #include "el.h"
     int main(void) {
-      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(el_params), sizeof(el_state), sizeof(el_obs),
-             offsetof(el_params, tau), offsetof(el_state, parity), offsetof(el_obs, nonfinite),
-             sizeof(el_drift), offsetof(el_drift, step0), sizeof(el_batch_tuning));
+      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(el_params), sizeof(el_state),
+             sizeof(el_obs), offsetof(el_params, tau), offsetof(el_state, parity), offsetof(el_obs, nonfinite),
+             sizeof(el_drift), offsetof(el_drift, step0), sizeof(el_batch_tuning), sizeof(el_tubes),
+             offsetof(el_obs, tube_centroid), offsetof(el_drift, seed), offsetof(el_drift, displacement));
       return 0; }
     '''
     import tempfile
@@ -54,7 +55,9 @@ def test_struct_sizes_match_header():
         vals = [int(v) for v in subprocess.check_output([exe], text=True).split()]
     assert vals == [C.sizeof(el.el_params), C.sizeof(el.el_state), C.sizeof(el.el_obs),
                     el.el_params.tau.offset, el.el_state.parity.offset, el.el_obs.nonfinite.offset,
-                    C.sizeof(el.el_drift), el.el_drift.step0.offset, C.sizeof(el.el_batch_tuning)]
+                    C.sizeof(el.el_drift), el.el_drift.step0.offset, C.sizeof(el.el_batch_tuning),
+                    C.sizeof(el.el_tubes), el.el_obs.tube_centroid.offset, el.el_drift.seed.offset,
+                    el.el_drift.displacement.offset]
 
 
 def test_validate_accepts_workloads():
@@ -133,7 +136,7 @@ def test_null_arguments_are_rejected_without_device_work():
     assert lib.el_init_lattice(C.byref(p), C.byref(s), None, None) == el.EL_EINVAL
     assert lib.el_step_lbm(C.byref(p), None, 1, 0, None) == el.EL_EINVAL
     assert lib.el_step_director(None, C.byref(s), None) == el.EL_EINVAL
-    assert lib.el_observables(C.byref(p), C.byref(s), None, None) == el.EL_EINVAL
+    assert lib.el_observables(C.byref(p), C.byref(s), None, None, None) == el.EL_EINVAL
     assert lib.el_error_norms(C.byref(p), None, None, 3, None, None, None) == el.EL_EINVAL
     assert lib.el_halo_pack(C.byref(p), None, None, None) == el.EL_EINVAL
     assert lib.el_halo_unpack(C.byref(p), C.byref(s), None, None, None) == el.EL_EINVAL

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2503_06610_amd import el, inputs
+from tests.helpers import oracle_for
 
 pytestmark = pytest.mark.gpu
 
@@ -188,6 +189,31 @@ def test_c4_ensemble_full_size():
         fa, fs = _fields(lats[i]), _fields(s)
         for k in fa:
             assert np.array_equal(fa[k], fs[k]), (i, k)
+
+
+def test_batch_tube_observables_per_channel():
+    """el_batch_observables with one tube set per channel: each channel's
+    per-tube sums equal el_observables of that channel alone (bitwise), and
+    match the oracle's nearest-seed centroids of the channel's director."""
+    import torch
+    chans = inputs.workload_c4(nchan=6, with_centres=True)
+    lats = _lattices([(p, n0) for p, n0, _ in chans], "f32_shifted")
+    b = el.Batch(lats)
+    b.step(10)
+    b.moments()
+    b.sync()
+    seeds = [[(x + 0.7, y - 0.4) for x, y in cs] for _, _, cs in chans]
+    obs = [el.obs_dict(o) for o in b.observables(seeds)]
+    for c, ((prob, n0, centres), lat) in enumerate(zip(chans, lats)):
+        alone = lat.observables(seeds=seeds[c])
+        assert obs[c]["ntubes"] == len(centres)
+        assert np.array_equal(obs[c]["tube_weight"], alone["tube_weight"]), c
+        assert np.array_equal(obs[c]["tube_centroid"], alone["tube_centroid"]), c
+        o = oracle_for(prob)
+        o.init(lat.get("n"))
+        w, cen = o.tube_centroids(seeds[c])
+        assert np.abs(obs[c]["tube_weight"] - w).max() < 1e-12 * w.max(), c
+        assert np.abs(obs[c]["tube_centroid"] - cen).max() < 1e-9, c
 
 
 def test_capture_on_null_stream_is_rejected():

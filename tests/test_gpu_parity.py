@@ -252,8 +252,9 @@ def test_mass_and_observables_match_oracle():
     x = np.arange(prob.nx)[None, None, :]
     ang = 2 * math.pi * x / prob.nx
     cx = math.atan2((w * np.sin(ang)).sum(), (w * np.cos(ang)).sum()) * prob.nx / (2 * math.pi) % prob.nx
-    assert abs(og["tube_weight"] - w.sum()) < 1e-10 * w.sum()
-    assert abs(og["tube_centroid"][0] - cx) < 1e-9
+    assert og["ntubes"] == 1
+    assert abs(og["tube_weight"][0] - w.sum()) < 1e-10 * w.sum()
+    assert abs(og["tube_centroid"][0][0] - cx) < 1e-9
 
 
 def test_nonfinite_flag():
@@ -335,7 +336,7 @@ def test_tube_drift_unwraps_across_the_period():
     ang = 2 * math.pi * x / prob.nx
     host_unwrapped, last = None, None
     for k in range(12):
-        d = lat.track_drift()
+        d = lat.track_drift(seeds=[(39.9, 10.0)])
         n = o.get("n")
         w = np.maximum(0.0, -n[2])
         cx = math.atan2((w * np.sin(ang)).sum(), (w * np.cos(ang)).sum()) * prob.nx / (2 * math.pi) % prob.nx
@@ -346,13 +347,86 @@ def test_tube_drift_unwraps_across_the_period():
             dlt -= prob.nx * math.floor(dlt / prob.nx + 0.5)
             host_unwrapped += dlt
         last = cx
-        assert abs(d["centroid"][0] - cx) < 1e-8
-        assert abs(d["unwrapped"][0] - host_unwrapped) < 1e-8
+        assert abs(d["centroid"][0][0] - cx) < 1e-8
+        assert abs(d["unwrapped"][0][0] - host_unwrapped) < 1e-8
         lat.run(50)
         o.run(50)
     _say(f"tube displacement {d['displacement']} over {d['steps']} steps")
     assert d["ncalls"] == 12 and d["steps"] == 550
-    assert abs(d["displacement"][0]) > 0.05
+    assert abs(d["displacement"][0][0]) > 0.05
+
+
+def _three_tubes():
+    """A 48x40 channel with three tubes, one across the periodic x boundary."""
+    mat = inputs.set_b()
+    prob = inputs.channel(48, 40, 12, mat, g=(6e-5, 0.0, 0.0), K=3e-3, q0=2 * math.pi / 16, fd_ratio=5)
+    centres = [(47.5, 8.0), (16.0, 20.5), (33.0, 31.0)]
+    seeds = [(1.0, 9.0), (15.0, 22.0), (34.5, 30.0)]
+    return prob, inputs.director_tubes(prob, centres, 6.0), centres, seeds
+
+
+@pytest.mark.parametrize("precision", ["f64_shifted", "f32_shifted"])
+def test_tube_centroids_match_oracle(precision):
+    """Per-tube weights and circular-mean centroids (nearest-seed assignment)
+    against the oracle's, on the director the GPU itself holds after a
+    coupled run; FP64 parity of the fields on top for the FP64 variant."""
+    prob, n0, centres, seeds = _three_tubes()
+    lat = _gpu(prob, n0, precision, 60)
+    og = lat.observables(seeds=seeds)
+    o = _oracle(prob, n0)
+    o.set("n", lat.get("n"))
+    w, c = o.tube_centroids(seeds)
+    _say(f"tubes {precision}: weights {og['tube_weight']} centroids {og['tube_centroid'].tolist()}")
+    assert og["ntubes"] == 3
+    assert np.abs(og["tube_weight"] - w).max() < 1e-12 * w.max()
+    assert np.abs(og["tube_centroid"] - c).max() < 1e-9
+    if precision == "f64_shifted":
+        o2 = _oracle(prob, n0, 60)
+        w2, c2 = o2.tube_centroids(seeds)
+        assert np.abs(og["tube_centroid"] - c2).max() < 1e-9
+        assert np.abs(og["tube_weight"] - w2).max() < 1e-10 * w2.max()
+    # every tube still sits near its ansatz centre after 60 steps
+    for k, (cx, cy) in enumerate(centres):
+        assert abs((og["tube_centroid"][k][0] - cx + 24) % 48 - 24) < 1.0
+
+
+def test_tube_drift_follows_three_tubes():
+    """The tracker moves each seed to its tube's centroid and unwraps each tube
+    separately; checked against the oracle's per-tube centroids with the same
+    moving seeds, the first tube crossing the periodic boundary."""
+    prob, n0, centres, seeds = _three_tubes()
+    lat = _gpu(prob, n0, "f64_shifted")
+    o = _oracle(prob, n0)
+    cur = list(seeds)
+    unwrapped = None
+    for k in range(10):
+        d = lat.track_drift(seeds=seeds)
+        w, c = o.tube_centroids(cur)
+        if unwrapped is None:
+            unwrapped = c.copy()
+        else:
+            dl = c - last
+            dl -= np.array([prob.nx, prob.ny]) * np.floor(dl / np.array([prob.nx, prob.ny]) + 0.5)
+            unwrapped += dl
+        last = c.copy()
+        cur = [tuple(v) for v in c]
+        assert np.abs(d["centroid"] - c).max() < 1e-8
+        assert np.abs(d["unwrapped"] - unwrapped).max() < 1e-8
+        assert np.abs(d["seed"] - c).max() < 1e-8
+        lat.run(40)
+        o.run(40)
+    _say(f"three tubes: displacement {d['displacement'].tolist()} over {d['steps']} steps")
+    assert d["ncalls"] == 10 and d["steps"] == 360
+    assert (np.abs(d["displacement"][:, 0]) > 0.02).all()
+
+
+def test_observables_reject_bad_tube_count():
+    prob, n0, _, seeds = _three_tubes()
+    lat = _gpu(prob, n0, "f32_shifted")
+    with pytest.raises(el.ElError):
+        lat.observables(seeds=[(1.0, 1.0)] * 9)
+    with pytest.raises(el.ElError):
+        lat.observables(seeds=[])
 
 
 # ---------------------------------------------------------------------------

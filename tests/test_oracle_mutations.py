@@ -59,6 +59,9 @@ MUTATIONS = [
      "if ((s->t + 1) % s->p.fd_ratio == 0) or_step_director(s);"),
     ("no_initial_force", "or_force(s); /* R10: initial force from n0 with u = 0 */", "/* no initial force */"),
     ("no_force_after_fd", "    or_force(s);\n}\n\n/* Hybrid loop", "}\n\n/* Hybrid loop"),
+    # tube centroids (R14)
+    ("tube_no_minimum_image", "dx -= p->nx * floor(dx / p->nx + 0.5);", ""),
+    ("tube_circular_mean_swapped", "atan2(sums[t][2], sums[t][1])", "atan2(sums[t][1], sums[t][2])"),
     ("no_moments_after_stream", "        lbm_step(s);\n        or_moments(s);", "        lbm_step(s);"),
 ]
 
@@ -90,6 +93,7 @@ PINS = [
     lambda: pins.test_hybrid_loop_matches_numpy_step(4, 4, 6, 2, True),
     lambda: pins.test_hybrid_loop_matches_numpy_step(3, 5, 6, 3, False),
     pins.test_hybrid_loop_variants_match_numpy_step,
+    pins.test_tube_centroids_of_analytic_tubes,
 ]
 
 

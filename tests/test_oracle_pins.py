@@ -705,3 +705,33 @@ def test_hybrid_loop_variants_match_numpy_step():
         ref.run(4)
         for name, want in (("q", ref.q), ("u", ref.u), ("n", ref.n), ("nP", ref.nP), ("F", ref.F)):
             assert _rel(o.get(name), want) < 1e-13, (periodic, renorm, name)
+
+
+# ---------------------------------------------------------------------------
+# Tube centroids (R14): nearest-seed assignment and periodic circular means.
+
+def test_tube_centroids_of_analytic_tubes():
+    """Three ansatz tubes with centres on node or half-node coordinates, one
+    across the periodic x boundary and one across the y boundary: the sampled
+    weights are symmetric about each centre, so each circular mean is the
+    centre itself; seeds a few nodes off (one on the far side of the boundary)
+    still pick the right nodes, and each tube's weight is that of a lone tube."""
+    prob = inputs.channel(40, 36, 6, inputs.set_b(), K=1e-3, q0=2 * math.pi / 16)
+    R = 6.0
+    centres = [(0.5, 10.0), (20.0, 35.5), (27.5, 18.0)]
+    seeds = [(38.0, 11.5), (18.5, 1.0), (29.0, 16.0)]
+    o = oracle_for(prob)
+    o.init(inputs.director_tubes(prob, centres, R))
+    w, c = o.tube_centroids(seeds)
+    for k, (cx, cy) in enumerate(centres):
+        assert abs((c[k, 0] - cx + 20) % 40 - 20) < 1e-12 and abs((c[k, 1] - cy + 18) % 36 - 18) < 1e-12, (k, c[k])
+        lone = oracle_for(prob)
+        lone.init(inputs.director_tubes(prob, [(cx, cy)], R))
+        n = lone.get("n")
+        assert abs(w[k] - np.maximum(0.0, -n[2]).sum()) < 1e-12 * w[k]
+    # a seed with no tube keeps its place and gets no weight
+    w4, c4 = o.tube_centroids(seeds + [(10.0, 30.0)])
+    assert np.array_equal(w4[:3], w) and w4[3] == 0.0 and tuple(c4[3]) == (10.0, 30.0)
+    # one seed takes every tube: the circular mean of the whole weight
+    w1, c1 = o.tube_centroids([(5.0, 5.0)])
+    assert abs(w1[0] - w.sum()) < 1e-12 * w.sum()
