@@ -195,14 +195,17 @@ size_t el_buffer_bytes(const el_params* p, int32_t which);
  * with EL_PERIODIC_Z), tau <= 1/2, r < 1, gamma1 = alpha3 - alpha2 <= 0 with
  * coupling, unknown precision or flags, both force-kernel flags.  EL_EUNSTABLE (unless
  * EL_ALLOW_UNSTABLE): r * 12 K / gamma1 > 2 (the explicit Heun step on the
- * compact Laplacian); r = 1 with coupling and tau > 1.5 (the Leslie force
- * refreshed every LBM step diverges there within a few hundred steps: an
- * empirical bound, found with the FP64 CPU implementation); or a Mach
- * estimate |g| H^2/(8 nu) sqrt(3) > 0.1.  Passing does not guarantee long
- * runs: a force held over an odd number r of LBM steps can feed the
- * lattice's sign-alternating (period-2) velocity modes, which then grow
- * slowly (seen over 5,000-25,000 steps at r = 1, tau = 0.8 and r = 5,
- * tau = 1.8977 with strongly distorted directors); even r never diverged. */
+ * compact Laplacian); an odd r with coupling and tau > 1.5; or a Mach
+ * estimate |g| H^2/(8 nu) sqrt(3) > 0.1.  The odd-r bound is empirical: a
+ * force held over an odd number of LBM steps meets the lattice's
+ * sign-alternating (period-2) velocity modes with the opposite sign at each
+ * FD step and pumps them (over an even number the kicks cancel).  With the
+ * Table-1 viscosities at tau = 1.8977 the FP64 CPU implementation grows
+ * without bound for r = 1, 3 and 5 within a few thousand steps and stays
+ * bounded for r = 2, 4 and 10.  Passing does not guarantee long runs: at
+ * tau <= 1.5 an odd r grows far more slowly but can still diverge (r = 1 at
+ * tau = 0.8 within a few thousand steps on strongly distorted directors);
+ * even r never diverged.  Watch el_obs.nonfinite and max_u. */
 int el_validate(const el_params* p);
 
 /* Initialisation (Sec. II D, first step): q = rest state (0 when shifted,

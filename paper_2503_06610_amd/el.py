@@ -27,7 +27,8 @@ PRECISIONS = {"f64": EL_F64, "f64_shifted": EL_F64_SHIFTED, "f32": EL_F32, "f32_
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTED = ("el_version", "el_strerror", "el_last_error", "el_buffer_bytes", "el_validate", "el_init_lattice",
             "el_init_flow", "el_step_lbm", "el_moments", "el_step_director", "el_force", "el_run",
-            "el_observables", "el_tube_drift", "el_error_norms", "el_batch_create", "el_batch_step", "el_batch_capture",
+            "el_observables", "el_tube_drift", "el_error_norms", "el_batch_create",
+            "el_batch_step", "el_batch_capture",
             "el_batch_moments", "el_batch_observables", "el_batch_sync", "el_batch_get_tuning", "el_batch_destroy",
             "el_nn_input", "el_nn_conv_forward", "el_nn_conv_backward_data", "el_nn_work_bytes",
             "el_nn_conv_backward_weight", "el_nn_mse", "el_nn_adam", "el_nn_velocity", "el_halo_pack",
@@ -77,10 +78,12 @@ class el_drift(C.Structure):
 
 
 def make_tubes(seeds) -> el_tubes:
-    """el_tubes from a list of (x, y) seeds (1..EL_MAX_TUBES)."""
+    """el_tubes from a list of (x, y) seeds.  The count is passed as given and
+    the library validates it (1..EL_MAX_TUBES); seeds beyond the struct's
+    capacity are not copied."""
     t = el_tubes()
     t.ntubes = len(seeds)
-    for k, (x, y) in enumerate(seeds):
+    for k, (x, y) in enumerate(seeds[:EL_MAX_TUBES]):
         t.seed[k][0], t.seed[k][1] = float(x), float(y)
     return t
 
@@ -300,7 +303,7 @@ class Lattice:
             d0 = el_drift()
             seeds = seeds if seeds is not None else [(self.prob.nx / 2.0, self.prob.ny / 2.0)]
             d0.ntubes = len(seeds)
-            for k, (x, y) in enumerate(seeds):
+            for k, (x, y) in enumerate(seeds[:EL_MAX_TUBES]):
                 d0.seed[k][0], d0.seed[k][1] = float(x), float(y)
             host = np.frombuffer(bytes(d0) + b"\0" * (-C.sizeof(el_drift) % 8), dtype=np.float64).copy()
             self.drift_buf = torch.from_numpy(host).to(self.n.device)

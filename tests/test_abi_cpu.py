@@ -76,7 +76,7 @@ def test_validate_accepts_workloads():
     ("flags", 128, el.EL_EINVAL),
     ("K", 0.5, el.EL_EUNSTABLE),
     ("fd_ratio", 2, el.EL_EUNSTABLE),  # C1 with K = 0.01: r*12K/gamma1 = 2.6
-    ("tau", 1.9, el.EL_EUNSTABLE),     # r = 1 with tau > 1.5
+    ("tau", 1.9, el.EL_EUNSTABLE),     # odd r (here 1) with tau > 1.5
 ])
 def test_validate_rejects(field, value, code):
     prob = inputs.workload_c1()[0]
@@ -84,6 +84,23 @@ def test_validate_rejects(field, value, code):
     setattr(p, field, value)
     assert el.validate(p) == code
     assert el.load().el_last_error()
+
+
+@pytest.mark.parametrize("r,code", [(1, el.EL_EUNSTABLE), (2, el.EL_OK), (3, el.EL_EUNSTABLE), (4, el.EL_OK),
+                                    (5, el.EL_EUNSTABLE), (10, el.EL_OK)])
+def test_validate_odd_r_at_large_tau(r, code):
+    """Table-1 viscosities at tau = 1.8977: an odd r with coupling is rejected
+    (the period-2 velocity modes grow, see test_stability_cpu.py); the same
+    lattice without coupling, or with EL_ALLOW_UNSTABLE, is accepted."""
+    prob = inputs.channel(32, 32, 16, inputs.set_b(), g=(1e-6, 0.0, 0.0), K=1e-3, fd_ratio=r)
+    assert el.validate(el.make_params(prob, "f32_shifted")) == code
+    assert el.validate(el.make_params(prob.with_(coupling=False), "f32_shifted")) == el.EL_OK
+    p = el.make_params(prob, "f32_shifted")
+    p.flags |= el.EL_ALLOW_UNSTABLE
+    assert el.validate(p) == el.EL_OK
+    # tau <= 1.5 (Leslie set A) stays accepted at every r
+    prob_a = inputs.channel(32, 32, 16, inputs.set_a(), g=(1e-6, 0.0, 0.0), K=1e-3, fd_ratio=r)
+    assert el.validate(el.make_params(prob_a, "f32_shifted")) == el.EL_OK
 
 
 def test_validate_rejects_nonpositive_gamma1_and_nan():

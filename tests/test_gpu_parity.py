@@ -21,9 +21,9 @@ def _say(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def _gpu(prob, n0, precision, T=0):
+def _gpu(prob, n0, precision, T=0, allow_unstable=False):
     import torch
-    lat = el.Lattice(prob, precision)
+    lat = el.Lattice(prob, precision, allow_unstable=allow_unstable)
     lat.init_lattice(n0)
     if T:
         lat.run(T)
@@ -83,14 +83,16 @@ def test_c1_fp32_shifted_within_targets():
 
 def test_ragged_lattice_all_terms_fp64():
     """Odd sizes (tiles with ragged tails), chirality, bulk anchoring, alpha4',
-    r = 3 and a run that ends inside an FD interval."""
+    r = 3 and a run that ends inside an FD interval.  An odd r at tau = 1.8977
+    is outside el_validate's bounds (period-2 modes grow over thousands of
+    steps); over these 20 steps it is a plain parity case."""
     mat = inputs.set_b()
     prob = inputs.Problem(nx=13, ny=7, nz=11, tau=mat.tau, alpha=mat.alpha, alpha4p=0.02, g=(3e-6, 1e-6, 0.0),
                           K=4e-3, q0=2 * math.pi / 9, W0=2e-4, fd_ratio=3)
     n0 = inputs.director_tubes(prob, [(6.0, 3.0)], 3.5)
     for precision in ("f64", "f64_shifted"):
         _say(f"ragged {precision}")
-        lat = _gpu(prob, n0, precision, 20)
+        lat = _gpu(prob, n0, precision, 20, allow_unstable=True)
         o = _oracle(prob, n0, 20, shifted=precision.endswith("shifted"))
         assert rel_l2(lat.get("u"), o.get("u")) < 1e-11
         assert rel_l2(lat.get("n"), o.get("n")) < 1e-12
@@ -328,7 +330,7 @@ def test_tube_drift_unwraps_across_the_period():
     oracle's director, with the tube starting on the periodic boundary so
     that its centroid wraps from x ~ nx to x ~ 0 while it is carried along."""
     mat = inputs.set_b()
-    prob = inputs.channel(40, 20, 14, mat, g=(8e-5, 0.0, 0.0), K=3e-3, q0=2 * math.pi / 16, fd_ratio=5)
+    prob = inputs.channel(40, 20, 14, mat, g=(8e-5, 0.0, 0.0), K=3e-3, q0=2 * math.pi / 16, fd_ratio=4)
     n0 = inputs.director_tubes(prob, [(39.9, 10.0)], 6.0)
     lat = _gpu(prob, n0, "f64_shifted")
     o = _oracle(prob, n0)
@@ -359,7 +361,7 @@ def test_tube_drift_unwraps_across_the_period():
 def _three_tubes():
     """A 48x40 channel with three tubes, one across the periodic x boundary."""
     mat = inputs.set_b()
-    prob = inputs.channel(48, 40, 12, mat, g=(6e-5, 0.0, 0.0), K=3e-3, q0=2 * math.pi / 16, fd_ratio=5)
+    prob = inputs.channel(48, 40, 12, mat, g=(6e-5, 0.0, 0.0), K=3e-3, q0=2 * math.pi / 16, fd_ratio=4)
     centres = [(47.5, 8.0), (16.0, 20.5), (33.0, 31.0)]
     seeds = [(1.0, 9.0), (15.0, 22.0), (34.5, 30.0)]
     return prob, inputs.director_tubes(prob, centres, 6.0), centres, seeds
