@@ -20,6 +20,19 @@
  *   R4  one-constant Frank energy
  *         f = K/2 (d_b n_g)^2 + K q0 n.(curl n) - W0/2 (n_z)^2
  *       so h = K lap n - 2 K q0 curl n + W0 n_z z-hat; h is not projected.
+ *   R4' three-constant Frank energy (frank3): with S = div n, c = curl n,
+ *       T = n.c, B = n x c the printed density K11/2 S^2 + K22/2 (T + q0)^2
+ *       + K33/2 |B|^2 is, for |n| = 1 and up to a null Lagrangian and a
+ *       constant, the one-constant density with K = Km = min(K11, K22, K33)
+ *       plus corrections:
+ *         f = Km/2 (d_b n_g)^2 + K22 q0 T + (K11-Km)/2 S^2
+ *           + (K22-Km)/2 T^2 + (K33-Km)/2 |B|^2 - W0/2 n_z^2.
+ *       h = -df/dn + d_b df/d(d_b n) takes the Km part with the compact
+ *       Laplacian as in R4 and expands the corrections by the product rule
+ *       into first and second derivatives of n at the node: central first
+ *       differences, compact diagonal and four-point mixed second differences
+ *       (the edge neighbours of the node).  With K11 = K22 = K33 this is R4
+ *       exactly.
  *   R5  the predictor is normalised when renorm_predictor is set; the
  *       corrector always is.
  *   R6  N in the Leslie stress is (h - gamma2 D n)/gamma1 at the new director.
@@ -316,6 +329,129 @@ static void grad3(const or_state* st, const double* m, int kind, int x, int y, i
             G[b][g] = 0.5 * (nb(st, m, kind, g, x, y, z, b, +1) - nb(st, m, kind, g, x, y, z, b, -1));
 }
 
+/* Value of component c of a field at (x, y, z) + sa e_a + sb e_b (a != b),
+ * periodic in x, y (and z when periodic_z); the solid value if that node is
+ * solid. */
+static double nb2(const or_state* st, const double* f, int field_kind, int c, int x, int y, int z, int a, int sa, int b,
+                  int sb)
+{
+    const or_params* p = &st->p;
+    int co[3] = {x, y, z};
+    co[a] += sa;
+    co[b] += sb;
+    co[0] = wrap(co[0], p->nx);
+    co[1] = wrap(co[1], p->ny);
+    if (p->periodic_z) co[2] = wrap(co[2], p->nz);
+    if (is_solid(p, co[2])) return solid_value(field_kind, c);
+    return f[(int64_t)c * st->N + idx(p, co[0], co[1], co[2])];
+}
+
+/* H[a][b][g] = d_a d_b m_g: compact 3-point difference for a == b, the
+ * four-point central difference over the edge neighbours for a != b. */
+static void hess3(const or_state* st, const double* m, int x, int y, int z, double H[3][3][3])
+{
+    const or_params* p = &st->p;
+    int64_t k = idx(p, x, y, z);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            for (int g = 0; g < 3; ++g) {
+                if (a == b)
+                    H[a][b][g] = nb(st, m, 0, g, x, y, z, a, +1) - 2.0 * m[(int64_t)g * st->N + k] +
+                                 nb(st, m, 0, g, x, y, z, a, -1);
+                else
+                    H[a][b][g] = 0.25 * (nb2(st, m, 0, g, x, y, z, a, +1, b, +1) - nb2(st, m, 0, g, x, y, z, a, +1, b, -1) -
+                                         nb2(st, m, 0, g, x, y, z, a, -1, b, +1) + nb2(st, m, 0, g, x, y, z, a, -1, b, -1));
+            }
+}
+
+/* The constants of the elastic energy: Km (the compact-Laplacian part), Kt
+ * (the chiral term's constant) and the corrections a[3] of R4'. */
+static void frank_constants(const or_params* p, double* Km, double* Kt, double a[3])
+{
+    if (!p->frank3) {
+        *Km = p->K;
+        *Kt = p->K;
+        a[0] = a[1] = a[2] = 0.0;
+        return;
+    }
+    double m = p->K11;
+    if (p->K22 < m) m = p->K22;
+    if (p->K33 < m) m = p->K33;
+    *Km = m;
+    *Kt = p->K22;
+    a[0] = p->K11 - m;
+    a[1] = p->K22 - m;
+    a[2] = p->K33 - m;
+}
+
+/* Splay, twist and bend pieces of the director gradient at a node (R4'):
+ * S = d_g n_g, c_g = eps_gab d_a n_b, T = n.c, B = n x c. */
+typedef struct {
+    double S, c[3], T, B[3];
+} frank_parts;
+
+static void frank_parts_of(const double n[3], const double G[3][3], frank_parts* fp)
+{
+    fp->S = G[0][0] + G[1][1] + G[2][2];
+    for (int g = 0; g < 3; ++g) {
+        fp->c[g] = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) fp->c[g] += eps3(g, a, b) * G[a][b];
+    }
+    fp->T = n[0] * fp->c[0] + n[1] * fp->c[1] + n[2] * fp->c[2];
+    for (int m = 0; m < 3; ++m) {
+        fp->B[m] = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) fp->B[m] += eps3(m, a, b) * n[a] * fp->c[b];
+    }
+}
+
+/* Corrections of R4' to h at a node:
+ *   a1 d_mu S
+ * + a2 [ (n x grad T)_mu - 2 T c_mu ]
+ * + a3 [ (div B) n_mu + B_b d_b n_mu - n_b d_b B_mu - S B_mu - (c x B)_mu ],
+ * with d_b c_g = eps_gpq d_b d_p n_q, d_b T = d_b n_g c_g + n_g d_b c_g and
+ * d_b B_m = eps_mpq (d_b n_p c_q + n_p d_b c_q). */
+static void frank3_correction(const double n[3], const double G[3][3], const double H[3][3][3], const double a[3],
+                              double dh[3])
+{
+    frank_parts fp;
+    frank_parts_of(n, G, &fp);
+    double dS[3], dc[3][3], dT[3], dB[3][3];
+    for (int mu = 0; mu < 3; ++mu) dS[mu] = H[mu][0][0] + H[mu][1][1] + H[mu][2][2];
+    for (int b = 0; b < 3; ++b)
+        for (int g = 0; g < 3; ++g) {
+            dc[b][g] = 0.0;
+            for (int pp = 0; pp < 3; ++pp)
+                for (int q = 0; q < 3; ++q) dc[b][g] += eps3(g, pp, q) * H[b][pp][q];
+        }
+    for (int b = 0; b < 3; ++b) {
+        dT[b] = 0.0;
+        for (int g = 0; g < 3; ++g) dT[b] += G[b][g] * fp.c[g] + n[g] * dc[b][g];
+    }
+    for (int b = 0; b < 3; ++b)
+        for (int m = 0; m < 3; ++m) {
+            dB[b][m] = 0.0;
+            for (int pp = 0; pp < 3; ++pp)
+                for (int q = 0; q < 3; ++q) dB[b][m] += eps3(m, pp, q) * (G[b][pp] * fp.c[q] + n[pp] * dc[b][q]);
+        }
+    double divB = dB[0][0] + dB[1][1] + dB[2][2];
+    for (int mu = 0; mu < 3; ++mu) {
+        double nxdT = 0.0, cxB = 0.0, BdN = 0.0, ndB = 0.0;
+        for (int pp = 0; pp < 3; ++pp)
+            for (int q = 0; q < 3; ++q) {
+                nxdT += eps3(mu, pp, q) * n[pp] * dT[q];
+                cxB += eps3(mu, pp, q) * fp.c[pp] * fp.B[q];
+            }
+        for (int b = 0; b < 3; ++b) {
+            BdN += fp.B[b] * G[b][mu];
+            ndB += n[b] * dB[b][mu];
+        }
+        dh[mu] = a[0] * dS[mu] + a[1] * (nxdT - 2.0 * fp.T * fp.c[mu]) +
+                 a[2] * (divB * n[mu] + BdN - ndB - fp.S * fp.B[mu] - cxB);
+    }
+}
+
 /* Molecular field h = -dE/dn for the one-constant energy (R4):
  *   h = K lap m - 2 K q0 curl m + W0 m_z z-hat,
  * with the compact Laplacian sum_b [m(x+b) - 2 m(x) + m(x-b)] (R3). */
@@ -323,7 +459,8 @@ static void molecular_field(const or_state* st, const double* m, int x, int y, i
 {
     const or_params* p = &st->p;
     int64_t k = idx(p, x, y, z);
-    double G[3][3];
+    double G[3][3], Km, Kt, a[3];
+    frank_constants(p, &Km, &Kt, a);
     grad3(st, m, 0, x, y, z, G);
     for (int g = 0; g < 3; ++g) {
         double mc = m[(int64_t)g * st->N + k];
@@ -333,9 +470,17 @@ static void molecular_field(const or_state* st, const double* m, int x, int y, i
         double curl = 0.0; /* curl_g = eps_{g a b} d_a m_b */
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) curl += eps3(g, a, b) * G[a][b];
-        h[g] = p->K * lap - 2.0 * p->K * p->q0 * curl;
+        h[g] = Km * lap - 2.0 * Kt * p->q0 * curl;
     }
     h[2] += p->W0 * m[2 * st->N + k];
+    if (p->frank3) {
+        /* R4' corrections */
+        double H[3][3][3], n[3], dh[3];
+        hess3(st, m, x, y, z, H);
+        for (int g = 0; g < 3; ++g) n[g] = m[(int64_t)g * st->N + k];
+        frank3_correction(n, G, H, a, dh);
+        for (int g = 0; g < 3; ++g) h[g] += dh[g];
+    }
 }
 
 /* Velocity-gradient tensors [HE]: A[b][a] = d_b u_a,
@@ -387,7 +532,10 @@ static void normalise(double v[3])
  *   sigma_ab = a1 n_a n_b (n.D.n) + a2 n_b N_a + a3 n_a N_b + a4' D_ab
  *            + a5 n_b (D n)_a + a6 n_a (D n)_b - d_a n_g Pi_bg,
  *   N = (h - gamma2 D n)/gamma1 (R6),
- *   Pi_bg = df/d(d_b n_g) = K d_b n_g + K q0 eps_{m b g} n_m. */
+ *   Pi_bg = df/d(d_b n_g) = K d_b n_g + K q0 eps_{m b g} n_m (R4), or for
+ *   the three-constant energy (R4')
+ *   Pi_bg = Km d_b n_g + (K22 q0 + a2 T) eps_{m b g} n_m + a1 S delta_bg
+ *         + a3 (B_b n_g - B_g n_b). */
 static void stress_node(const or_state* st, int term_mask, int x, int y, int z, double sig[3][3])
 {
     const or_params* p = &st->p;
@@ -407,11 +555,18 @@ static void stress_node(const or_state* st, int term_mask, int x, int y, int z, 
     }
     for (int a = 0; a < 3; ++a) nDn += n[a] * Dn[a];
     for (int a = 0; a < 3; ++a) N[a] = (h[a] - gamma2 * Dn[a]) / gamma1;
+    double Km, Kt, ac[3];
+    frank_constants(p, &Km, &Kt, ac);
+    frank_parts fp;
+    frank_parts_of(n, G, &fp);
     for (int b = 0; b < 3; ++b)
         for (int g = 0; g < 3; ++g) {
             double chiral = 0.0;
             for (int m = 0; m < 3; ++m) chiral += eps3(m, b, g) * n[m];
-            Pi[b][g] = p->K * G[b][g] + p->K * p->q0 * chiral;
+            Pi[b][g] = Km * G[b][g] + Kt * p->q0 * chiral;
+            if (p->frank3)
+                Pi[b][g] += ac[0] * fp.S * (b == g ? 1.0 : 0.0) + ac[1] * fp.T * chiral +
+                            ac[2] * (fp.B[b] * n[g] - fp.B[g] * n[b]);
         }
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {

@@ -47,6 +47,9 @@ typedef struct {
     double K, q0, W0;       /* one-constant Frank elasticity, chirality, bulk anchoring */
     double alpha[6];        /* Leslie alpha1..alpha6 (alpha[3] is informational) */
     double alpha4p;         /* alpha4' carried by the finite-difference force */
+    int32_t frank3;         /* 1: three-constant Frank energy with K11, K22, K33 (K unused) */
+    int32_t reserved;
+    double K11, K22, K33;   /* splay, twist, bend constants (used when frank3) */
 } or_params;
 
 typedef struct or_state or_state;

@@ -34,7 +34,9 @@ class _Params(C.Structure):
                 ("renorm_predictor", C.c_int32), ("coupling", C.c_int32),
                 ("tau", C.c_double), ("g", C.c_double * 3),
                 ("K", C.c_double), ("q0", C.c_double), ("W0", C.c_double),
-                ("alpha", C.c_double * 6), ("alpha4p", C.c_double)]
+                ("alpha", C.c_double * 6), ("alpha4p", C.c_double),
+                ("frank3", C.c_int32), ("reserved", C.c_int32),
+                ("K11", C.c_double), ("K22", C.c_double), ("K33", C.c_double)]
 
 
 class _Obs(C.Structure):
@@ -134,6 +136,10 @@ class OracleParams:
     periodic_z: bool = False
     renorm_predictor: bool = True
     coupling: bool = True
+    frank3: bool = False
+    K11: float = 0.0
+    K22: float = 0.0
+    K33: float = 0.0
 
     @property
     def nzf(self) -> int:
@@ -152,6 +158,8 @@ class OracleParams:
         p.K, p.q0, p.W0 = self.K, self.q0, self.W0
         p.alpha = (C.c_double * 6)(*self.alpha)
         p.alpha4p = self.alpha4p
+        p.frank3 = int(self.frank3)
+        p.K11, p.K22, p.K33 = self.K11, self.K22, self.K33
         return p
 
 

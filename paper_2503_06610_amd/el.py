@@ -178,6 +178,8 @@ def _check(status: int, what: str):
 
 def make_params(prob, precision: str = "f32_shifted") -> el_params:
     """el_params from a seeded Problem (paper_2503_06610_amd.inputs)."""
+    if getattr(prob, "frank3", False):
+        raise ElError(EL_EINVAL, "make_params", "the three-constant Frank energy is not supported by libel.so yet")
     p = el_params()
     p.nx, p.ny, p.nz = prob.nx, prob.ny, prob.nz
     p.precision = PRECISIONS[precision]

@@ -84,6 +84,10 @@ class Problem:
     periodic_z: bool = False
     renorm_predictor: bool = True
     coupling: bool = True
+    frank3: bool = False   # three-constant Frank energy with K11, K22, K33 (K unused)
+    K11: float = 0.0
+    K22: float = 0.0
+    K33: float = 0.0
 
     @property
     def nzf(self) -> int:

@@ -1,0 +1,246 @@
+"""Pins of the oracle's three-constant Frank elasticity (Sec. II A, the
+Frank-Oseen energy with splay, twist and bend constants K11, K22, K33).
+
+The oracle evaluates the printed energy in a split form (its reading R4'):
+with S = div n, c = curl n, T = n.c, B = n x c and Km = min(K11, K22, K33),
+
+    f' = Km/2 |grad n|^2 + K22 q0 T + (K11-Km)/2 S^2 + (K22-Km)/2 T^2
+       + (K33-Km)/2 |B|^2,
+
+which differs from the printed K11/2 S^2 + K22/2 (T + q0)^2 + K33/2 |B|^2 by a
+null Lagrangian, a constant and Km/2 (|n|^2 - 1)|c|^2.  The pins below fix it
+against things the oracle does not compute itself:
+
+* equal constants reduce to the one-constant path bit for bit;
+* the discrete relaxation rate of a small splay, twist and bend mode about a
+  uniform director is K11, K22 and K33 times the compact Laplacian symbol (the
+  Heun growth factor per FD step, to 1e-6);
+* the molecular field converges at second order to h = -dE'/dn taken
+  symbolically (sympy) from f', and on a unit director field sympy's h of the
+  printed energy is that h minus Km |c|^2 n exactly (a radial term, which the
+  renormalisation of the director removes);
+* the elastic stress satisfies the Ericksen identity
+  d_b sigma^e_ab = -(d_a n_g) h_g - d_a f' at second order.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2503_06610_amd import inputs
+from tests.helpers import oracle_for
+
+RNG = np.random.default_rng(2024)
+KS = (0.013, 0.006, 0.021)  # distinct splay, twist, bend constants
+
+
+def _box(n=12, **kw):
+    base = dict(nx=n, ny=n, nz=n, periodic_z=True, tau=0.8, alpha=(0, -0.2, 0.1, 0, 0, 0))
+    base.update(kw)
+    return inputs.Problem(**base)
+
+
+def _frank3(prob, K11, K22, K33):
+    return prob.with_(frank3=True, K11=K11, K22=K22, K33=K33, K=0.0)
+
+
+def _random_unit(shape):
+    n = RNG.normal(size=shape)
+    n[2] += 2.0
+    return n / np.sqrt((n * n).sum(0))
+
+
+def test_equal_constants_reduce_to_one_constant():
+    """K11 = K22 = K33 = K: h, the stress and F of the three-constant path are
+    those of the one-constant path bit for bit, and so is a coupled run with
+    walls, chirality, bulk anchoring and every Leslie term."""
+    K = 0.011
+    prob1 = inputs.channel(9, 7, 8, inputs.set_a(), g=(2e-5, 0, 0), K=K, q0=0.4, W0=1e-3, fd_ratio=2)
+    prob3 = _frank3(prob1, K, K, K)
+    n0 = inputs.director_tilt(prob1, seed=5, amplitude=0.3)
+    o1, o3 = oracle_for(prob1), oracle_for(prob3)
+    o1.init(n0)
+    o3.init(n0)
+    assert np.array_equal(o1.molecular_field(), o3.molecular_field())
+    assert np.array_equal(o1.stress(127), o3.stress(127))
+    assert np.array_equal(o1.get("F"), o3.get("F"))
+    o1.run(12)
+    o3.run(12)
+    for f in ("q", "n", "u", "F"):
+        assert np.array_equal(o1.get(f), o3.get(f)), f
+
+
+@pytest.mark.parametrize("axis,const", [(0, 0), (1, 1), (2, 2)], ids=["splay", "twist", "bend"])
+def test_single_mode_relaxation_rate(axis, const):
+    """Uniform n = z-hat plus dn_x = eps sin(2 pi j/L) along x (splay), y
+    (twist) or z (bend), u = 0, q0 = W0 = 0: every Heun step multiplies the
+    amplitude by 1 + s + s^2/2 with s = -r K_i (2 - 2 cos(2 pi/L))/gamma1."""
+    L, r = 16, 3
+    prob = _frank3(_box(L, coupling=False, fd_ratio=r), *KS)
+    gamma1 = 0.3
+    o = oracle_for(prob)
+    eps = 1e-6
+    coord = np.arange(L)
+    mode = np.sin(2 * math.pi * coord / L)
+    shape = [1, 1, 1]
+    shape[2 - axis] = L  # external layout (zf, y, x)
+    mode = np.broadcast_to(mode.reshape(shape), (L, L, L))
+    n = np.zeros(prob.shape(3))
+    n[0] = eps * mode
+    n[2] = np.sqrt(1 - n[0] ** 2)
+    o.init(n)
+    s = -r * KS[const] / gamma1 * (2 - 2 * math.cos(2 * math.pi / L))
+    growth = 1 + s + s * s / 2
+    M = 10
+    for _ in range(M):
+        o.step_director()
+    nn = o.get("n")
+    amp = (nn[0] * mode).sum() / (mode * mode).sum()
+    assert abs(amp / (eps * growth ** M) - 1.0) < 1e-6
+    assert np.abs(nn[1]).max() < 1e-18
+
+
+def _sym_setup(N, unit):
+    import sympy as sp
+    X = sp.symbols("x y z", real=True)
+    k = 2 * sp.pi / N
+    x, y, z = X
+    v = [sp.Rational(3, 10) * sp.sin(k * x + k * y) + sp.Rational(1, 10) * sp.cos(k * z),
+         sp.Rational(2, 10) * sp.cos(k * x - k * z) + sp.Rational(1, 10) * sp.sin(k * y),
+         1 + sp.Rational(2, 10) * sp.sin(k * y + k * z)]
+    if unit:
+        norm = sp.sqrt(sum(c ** 2 for c in v))
+        v = [c / norm for c in v]
+    return sp, X, v
+
+
+def _variational(sp, X, n, f_of):
+    """h = -df/dn + d_b df/d(d_b n) and f itself, for a density f_of(ns, G)."""
+    ns = [sp.Symbol(f"n{g}") for g in range(3)]
+    G = [[sp.Symbol(f"G{b}{g}") for g in range(3)] for b in range(3)]
+    f = f_of(sp, ns, G)
+    subs = {ns[g]: n[g] for g in range(3)}
+    subs.update({G[b][g]: sp.diff(n[g], X[b]) for b in range(3) for g in range(3)})
+    h = []
+    for g in range(3):
+        term = -sp.diff(f, ns[g]).subs(subs)
+        for b in range(3):
+            term += sp.diff(sp.diff(f, G[b][g]).subs(subs), X[b])
+        h.append(term)
+    return h, f.subs(subs)
+
+
+def _parts(sp, ns, G):
+    S = G[0][0] + G[1][1] + G[2][2]
+    c = [sum(sp.LeviCivita(g, a, b) * G[a][b] for a in range(3) for b in range(3)) for g in range(3)]
+    T = sum(ns[g] * c[g] for g in range(3))
+    B = [sum(sp.LeviCivita(m, a, b) * ns[a] * c[b] for a in range(3) for b in range(3)) for m in range(3)]
+    return S, c, T, B
+
+
+def _split_density(K11, K22, K33, q0):
+    Km = min(K11, K22, K33)
+
+    def f(sp, ns, G):
+        S, c, T, B = _parts(sp, ns, G)
+        return (Km / 2 * sum(G[b][g] ** 2 for b in range(3) for g in range(3)) + K22 * q0 * T
+                + (K11 - Km) / 2 * S ** 2 + (K22 - Km) / 2 * T ** 2 + (K33 - Km) / 2 * sum(b * b for b in B))
+    return f
+
+
+def _printed_density(K11, K22, K33, q0):
+    def f(sp, ns, G):
+        S, c, T, B = _parts(sp, ns, G)
+        return K11 / 2 * S ** 2 + K22 / 2 * (T + q0) ** 2 + K33 / 2 * sum(b * b for b in B)
+    return f
+
+
+def _grid(N):
+    zf, y, x = np.meshgrid(np.arange(N, dtype=float), np.arange(N, dtype=float), np.arange(N, dtype=float),
+                           indexing="ij")
+    return x, y, zf
+
+
+def _eval(sp, X, exprs, N):
+    x, y, zf = _grid(N)
+    vals = sp.lambdify(X, list(exprs), "numpy", cse=True)(x, y, zf)
+    return np.stack([np.broadcast_to(np.asarray(v, dtype=float), x.shape) for v in vals])
+
+
+# (K11, K22, K33) in thousandths: twist smallest (as for the paper's material:
+# no twist correction) and splay smallest (no splay correction)
+ORDERINGS = [(13, 6, 21), (9, 15, 21)]
+
+
+@pytest.mark.parametrize("consts", ORDERINGS, ids=["twist_min", "splay_min"])
+def test_molecular_field_converges_to_variational_derivative(consts):
+    """On a smooth unit director field the oracle's h converges at second order
+    to sympy's -dE'/dn of the split density; sympy's h of the printed density
+    is that h minus Km |c|^2 n exactly."""
+    import sympy
+    K11, K22, K33 = (sympy.Rational(v, 1000) for v in consts)
+    q0 = sympy.Rational(2, 5)
+    Km = min(K11, K22, K33)
+    errs = []
+    for N in (24, 48):  # 12 -> 24 is not yet in the asymptotic range (ratio 3.2)
+        sp, X, n = _sym_setup(N, unit=True)
+        h_split, _ = _variational(sp, X, n, _split_density(K11, K22, K33, q0))
+        prob = _frank3(_box(N, q0=float(q0)), float(K11), float(K22), float(K33))
+        o = oracle_for(prob, threads=4)
+        nv = _eval(sp, X, n, N)
+        o.init(nv)
+        h = o.molecular_field()
+        want = _eval(sp, X, h_split, N)
+        errs.append(np.abs(h - want).max() / np.abs(want).max())
+        if N == 24:
+            h_printed, _ = _variational(sp, X, n, _printed_density(K11, K22, K33, q0))
+            c = [sum(sp.LeviCivita(g, a, b) * sp.diff(n[b], X[a]) for a in range(3) for b in range(3))
+                 for g in range(3)]
+            radial = [Km * sum(cc ** 2 for cc in c) * n[g] for g in range(3)]
+            diff = _eval(sp, X, [h_printed[g] - h_split[g] + radial[g] for g in range(3)], N)
+            assert np.abs(diff).max() < 1e-14 * np.abs(want).max()
+    assert errs[1] < 0.01
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+@pytest.mark.parametrize("consts", ORDERINGS, ids=["twist_min", "splay_min"])
+def test_elastic_stress_satisfies_ericksen_identity_three_constants(consts):
+    """d_b sigma^e_ab = -(d_a n_g) h_g - d_a f' for any field n (not normalised
+    here), with h = -dE'/dn: the discrete elastic force converges to it at
+    second order (periodic box, u = 0)."""
+    import sympy
+    K11, K22, K33 = (sympy.Rational(v, 1000) for v in consts)
+    q0 = sympy.Rational(2, 5)
+    errs = []
+    for N in (24, 48):
+        sp, X, n = _sym_setup(N, unit=False)
+        h, f = _variational(sp, X, n, _split_density(K11, K22, K33, q0))
+        target = [-sum(sp.diff(n[g], X[a]) * h[g] for g in range(3)) - sp.diff(f, X[a]) for a in range(3)]
+        prob = _frank3(_box(N, q0=float(q0)), float(K11), float(K22), float(K33))
+        o = oracle_for(prob, threads=4)
+        o.init(_eval(sp, X, n, N))
+        F = o.force_masked(64)
+        want = _eval(sp, X, target, N)
+        errs.append(np.abs(F - want).max() / np.abs(want).max())
+    # max-norm ratios 4.1, 4.6, 5.7 for N = 12 -> 24 -> 48 -> 96
+    assert errs[1] < 0.02
+    assert 3.5 < errs[0] / errs[1] < 6.0
+
+
+def test_three_constant_director_stays_unit_and_relaxes():
+    """Director-only relaxation with distinct constants between walls: |n| = 1
+    after every FD step, and the tangential molecular field (the elastic
+    torque) relaxes."""
+    prob = _frank3(inputs.channel(10, 9, 10, inputs.set_b(), K=0.0, q0=0.3, coupling=False, fd_ratio=2), *KS)
+    o = oracle_for(prob)
+    n0 = inputs.director_tilt(prob, seed=9, amplitude=0.5)
+    o.init(n0)
+    start = np.abs(o.molecular_field()).max()
+    for _ in range(40):
+        o.step_director()
+        nn = o.get("n")
+        assert np.abs(np.sqrt((nn * nn).sum(0)) - 1.0).max() < 4e-16
+    # the tangential molecular field (the driving torque) has relaxed
+    h = o.molecular_field()
+    ht = h - (h * nn).sum(0) * nn
+    assert np.abs(ht).max() < 0.2 * start

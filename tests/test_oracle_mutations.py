@@ -12,6 +12,7 @@ import subprocess
 import pytest
 
 import oracle.oracle as oo
+from tests import test_frank3_pins as f3
 from tests import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(oo.__file__), "el_oracle.c")
@@ -29,7 +30,7 @@ MUTATIONS = [
     ("stream_direction", "int xd = wrap(x + E[i][0], p->nx);", "int xd = wrap(x - E[i][0], p->nx);"),
     ("weight_edge", "return 1.0 / 36.0;", "return 1.0 / 30.0;"),
     ("laplacian_centre", "- 2.0 * mc +", "- 1.0 * mc +"),
-    ("chirality_sign", "h[g] = p->K * lap - 2.0 * p->K * p->q0 * curl;", "h[g] = p->K * lap + 2.0 * p->K * p->q0 * curl;"),
+    ("chirality_sign", "h[g] = Km * lap - 2.0 * Kt * p->q0 * curl;", "h[g] = Km * lap + 2.0 * Kt * p->q0 * curl;"),
     ("anchoring_sign", "h[2] += p->W0 * m[2 * st->N + k];", "h[2] -= p->W0 * m[2 * st->N + k];"),
     ("vorticity_transposed", "W[a][m] = 0.5 * (A[m][a] - A[a][m]);", "W[a][m] = 0.5 * (A[a][m] - A[m][a]);"),
     ("alignment_sign", "h[mu] / gamma1 - (gamma2 / gamma1) * align", "h[mu] / gamma1 + (gamma2 / gamma1) * align"),
@@ -65,6 +66,21 @@ MUTATIONS = [
     ("no_moments_after_stream", "        lbm_step(s);\n        or_moments(s);", "        lbm_step(s);"),
 ]
 
+# mistakes in the three-constant Frank elasticity (R4'), checked against its own pins
+MUTATIONS_FRANK3 = [
+    ("frank3_splay_takes_twist_constant", "dh[mu] = a[0] * dS[mu]", "dh[mu] = a[1] * dS[mu]"),
+    ("frank3_twist_factor_two", "(nxdT - 2.0 * fp.T * fp.c[mu])", "(nxdT - fp.T * fp.c[mu])"),
+    ("frank3_bend_stress_transposed", "ac[2] * (fp.B[b] * n[g] - fp.B[g] * n[b])",
+     "ac[2] * (fp.B[g] * n[b] - fp.B[b] * n[g])"),
+    ("frank3_chiral_constant", "*Kt = p->K22;", "*Kt = p->K11;"),
+    ("frank3_mixed_stencil_sign", "nb2(st, m, 0, g, x, y, z, a, +1, b, +1) - nb2(st, m, 0, g, x, y, z, a, +1, b, -1)",
+     "nb2(st, m, 0, g, x, y, z, a, +1, b, +1) + nb2(st, m, 0, g, x, y, z, a, +1, b, -1)"),
+    ("frank3_reference_not_minimum", "    if (p->K22 < m) m = p->K22;\n", ""),
+    ("frank3_no_div_B", "a[2] * (divB * n[mu] + BdN", "a[2] * (BdN"),
+    ("frank3_grad_T_drops_G", "dT[b] += G[b][g] * fp.c[g] + n[g] * dc[b][g];", "dT[b] += n[g] * dc[b][g];"),
+    ("frank3_bend_force_sign", "- fp.S * fp.B[mu] - cxB);", "- fp.S * fp.B[mu] + cxB);"),
+]
+
 PINS = [
     pins.test_lattice_isotropy,
     lambda: pins.test_equilibrium_moments(False),
@@ -96,12 +112,23 @@ PINS = [
     pins.test_tube_centroids_of_analytic_tubes,
 ]
 
+PINS_FRANK3 = [
+    f3.test_equal_constants_reduce_to_one_constant,
+    lambda: f3.test_single_mode_relaxation_rate(0, 0),
+    lambda: f3.test_single_mode_relaxation_rate(1, 1),
+    lambda: f3.test_single_mode_relaxation_rate(2, 2),
+    lambda: f3.test_elastic_stress_satisfies_ericksen_identity_three_constants(f3.ORDERINGS[0]),
+    lambda: f3.test_elastic_stress_satisfies_ericksen_identity_three_constants(f3.ORDERINGS[1]),
+    lambda: f3.test_molecular_field_converges_to_variational_derivative(f3.ORDERINGS[0]),
+    lambda: f3.test_molecular_field_converges_to_variational_derivative(f3.ORDERINGS[1]),
+]
 
-def _caught(lib) -> str:
+
+def _caught(lib, pin_list) -> str:
     saved = oo._lib
     oo._lib = lib
     try:
-        for pin in PINS:
+        for pin in pin_list:
             try:
                 pin()
             except Exception as e:  # an assertion or a numerical failure
@@ -111,8 +138,10 @@ def _caught(lib) -> str:
         oo._lib = saved
 
 
-@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
-def test_planted_mistake_is_caught(name, old, new, tmp_path):
+@pytest.mark.parametrize("name,old,new,pin_list", [m + (PINS,) for m in MUTATIONS] +
+                         [m + (PINS_FRANK3,) for m in MUTATIONS_FRANK3],
+                         ids=[m[0] for m in MUTATIONS + MUTATIONS_FRANK3])
+def test_planted_mistake_is_caught(name, old, new, pin_list, tmp_path):
     src = open(SRC).read()
     assert src.count(old) >= 1, f"mutation site not found: {old}"
     mutated = src.replace(old, new, 1)
@@ -122,6 +151,6 @@ def test_planted_mistake_is_caught(name, old, new, tmp_path):
     lpath = tmp_path / "libmut.so"
     subprocess.check_call(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-o",
                            str(lpath), str(cpath), "-lm"])
-    caught_by = _caught(oo.load_library(str(lpath)))
+    caught_by = _caught(oo.load_library(str(lpath)), pin_list)
     print(f"{name}: caught by {caught_by}")
     assert caught_by, f"no pin fails for the planted mistake {name!r}"
