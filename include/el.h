@@ -333,6 +333,21 @@ int el_tube_drift(const el_params* p, const el_state* s, el_drift* d, void* stre
 int el_error_norms(const el_params* p, const void* a, const double* ref, int32_t ncomp, void* work,
                    double* out, void* stream);
 
+/* el_error_norms for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same sums into out, with the partial sums in an 80 KiB array the library
+ * holds on each GPU (allocated with the code object, held until the process
+ * ends) instead of a work buffer.  Allocates nothing; the first call with a
+ * device current looks up that device's copy of the array.  Every call on one
+ * GPU shares its array: calls that overlap on one GPU (two streams, two
+ * threads) race and must be serialised by the caller.  The partial rows are
+ * written before they are read in each call, so nothing needs clearing.
+ * EL_EINVAL as for el_error_norms; EL_ENOMEM if the reduction would need more
+ * partial rows than the array holds (1024 rows of 10 doubles); EL_EDEVICE if
+ * the array's device address cannot be obtained. */
+int el_error_norms_noalloc(const el_params* p, const void* a, const double* ref, int32_t ncomp, double* out,
+                           void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched ensemble: many independent channels of uneven sizes, body forces
  * and FD/LBM step ratios advanced together.  Each step launches the LBM

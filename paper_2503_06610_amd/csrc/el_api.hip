@@ -2,6 +2,7 @@
 // validation, precision dispatch and the launch sequence of the hybrid step
 // (Sec. II D).  All device memory belongs to the caller.
 #include <algorithm>
+#include <mutex>
 
 #include "host_common.hpp"
 
@@ -328,6 +329,43 @@ int fd_stage_impl(const el_params* p, el_state* s, int stage, const T* lower, co
 
 }  // namespace
 
+// ==========================================================================
+// Library-owned partial sums for el_error_norms_noalloc: one row of ERR_NQ
+// doubles per reduction block (at most RED_MAX_BLOCKS rows, 80 KiB).  Each GPU
+// holds its own copy of the array for the life of the process.  In host code
+// the name `scratch` is only a stand-in for the symbol: the device address of
+// a GPU's copy comes from hipGetSymbolAddress with that GPU current, is cached
+// per device, and is what every kernel argument uses.
+namespace {
+constexpr size_t NOALLOC_DOUBLES = (size_t)el::RED_MAX_BLOCKS * el::ERR_NQ;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current GPU's copy of `scratch` (looked up once per
+// device, on the first call with that device current).
+int noalloc_scratch(double** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(EL_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(EL_EDEVICE, "device %d beyond the %d devices this library tracks", dev, NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(EL_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_noalloc_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_noalloc_ptr[dev];
+    return EL_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int el_version(void) { return EL_ABI_VERSION; }
@@ -575,6 +613,24 @@ int el_error_norms(const el_params* p, const void* a, const double* ref, int32_t
     if (rc != EL_OK) return rc;
     if (!a || !ref || !work || !out) return fail(EL_EINVAL, "NULL pointer");
     if (ncomp < 1 || ncomp > 3) return fail(EL_EINVAL, "ncomp = %d", ncomp);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (is_f64(p)) return error_impl<double>(p, a, ref, ncomp, work, out, st);
+    return error_impl<float>(p, a, ref, ncomp, work, out, st);
+}
+
+int el_error_norms_noalloc(const el_params* p, const void* a, const double* ref, int32_t ncomp, double* out,
+                           void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if (!a || !ref || !out) return fail(EL_EINVAL, "NULL pointer");
+    if (ncomp < 1 || ncomp > 3) return fail(EL_EINVAL, "ncomp = %d", ncomp);
+    // the partial sums need one row per reduction block
+    const size_t rows = (size_t)std::min(grid_for(geom_of(p).N), el::RED_MAX_BLOCKS);
+    if (rows * el::ERR_NQ > NOALLOC_DOUBLES)
+        return fail(EL_ENOMEM, "%zu partial rows exceed the library's %zu-double scratch", rows, NOALLOC_DOUBLES);
+    double* work = nullptr;
+    if ((rc = noalloc_scratch(&work)) != EL_OK) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (is_f64(p)) return error_impl<double>(p, a, ref, ncomp, work, out, st);
     return error_impl<float>(p, a, ref, ncomp, work, out, st);

@@ -27,7 +27,7 @@ PRECISIONS = {"f64": EL_F64, "f64_shifted": EL_F64_SHIFTED, "f32": EL_F32, "f32_
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTED = ("el_version", "el_strerror", "el_last_error", "el_buffer_bytes", "el_validate", "el_init_lattice",
             "el_init_flow", "el_step_lbm", "el_moments", "el_step_director", "el_force", "el_run",
-            "el_observables", "el_tube_drift", "el_error_norms", "el_batch_create",
+            "el_observables", "el_tube_drift", "el_error_norms", "el_error_norms_noalloc", "el_batch_create",
             "el_batch_step", "el_batch_capture",
             "el_batch_moments", "el_batch_observables", "el_batch_sync", "el_batch_get_tuning", "el_batch_destroy",
             "el_nn_input", "el_nn_conv_forward", "el_nn_conv_backward_data", "el_nn_work_bytes",
@@ -138,6 +138,7 @@ def load(path: str = LIB_PATH):
         "el_run": (C.c_int, [P, S, C.c_int64, V]),
         "el_observables": (C.c_int, [P, S, C.POINTER(el_tubes), V, V]),
         "el_error_norms": (C.c_int, [P, V, V, C.c_int32, V, V, V]),
+        "el_error_norms_noalloc": (C.c_int, [P, V, V, C.c_int32, V, V]),
         "el_tube_drift": (C.c_int, [P, S, V, V]),
         "el_halo_pack": (C.c_int, [P, S, V, V]),
         "el_stream_copy": (C.c_int, [V, V, C.c_size_t, V]),
