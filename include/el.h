@@ -38,7 +38,8 @@
  *     z = nz - 1 (halfway bounce-back, wall midway between the last fluid
  *     and the solid layer), or zf = z and nzf = nz with EL_PERIODIC_Z.
  *     Solid nodes are not stored: they hold n = z-hat, u = 0 and zero stress
- *     (infinite homeotropic anchoring and no slip, Sec. II B).
+ *     (infinite homeotropic anchoring and no slip, Sec. II B; EL_FREE_WALLS
+ *     replaces the anchoring by a zero normal gradient of n).
  *   - The storage type T of q, n, n_pred, dndt, u and F is double for
  *     EL_F64*, float for EL_F32*; arithmetic is done in T.  Global sums
  *     (observables, error norms) are always accumulated in double.
@@ -59,7 +60,7 @@
 extern "C" {
 #endif
 
-#define EL_ABI_VERSION 2
+#define EL_ABI_VERSION 3
 
 /* status codes */
 enum {
@@ -85,9 +86,16 @@ enum {
                                      of a fixed director, used to make surrogate training pairs) */
     EL_FORCE_ONE_PASS = 32,       /* F^LC by the one-pass kernel: the stress of a tile and its
                                      one-node ring kept in LDS (same result, bit for bit) */
-    EL_FORCE_TWO_PASS = 64        /* F^LC as stress to scratch, then its divergence.  With
+    EL_FORCE_TWO_PASS = 64,       /* F^LC as stress to scratch, then its divergence.  With
                                      neither flag: one pass for FP64 on large lattices; both
                                      flags: EL_EINVAL.  The ensemble calls ignore them */
+    EL_FRANK3 = 128,              /* three-constant Frank energy with K11, K22, K33 (K is
+                                     unused); F^LC always takes the two-pass kernels */
+    EL_FREE_WALLS = 256           /* no director anchoring at the walls (Sec. III A test
+                                     case): a wall node takes the director of the fluid node
+                                     next to it (zero normal gradient); u = 0 and zero stress
+                                     there as before.  Without it: infinite homeotropic
+                                     anchoring, n = z-hat at the walls (Sec. II B) */
 };
 
 typedef struct {
@@ -97,12 +105,14 @@ typedef struct {
     int32_t flags;          /* EL_PERIODIC_Z | EL_NO_COUPLING | ... */
     double tau;             /* BGK relaxation time > 1/2; nu = (tau - 1/2)/3 (Sec. II C) */
     double g[3];            /* body acceleration; the force density is rho*g (Sec. II A) */
-    double K;               /* one-constant Frank elasticity */
+    double K;               /* one-constant Frank elasticity (unused with EL_FRANK3) */
     double q0;              /* cholesteric wave number 2 pi / P */
     double W0;              /* weak bulk anchoring along z (Sec. III A) */
     double alpha[6];        /* Leslie viscosities alpha1..alpha6; alpha[3] (alpha4)
                                is informational: the LBM carries it through tau */
     double alpha4p;         /* alpha4' added to the finite-difference force (Sec. II B) */
+    double K11, K22, K33;   /* splay, twist and bend constants of the Frank energy
+                               (Sec. II A), used with EL_FRANK3 */
 } el_params;
 
 /* Caller-owned device buffers of one lattice (sizes from el_buffer_bytes). */
@@ -193,9 +203,12 @@ size_t el_buffer_bytes(const el_params* p, int32_t which);
 
 /* Checks the parameters.  EL_EINVAL: sizes (nx, ny >= 3; nz >= 4, or >= 3
  * with EL_PERIODIC_Z), tau <= 1/2, r < 1, gamma1 = alpha3 - alpha2 <= 0 with
- * coupling, unknown precision or flags, both force-kernel flags.  EL_EUNSTABLE (unless
+ * coupling, unknown precision or flags, both force-kernel flags, EL_FRANK3
+ * with a negative or non-finite K11, K22 or K33.  EL_EUNSTABLE (unless
  * EL_ALLOW_UNSTABLE): r * 12 K / gamma1 > 2 (the explicit Heun step on the
- * compact Laplacian); an odd r with coupling and tau > 1.5; or a Mach
+ * compact Laplacian; with EL_FRANK3, r * 4 (K11 + K22 + K33) / gamma1 > 2,
+ * the same bound on the largest eigenvalue of the three-constant operator,
+ * reached at the lattice's corner wave number); an odd r with coupling and tau > 1.5; or a Mach
  * estimate |g| H^2/(8 nu) sqrt(3) > 0.1.  The odd-r bound is empirical: a
  * force held over an odd number of LBM steps meets the lattice's
  * sign-alternating (period-2) velocity modes with the opposite sign at each
@@ -238,7 +251,18 @@ int el_moments(const el_params* p, el_state* s, void* stream);
  * on the director equation (Sec. II A) with the current u, the predictor
  * normalised unless EL_NO_RENORM_PREDICTOR, the corrector always normalised
  * to |n| = 1; then F^LC = d_b sigma_ab of the Leslie + elastic stress at the
- * new director (skipped with EL_NO_COUPLING). */
+ * new director (skipped with EL_NO_COUPLING).
+ * Molecular field and elastic stress: with one constant,
+ *   f = K/2 (d_b n_g)^2 + K q0 n.curl n - W0/2 n_z^2,
+ *   h = K lap n - 2 K q0 curl n + W0 n_z z-hat (compact Laplacian);
+ * with EL_FRANK3 the Frank-Oseen energy of Sec. II A, K11/2 (div n)^2 +
+ * K22/2 (n.curl n + q0)^2 + K33/2 |n x curl n|^2, written for |n| = 1 as the
+ * one-constant density at Km = min(K11, K22, K33) (chiral term K22 q0) plus
+ * (K11-Km)/2 (div n)^2 + (K22-Km)/2 (n.curl n)^2 + (K33-Km)/2 |n x curl n|^2;
+ * the corrections to h use central first differences and compact and
+ * four-point mixed second differences (the 12 edge neighbours of a node).
+ * Equal constants give the one-constant result bit for bit.  h is not
+ * projected perpendicular to n in either form. */
 int el_step_director(const el_params* p, el_state* s, void* stream);
 
 /* Recompute F^LC from the current n and u only. */

@@ -37,6 +37,10 @@
  *       corrector always is.
  *   R6  N in the Leslie stress is (h - gamma2 D n)/gamma1 at the new director.
  *   R7  solid nodes: n = z-hat, u = 0, sigma = 0; no director update there.
+ *   R7' without anchoring at the walls (free_walls): a wall node's director is
+ *       that of the fluid node next to it across the wall (zero normal
+ *       gradient, the natural condition of a free surface), u = 0 and
+ *       sigma = 0 as in R7.
  *   R8  collide, then stream; moments after streaming; reported u includes
  *       F/(2 rho).
  *   R9  total force density F = rho g + F^LC.
@@ -312,12 +316,19 @@ static double solid_value(int field_kind, int comp)
     return 0.0;
 }
 
+/* The fluid layer next to the wall layer z (R7'). */
+static int mirror_layer(const or_params* p, int z) { return z == 0 ? 1 : p->nz - 2; }
+
 /* Value of component c of a field (ncomp components, full-grid storage) at
  * the neighbour of (x,y,z) along axis b with step s. */
 static double nb(const or_state* st, const double* f, int field_kind, int c, int x, int y, int z, int b, int s)
 {
     int xo, yo, zo;
-    if (neighbour(&st->p, x, y, z, b, s, &xo, &yo, &zo)) return solid_value(field_kind, c);
+    if (neighbour(&st->p, x, y, z, b, s, &xo, &yo, &zo)) {
+        if (field_kind == 0 && st->p.free_walls)
+            return f[(int64_t)c * st->N + idx(&st->p, xo, yo, mirror_layer(&st->p, zo))];
+        return solid_value(field_kind, c);
+    }
     return f[(int64_t)c * st->N + idx(&st->p, xo, yo, zo)];
 }
 
@@ -342,7 +353,11 @@ static double nb2(const or_state* st, const double* f, int field_kind, int c, in
     co[0] = wrap(co[0], p->nx);
     co[1] = wrap(co[1], p->ny);
     if (p->periodic_z) co[2] = wrap(co[2], p->nz);
-    if (is_solid(p, co[2])) return solid_value(field_kind, c);
+    if (is_solid(p, co[2])) {
+        if (field_kind == 0 && p->free_walls)
+            return f[(int64_t)c * st->N + idx(p, co[0], co[1], mirror_layer(p, co[2]))];
+        return solid_value(field_kind, c);
+    }
     return f[(int64_t)c * st->N + idx(p, co[0], co[1], co[2])];
 }
 

@@ -48,7 +48,7 @@ typedef struct {
     double alpha[6];        /* Leslie alpha1..alpha6 (alpha[3] is informational) */
     double alpha4p;         /* alpha4' carried by the finite-difference force */
     int32_t frank3;         /* 1: three-constant Frank energy with K11, K22, K33 (K unused) */
-    int32_t reserved;
+    int32_t free_walls;     /* 1: no director anchoring at the walls (R7'), 0: n = z-hat there */
     double K11, K22, K33;   /* splay, twist, bend constants (used when frank3) */
 } or_params;
 

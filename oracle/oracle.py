@@ -35,7 +35,7 @@ class _Params(C.Structure):
                 ("tau", C.c_double), ("g", C.c_double * 3),
                 ("K", C.c_double), ("q0", C.c_double), ("W0", C.c_double),
                 ("alpha", C.c_double * 6), ("alpha4p", C.c_double),
-                ("frank3", C.c_int32), ("reserved", C.c_int32),
+                ("frank3", C.c_int32), ("free_walls", C.c_int32),
                 ("K11", C.c_double), ("K22", C.c_double), ("K33", C.c_double)]
 
 
@@ -137,6 +137,7 @@ class OracleParams:
     renorm_predictor: bool = True
     coupling: bool = True
     frank3: bool = False
+    free_walls: bool = False
     K11: float = 0.0
     K22: float = 0.0
     K33: float = 0.0
@@ -159,6 +160,7 @@ class OracleParams:
         p.alpha = (C.c_double * 6)(*self.alpha)
         p.alpha4p = self.alpha4p
         p.frank3 = int(self.frank3)
+        p.free_walls = int(self.free_walls)
         p.K11, p.K22, p.K33 = self.K11, self.K22, self.K33
         return p
 

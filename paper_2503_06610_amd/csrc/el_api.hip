@@ -29,7 +29,7 @@ int basic_checks(const el_params* p)
     if (p->precision < EL_F64 || p->precision > EL_F32_SHIFTED)
         return fail(EL_EINVAL, "unknown precision %d", p->precision);
     if (p->flags & ~(EL_PERIODIC_Z | EL_NO_COUPLING | EL_NO_RENORM_PREDICTOR | EL_ALLOW_UNSTABLE | EL_FREEZE_DIRECTOR |
-                     EL_FORCE_ONE_PASS | EL_FORCE_TWO_PASS))
+                     EL_FORCE_ONE_PASS | EL_FORCE_TWO_PASS | EL_FRANK3 | EL_FREE_WALLS))
         return fail(EL_EINVAL, "unknown flags 0x%x", p->flags);
     if ((p->flags & EL_FORCE_ONE_PASS) && (p->flags & EL_FORCE_TWO_PASS))
         return fail(EL_EINVAL, "EL_FORCE_ONE_PASS and EL_FORCE_TWO_PASS both set");
@@ -44,6 +44,11 @@ int basic_checks(const el_params* p)
     for (double v : {p->tau, p->g[0], p->g[1], p->g[2], p->K, p->q0, p->W0, p->alpha4p, p->alpha[0], p->alpha[1],
                      p->alpha[2], p->alpha[3], p->alpha[4], p->alpha[5]})
         if (!std::isfinite(v)) return fail(EL_EINVAL, "non-finite parameter");
+    if (frank3(p))
+        for (double v : {p->K11, p->K22, p->K33})
+            if (!std::isfinite(v) || v < 0.0)
+                return fail(EL_EINVAL, "Frank constants K11 = %g, K22 = %g, K33 = %g must be finite and >= 0", p->K11,
+                            p->K22, p->K33);
     return EL_OK;
 }
 
@@ -51,9 +56,12 @@ int stability_checks(const el_params* p)
 {
     if (p->flags & EL_ALLOW_UNSTABLE) return EL_OK;
     const double gamma1 = p->alpha[2] - p->alpha[1];
-    const double heun = p->fd_ratio * 12.0 * std::fabs(p->K) / gamma1;
+    // largest eigenvalue of the linearised elastic operator: 12 K with one
+    // constant, 4 (K11 + K22 + K33) with three (both at the corner wave number)
+    const double lam = frank3(p) ? 4.0 * (p->K11 + p->K22 + p->K33) : 12.0 * std::fabs(p->K);
+    const double heun = p->fd_ratio * lam / gamma1;
     if (heun > 2.0)
-        return fail(EL_EUNSTABLE, "explicit director step unstable: r*12K/gamma1 = %g > 2", heun);
+        return fail(EL_EUNSTABLE, "explicit director step unstable: r*lambda_max/gamma1 = %g > 2", heun);
     // A force held over an odd number of LBM steps sees the lattice's
     // sign-alternating (period-2) velocity modes with the opposite sign at
     // every FD step and pumps them; over an even number the kicks cancel.
@@ -153,7 +161,7 @@ int launch_force(const el_params* p, el_state* s, hipStream_t st)
     const int tiles_x = (a.g.nx + el::FORCE_TX - 1) / el::FORCE_TX;
     const int tiles_y = (a.g.ny + el::FORCE_TY - 1) / el::FORCE_TY;
     const int chunks = (a.g.nzf + el::FORCE_ZC - 1) / el::FORCE_ZC;
-    if (one_pass_force(p, tiles_x * tiles_y * chunks)) {
+    if (!frank3(p) && one_pass_force(p, tiles_x * tiles_y * chunks)) {
         hipLaunchKernelGGL((el::k_fd_force<T, el::FORCE_TY>), dim3(tiles_x * tiles_y * chunks),
                            dim3(el::FORCE_TX * el::FORCE_TY), 0, st, static_cast<const T*>(s->n),
                            static_cast<const T*>(s->u), static_cast<T*>(s->F), a, el::FORCE_ZC, tiles_x, tiles_y);
@@ -161,8 +169,12 @@ int launch_force(const el_params* p, el_state* s, hipStream_t st)
     }
     T* sig = sigma_of<T>(s);
     const int grid = grid_for(a.g.N);
-    hipLaunchKernelGGL((el::k_fd_stress<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
-                       static_cast<const T*>(s->u), sig, a, fd_strip(a.g));
+    if (frank3(p))
+        hipLaunchKernelGGL((el::k_fd_stress<T, true>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
+                           static_cast<const T*>(s->u), sig, a, fd_strip(a.g));
+    else
+        hipLaunchKernelGGL((el::k_fd_stress<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
+                           static_cast<const T*>(s->u), sig, a, fd_strip(a.g));
     hipLaunchKernelGGL((el::k_fd_divergence<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(sig),
                        static_cast<T*>(s->F), a, fd_strip(a.g));
     return check_launch("force kernels");
@@ -174,12 +186,21 @@ int launch_director(const el_params* p, el_state* s, hipStream_t st)
     const el::FdArgs<T> a = fd_args<T>(p);
     if (p->flags & EL_FREEZE_DIRECTOR) return launch_force<T>(p, s, st);
     const int grid = grid_for(a.g.N);
-    hipLaunchKernelGGL((el::k_fd_predictor<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
-                       static_cast<const T*>(s->u), static_cast<T*>(s->n_pred), static_cast<T*>(s->dndt), a,
-                       fd_strip(a.g));
-    hipLaunchKernelGGL((el::k_fd_corrector<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<T*>(s->n),
-                       static_cast<const T*>(s->n_pred), static_cast<const T*>(s->u),
-                       static_cast<const T*>(s->dndt), a, fd_strip(a.g));
+    if (frank3(p)) {
+        hipLaunchKernelGGL((el::k_fd_predictor<T, true>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
+                           static_cast<const T*>(s->u), static_cast<T*>(s->n_pred), static_cast<T*>(s->dndt), a,
+                           fd_strip(a.g));
+        hipLaunchKernelGGL((el::k_fd_corrector<T, true>), dim3(grid), dim3(BLOCK), 0, st, static_cast<T*>(s->n),
+                           static_cast<const T*>(s->n_pred), static_cast<const T*>(s->u),
+                           static_cast<const T*>(s->dndt), a, fd_strip(a.g));
+    } else {
+        hipLaunchKernelGGL((el::k_fd_predictor<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
+                           static_cast<const T*>(s->u), static_cast<T*>(s->n_pred), static_cast<T*>(s->dndt), a,
+                           fd_strip(a.g));
+        hipLaunchKernelGGL((el::k_fd_corrector<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<T*>(s->n),
+                           static_cast<const T*>(s->n_pred), static_cast<const T*>(s->u),
+                           static_cast<const T*>(s->dndt), a, fd_strip(a.g));
+    }
     int rc = check_launch("director kernels");
     if (rc != EL_OK) return rc;
     return launch_force<T>(p, s, st);
@@ -552,6 +573,7 @@ int el_fd_halo_pack(const el_params* p, const el_state* s, int32_t stage, void* 
     if ((rc = state_checks(p, s)) != EL_OK) return rc;
     if (stage < 0 || stage > 3) return fail(EL_EINVAL, "FD stage %d (0..3)", stage);
     if (!out) return fail(EL_EINVAL, "halo buffer is NULL");
+    if (frank3(p)) return fail(EL_EINVAL, "the y-slab FD stages do not support EL_FRANK3");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (is_f64(p)) return fd_face_pack_impl<double>(p, s, stage, static_cast<double*>(out), st);
     return fd_face_pack_impl<float>(p, s, stage, static_cast<float*>(out), st);
@@ -564,6 +586,7 @@ int el_fd_stage(const el_params* p, el_state* s, int32_t stage, const void* lowe
     if ((rc = state_checks(p, s)) != EL_OK) return rc;
     if (stage < 0 || stage > 3) return fail(EL_EINVAL, "FD stage %d (0..3)", stage);
     if (!lower || !upper) return fail(EL_EINVAL, "halo buffer is NULL");
+    if (frank3(p)) return fail(EL_EINVAL, "the y-slab FD stages do not support EL_FRANK3");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (is_f64(p))
         return fd_stage_impl<double>(p, s, stage, static_cast<const double*>(lower), static_cast<const double*>(upper),

@@ -38,6 +38,8 @@ struct Geom {
     int nx, ny, nzf;   // fluid nodes per axis
     int periodic_z;    // 1: z wraps, 0: solid walls below zf = 0 and above zf = nzf-1
     int N;             // nx*ny*nzf
+    int free_walls;    // 1: the director is not anchored at the walls (a wall node takes the
+                       // director of the fluid node next to it), 0: n = z-hat at the walls
 };
 
 // Neighbour indices of node (x, y, zf) along the three axes; a z neighbour
@@ -46,6 +48,7 @@ struct Nbr {
     int c;                   // own index
     int xm, xp, ym, yp, zm, zp;  // linear indices of the six face neighbours (valid when not wall)
     bool wall_zm, wall_zp;
+    bool free_walls;             // Geom::free_walls
 };
 
 __device__ inline Nbr make_nbr(const Geom& g, int x, int y, int z)
@@ -60,6 +63,7 @@ __device__ inline Nbr make_nbr(const Geom& g, int x, int y, int z)
     int zm = z - 1, zp = z + 1;
     n.wall_zm = false;
     n.wall_zp = false;
+    n.free_walls = g.free_walls != 0;
     if (g.periodic_z) {
         if (zm < 0) zm = g.nzf - 1;
         if (zp == g.nzf) zp = 0;

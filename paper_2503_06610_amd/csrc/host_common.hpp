@@ -39,6 +39,7 @@ inline bool is_f64(const el_params* p) { return p->precision == EL_F64 || p->pre
 inline bool is_shifted(const el_params* p) { return p->precision == EL_F64_SHIFTED || p->precision == EL_F32_SHIFTED; }
 inline bool periodic_z(const el_params* p) { return (p->flags & EL_PERIODIC_Z) != 0; }
 inline bool coupling(const el_params* p) { return (p->flags & EL_NO_COUPLING) == 0; }
+inline bool frank3(const el_params* p) { return (p->flags & EL_FRANK3) != 0; }
 inline int nzf_of(const el_params* p) { return periodic_z(p) ? p->nz : p->nz - 2; }
 
 inline el::Geom geom_of(const el_params* p)
@@ -49,6 +50,7 @@ inline el::Geom geom_of(const el_params* p)
     g.nzf = nzf_of(p);
     g.periodic_z = periodic_z(p) ? 1 : 0;
     g.N = p->nx * p->ny * g.nzf;
+    g.free_walls = (p->flags & EL_FREE_WALLS) ? 1 : 0;
     return g;
 }
 
@@ -119,9 +121,21 @@ el::FdArgs<T> fd_args(const el_params* p)
     const double g1 = p->alpha[2] - p->alpha[1];
     const double g2 = p->alpha[2] + p->alpha[1];
     a.dt = T(p->fd_ratio);
-    a.K = T(p->K);
-    a.Kq0x2 = T(2.0 * p->K * p->q0);
-    a.Kq0 = T(p->K * p->q0);
+    if (frank3(p)) {
+        // three constants: one-constant part at Km, chiral term with K22
+        const double Km = std::fmin(p->K11, std::fmin(p->K22, p->K33));
+        a.K = T(Km);
+        a.Kq0x2 = T(2.0 * p->K22 * p->q0);
+        a.Kq0 = T(p->K22 * p->q0);
+        a.ks = T(p->K11 - Km);
+        a.kt = T(p->K22 - Km);
+        a.kb = T(p->K33 - Km);
+    } else {
+        a.K = T(p->K);
+        a.Kq0x2 = T(2.0 * p->K * p->q0);
+        a.Kq0 = T(p->K * p->q0);
+        a.ks = a.kt = a.kb = T(0);
+    }
     a.W0 = T(p->W0);
     a.inv_g1 = T(1.0 / g1);
     a.g2_over_g1 = T(g2 / g1);

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libel.so")
 EL_OK, EL_EINVAL, EL_EUNSTABLE, EL_EDEVICE, EL_ENAN, EL_ENOMEM = 0, -1, -2, -3, -4, -5
 EL_F64, EL_F64_SHIFTED, EL_F32, EL_F32_SHIFTED = 0, 1, 2, 3
 EL_PERIODIC_Z, EL_NO_COUPLING, EL_NO_RENORM_PREDICTOR, EL_ALLOW_UNSTABLE, EL_FREEZE_DIRECTOR = 1, 2, 4, 8, 16
+EL_FRANK3, EL_FREE_WALLS = 128, 256
 EL_FORCE_ONE_PASS, EL_FORCE_TWO_PASS = 32, 64
 EL_BUF_Q, EL_BUF_VEC3, EL_BUF_SCRATCH, EL_BUF_HALO, EL_BUF_FD_HALO = 0, 1, 2, 3, 4
 
@@ -45,7 +46,8 @@ class el_params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("precision", C.c_int32), ("fd_ratio", C.c_int32), ("flags", C.c_int32),
                 ("tau", C.c_double), ("g", C.c_double * 3), ("K", C.c_double), ("q0", C.c_double),
-                ("W0", C.c_double), ("alpha", C.c_double * 6), ("alpha4p", C.c_double)]
+                ("W0", C.c_double), ("alpha", C.c_double * 6), ("alpha4p", C.c_double),
+                ("K11", C.c_double), ("K22", C.c_double), ("K33", C.c_double)]
 
 
 class el_state(C.Structure):
@@ -179,8 +181,6 @@ def _check(status: int, what: str):
 
 def make_params(prob, precision: str = "f32_shifted") -> el_params:
     """el_params from a seeded Problem (paper_2503_06610_amd.inputs)."""
-    if getattr(prob, "frank3", False):
-        raise ElError(EL_EINVAL, "make_params", "the three-constant Frank energy is not supported by libel.so yet")
     p = el_params()
     p.nx, p.ny, p.nz = prob.nx, prob.ny, prob.nz
     p.precision = PRECISIONS[precision]
@@ -192,12 +192,17 @@ def make_params(prob, precision: str = "f32_shifted") -> el_params:
         flags |= EL_NO_COUPLING
     if not prob.renorm_predictor:
         flags |= EL_NO_RENORM_PREDICTOR
+    if prob.frank3:
+        flags |= EL_FRANK3
+    if prob.free_walls:
+        flags |= EL_FREE_WALLS
     p.flags = flags
     p.tau = float(prob.tau)
     p.g = (C.c_double * 3)(*prob.g)
     p.K, p.q0, p.W0 = float(prob.K), float(prob.q0), float(prob.W0)
     p.alpha = (C.c_double * 6)(*prob.alpha)
     p.alpha4p = float(prob.alpha4p)
+    p.K11, p.K22, p.K33 = float(prob.K11), float(prob.K22), float(prob.K33)
     return p
 
 

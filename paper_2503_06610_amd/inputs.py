@@ -60,6 +60,16 @@ def set_a() -> Material:
     return Material(alpha=tuple(a * s for a in TABLE1_ALPHA), tau=0.8, alpha4p=0.0)
 
 
+# Frank constants of the paper's material table (lattice units): splay, twist, bend.
+TABLE1_FRANK = (1.67e-7, 7.88e-8, 2.62e-7)
+
+
+def frank_table1(mean: float) -> tuple:
+    """(K11, K22, K33) in the material table's ratios, scaled to the given mean."""
+    s = 3.0 * mean / sum(TABLE1_FRANK)
+    return tuple(k * s for k in TABLE1_FRANK)
+
+
 def set_b() -> Material:
     """Table-1 viscosities; tau chosen so that 2 rho c_s^2 (tau - 1/2) = alpha4."""
     return Material(alpha=TABLE1_ALPHA, tau=0.5 + 1.5 * TABLE1_ALPHA[3], alpha4p=0.0)
@@ -85,6 +95,7 @@ class Problem:
     renorm_predictor: bool = True
     coupling: bool = True
     frank3: bool = False   # three-constant Frank energy with K11, K22, K33 (K unused)
+    free_walls: bool = False  # no director anchoring at the walls (zero normal gradient)
     K11: float = 0.0
     K22: float = 0.0
     K33: float = 0.0
@@ -200,6 +211,15 @@ def workload_c3(r: int = 10) -> tuple:
     prob = channel(256, 256, 48, set_b(), g=(5e-6, 0.0, 0.0), K=5e-3, q0=2.0 * math.pi / 32.0,
                    fd_ratio=r)
     return prob, director_tubes(prob, [(128.0, 128.0)], 16.0), 100000
+
+
+def workload_c3_frank3(r: int = 10) -> tuple:
+    """The tube channel of workload_c3 with the three-constant Frank energy:
+    K11, K22, K33 in the material table's ratios with mean 5e-3 (the
+    one-constant K of workload_c3)."""
+    prob, n0, T = workload_c3(r)
+    K11, K22, K33 = frank_table1(5e-3)
+    return prob.with_(frank3=True, K11=K11, K22=K22, K33=K33, K=0.0), n0, T
 
 
 def workload_c4(seed: int = 4, nchan: int = 64, material: str = "set_a", K: float = 1e-3,

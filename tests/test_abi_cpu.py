@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared_functions():
         assert name in exported, name
         assert hasattr(lib, name)
-    assert lib.el_version() == 2
+    assert lib.el_version() == 3
 
 
 def test_struct_sizes_match_header():
@@ -73,7 +73,7 @@ def test_validate_accepts_workloads():
     ("nz", 3, el.EL_EINVAL),
     ("fd_ratio", 0, el.EL_EINVAL),
     ("precision", 7, el.EL_EINVAL),
-    ("flags", 128, el.EL_EINVAL),
+    ("flags", 512, el.EL_EINVAL),
     ("K", 0.5, el.EL_EUNSTABLE),
     ("fd_ratio", 2, el.EL_EUNSTABLE),  # C1 with K = 0.01: r*12K/gamma1 = 2.6
     ("tau", 1.9, el.EL_EUNSTABLE),     # odd r (here 1) with tau > 1.5
