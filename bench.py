@@ -218,7 +218,8 @@ def bench_batch(args):
             "ms_per_step": round(wall / args.steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "64 channels, Nx,Ny~U{48..160}, Nz~U{16..48}, 1-4 tubes, g_x log-uniform "
-                                   "[1e-7,1e-5], r in {2,5,10}, Leslie set A, K=1e-3, seed 4", "fluid_nodes": nf,
+                                   "[1e-7,1e-5], r in {1,5,10}, Leslie set B (tau=1.8977, alpha4'=0.4659), "
+                                   "K=5e-3, seed 4", "fluid_nodes": nf,
                        "tuning": b.tuning(), "autotune_s": round(tune_s, 2)},
             "step_roofline": {"bytes_per_update": round(step_bytes, 2),
                               "frac": round(mlups * 1e6 * step_bytes / (HBM_PEAK_GBS * 1e9), 4)},
@@ -292,11 +293,12 @@ def main():
         return
     if args.workload == "c2":
         prob, n0, _ = inputs.workload_c2(gx=args.gx, r=args.fd_ratio)
-        workload = ("precision-study channel 128x128x64 (walls at z=0,63), tau=0.8, Leslie set A, "
-                    f"K=5e-4, g_x={args.gx:g}, r={prob.fd_ratio}, FP32-shifted, seeded tilt")
+        workload = ("precision-study channel 128x128x64 (walls at z=0,63), tau=0.8, Leslie set A "
+                    f"(alpha4'=0.1), K=5e-4, g_x={args.gx:g}, r={prob.fd_ratio}, FP32-shifted, seeded tilt")
     else:
         prob, n0, _ = inputs.workload_c3(r=args.fd_ratio)
-        workload = ("skyrmion-tube channel 256x256x48 (walls at z=0,47), Leslie set B (tau=1.8977), K=5e-3, "
+        workload = ("skyrmion-tube channel 256x256x48 (walls at z=0,47), Leslie set B (tau=1.8977, "
+                    "alpha4'=0.4659), K=5e-3, "
                     f"q0=2pi/32, tube R=16, g_x=5e-6, r={prob.fd_ratio}, FP32-shifted")
     nf = prob.fluid_nodes
     nall = prob.nx * prob.ny * prob.nz

@@ -208,17 +208,19 @@ size_t el_buffer_bytes(const el_params* p, int32_t which);
  * EL_ALLOW_UNSTABLE): r * 12 K / gamma1 > 2 (the explicit Heun step on the
  * compact Laplacian; with EL_FRANK3, r * 4 (K11 + K22 + K33) / gamma1 > 2,
  * the same bound on the largest eigenvalue of the three-constant operator,
- * reached at the lattice's corner wave number); an odd r with coupling and tau > 1.5; or a Mach
- * estimate |g| H^2/(8 nu) sqrt(3) > 0.1.  The odd-r bound is empirical: a
- * force held over an odd number of LBM steps meets the lattice's
- * sign-alternating (period-2) velocity modes with the opposite sign at each
- * FD step and pumps them (over an even number the kicks cancel).  With the
- * Table-1 viscosities at tau = 1.8977 the FP64 CPU implementation grows
- * without bound for r = 1, 3 and 5 within a few thousand steps and stays
- * bounded for r = 2, 4 and 10.  Passing does not guarantee long runs: at
- * tau <= 1.5 an odd r grows far more slowly but can still diverge (r = 1 at
- * tau = 0.8 within a few thousand steps on strongly distorted directors);
- * even r never diverged.  Watch el_obs.nonfinite and max_u. */
+ * reached at the lattice's corner wave number); an odd r with coupling while
+ * the explicit viscous stress of F^LC can be anti-dissipative,
+ *   alpha4' + min(0, alpha1 + c, c/2) < 0,  c = alpha5 + alpha6 - gamma2^2/gamma1
+ * (the lower bound of its dissipation per |D|^2 over unit n and symmetric D);
+ * or a Mach estimate |g| H^2/(8 nu) sqrt(3) > 0.1.  The odd-r bound is found
+ * with the FP64 CPU implementation: a force held over an odd number of LBM
+ * steps meets the lattice's sign-alternating (period-2) velocity modes with
+ * the opposite sign at each FD step; an anti-dissipative force then pumps
+ * them without bound (Table-1 viscosity ratios: alpha4' below the bound grows
+ * within a few thousand steps, above it decays), while over an even number of
+ * steps the kicks cancel.  The paper's split of alpha4 between the LBM and
+ * the force (alpha4' = rho c_s^2 (tau - 1/2)) passes it.  Passing does not
+ * guarantee long runs: watch el_obs.nonfinite and max_u. */
 int el_validate(const el_params* p);
 
 /* Initialisation (Sec. II D, first step): q = rest state (0 when shifted,

@@ -62,17 +62,26 @@ int stability_checks(const el_params* p)
     const double heun = p->fd_ratio * lam / gamma1;
     if (heun > 2.0)
         return fail(EL_EUNSTABLE, "explicit director step unstable: r*lambda_max/gamma1 = %g > 2", heun);
-    // A force held over an odd number of LBM steps sees the lattice's
+    // A force held over an odd number of LBM steps meets the lattice's
     // sign-alternating (period-2) velocity modes with the opposite sign at
-    // every FD step and pumps them; over an even number the kicks cancel.
-    // With the Table-1 viscosities at tau = 1.8977 every odd r tried (1, 3, 5)
-    // grows without bound within a few thousand steps in the FP64 oracle, every
-    // even r (2, 4, 10) stays bounded.  At tau <= 1.5 the growth is far slower
-    // (r = 1 can still grow over thousands of steps); that regime is accepted.
-    if ((p->fd_ratio % 2) == 1 && coupling(p) && p->tau > 1.5)
-        return fail(EL_EUNSTABLE,
-                    "odd r = %d with tau = %g > 1.5: the explicit Leslie force pumps the period-2 velocity modes",
-                    p->fd_ratio, p->tau);
+    // every FD step; over an even number the kicks cancel.  The force's
+    // viscous part pumps those modes when it is anti-dissipative for some
+    // strain rate: with c = alpha5 + alpha6 - gamma2^2/gamma1 its dissipation
+    // per |D|^2 is bounded below by alpha4' + min(0, alpha1 + c, c/2).  Found
+    // with the FP64 oracle: odd r grows without bound below that bound and
+    // decays above it (Table-1 ratios at tau = 0.8: alpha4' = 0.05 grows, 0.08
+    // decays, against 0.071; at tau = 1.8977 alpha4' = 0 grows for r = 1, 3, 5
+    // and alpha4' = 0.4659 decays); even r stays bounded either way.
+    if ((p->fd_ratio % 2) == 1 && coupling(p)) {
+        const double g2 = p->alpha[2] + p->alpha[1];
+        const double c = p->alpha[4] + p->alpha[5] - g2 * g2 / gamma1;
+        const double dmin = p->alpha4p + std::fmin(0.0, std::fmin(p->alpha[0] + c, 0.5 * c));
+        if (dmin < 0.0)
+            return fail(EL_EUNSTABLE,
+                        "odd r = %d with an anti-dissipative explicit viscous stress (alpha4' + min(0, alpha1 + c, "
+                        "c/2) = %g < 0): the held force pumps the period-2 velocity modes",
+                        p->fd_ratio, dmin);
+    }
     if (!periodic_z(p)) {
         const double nu = (p->tau - 0.5) / 3.0;
         const double H = p->nz - 2;

@@ -136,8 +136,14 @@ int wgrad_blocks(const VolGeom& g) { return (int)((g.n_all + NN_CHUNK - 1) / NN_
 
 int pitch_of(int cin) { return ((27 * cin + 15) / 16) * 16; }
 
-// g_x / (2 nu V0): the Poiseuille velocity is this times (z - 1/2)(nz - 3/2 - z) V0.
-float poiseuille_coeff(const el_params* p, float V0) { return (float)(p->g[0] / (2.0 * (p->tau - 0.5) / 3.0) / V0); }
+// g_x / (2 nu V0): the Poiseuille velocity is this times (z - 1/2)(nz - 3/2 - z) V0,
+// with nu = (tau - 1/2)/3 + alpha4'/2 (rho = 1): the LBM viscosity plus the
+// isotropic viscous term alpha4' D that the coupling force carries.
+float poiseuille_coeff(const el_params* p, float V0)
+{
+    const double nu = (p->tau - 0.5) / 3.0 + 0.5 * p->alpha4p;
+    return (float)(p->g[0] / (2.0 * nu) / V0);
+}
 
 }  // namespace
 

@@ -183,7 +183,7 @@ def poiseuille_velocity(lat):
     """u_P x-hat of the lattice (the surrogate's analytic input) as a device tensor."""
     import torch
     p = lat.prob
-    nu = (p.tau - 0.5) / 3.0
+    nu = (p.tau - 0.5) / 3.0 + 0.5 * p.alpha4p  # LBM viscosity + the force's isotropic alpha4' term
     z = torch.arange(1, p.nz - 1, dtype=torch.float64)
     up = p.g[0] / (2 * nu) * (z - 0.5) * (p.nz - 1.5 - z)
     u = torch.zeros(p.shape(3), dtype=torch.float64)

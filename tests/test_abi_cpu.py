@@ -76,7 +76,7 @@ def test_validate_accepts_workloads():
     ("flags", 512, el.EL_EINVAL),
     ("K", 0.5, el.EL_EUNSTABLE),
     ("fd_ratio", 2, el.EL_EUNSTABLE),  # C1 with K = 0.01: r*12K/gamma1 = 2.6
-    ("tau", 1.9, el.EL_EUNSTABLE),     # odd r (here 1) with tau > 1.5
+    ("alpha4p", 0.0, el.EL_EUNSTABLE),  # odd r (here 1) with an anti-dissipative explicit stress
 ])
 def test_validate_rejects(field, value, code):
     prob = inputs.workload_c1()[0]
@@ -86,21 +86,31 @@ def test_validate_rejects(field, value, code):
     assert el.load().el_last_error()
 
 
-@pytest.mark.parametrize("r,code", [(1, el.EL_EUNSTABLE), (2, el.EL_OK), (3, el.EL_EUNSTABLE), (4, el.EL_OK),
-                                    (5, el.EL_EUNSTABLE), (10, el.EL_OK)])
-def test_validate_odd_r_at_large_tau(r, code):
-    """Table-1 viscosities at tau = 1.8977: an odd r with coupling is rejected
-    (the period-2 velocity modes grow, see test_stability_cpu.py); the same
-    lattice without coupling, or with EL_ALLOW_UNSTABLE, is accepted."""
-    prob = inputs.channel(32, 32, 16, inputs.set_b(), g=(1e-6, 0.0, 0.0), K=1e-3, fd_ratio=r)
-    assert el.validate(el.make_params(prob, "f32_shifted")) == code
-    assert el.validate(el.make_params(prob.with_(coupling=False), "f32_shifted")) == el.EL_OK
-    p = el.make_params(prob, "f32_shifted")
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 10])
+@pytest.mark.parametrize("material", ["set_a", "set_b"])
+def test_validate_odd_r_needs_a_dissipative_explicit_stress(material, r):
+    """The presets split alpha4 as the paper does (alpha4' = rho c_s^2 (tau - 1/2)),
+    which keeps the explicit viscous stress dissipative: every r is accepted.
+    With alpha4' = 0 the Table-1 ratios make it anti-dissipative and every odd r
+    is rejected (the period-2 velocity modes grow, test_stability_cpu.py); the
+    same lattice without coupling, or with EL_ALLOW_UNSTABLE, is accepted."""
+    mat = getattr(inputs, material)()
+    prob = inputs.channel(32, 32, 16, mat, g=(1e-6, 0.0, 0.0), K=1e-3, fd_ratio=r)
+    assert el.validate(el.make_params(prob, "f32_shifted")) == el.EL_OK, el.load().el_last_error()
+    bare = prob.with_(alpha4p=0.0)
+    assert el.validate(el.make_params(bare, "f32_shifted")) == (el.EL_EUNSTABLE if r % 2 else el.EL_OK)
+    assert el.validate(el.make_params(bare.with_(coupling=False), "f32_shifted")) == el.EL_OK
+    p = el.make_params(bare, "f32_shifted")
     p.flags |= el.EL_ALLOW_UNSTABLE
     assert el.validate(p) == el.EL_OK
-    # tau <= 1.5 (Leslie set A) stays accepted at every r
-    prob_a = inputs.channel(32, 32, 16, inputs.set_a(), g=(1e-6, 0.0, 0.0), K=1e-3, fd_ratio=r)
-    assert el.validate(el.make_params(prob_a, "f32_shifted")) == el.EL_OK
+
+
+def test_validate_odd_r_bound_at_its_threshold():
+    """Table-1 ratios at tau = 0.8: the bound alpha4' + alpha1 + c = 0 sits at
+    alpha4' = 0.0709; the oracle grows at 0.05 and decays at 0.08."""
+    prob = inputs.channel(16, 16, 12, inputs.set_a(), g=(1e-5, 0.0, 0.0), K=1e-3, fd_ratio=1)
+    assert el.validate(el.make_params(prob.with_(alpha4p=0.05), "f64")) == el.EL_EUNSTABLE
+    assert el.validate(el.make_params(prob.with_(alpha4p=0.08), "f64")) == el.EL_OK
 
 
 def test_validate_rejects_nonpositive_gamma1_and_nan():

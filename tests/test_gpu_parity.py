@@ -447,7 +447,8 @@ def _random_case(seed):
     gamma1 = alpha[2] - alpha[1]
     K = float(rs.uniform(0.1, 1.0)) * 2 * gamma1 / (12 * r) * 0.9
     q0 = float(rs.choice([0.0, 2 * math.pi / rs.integers(8, 33)]))
-    prob = inputs.Problem(nx=nx, ny=ny, nz=nz, tau=tau, alpha=alpha, alpha4p=float(rs.uniform(0.0, 0.03)),
+    # alpha4' at least 0.3304 scale keeps the explicit viscous stress dissipative (el_validate's odd-r bound)
+    prob = inputs.Problem(nx=nx, ny=ny, nz=nz, tau=tau, alpha=alpha, alpha4p=float(rs.uniform(0.0, 0.03)) + 0.3304 * scale,
                           g=tuple(float(v) for v in rs.uniform(-3e-6, 3e-6, 3) * (1, 1, periodic)), K=K, q0=q0,
                           W0=float(rs.choice([0.0, 1e-4])), fd_ratio=r, periodic_z=periodic,
                           coupling=bool(rs.random() < 0.85))
