@@ -60,7 +60,7 @@
 extern "C" {
 #endif
 
-#define EL_ABI_VERSION 3
+#define EL_ABI_VERSION 4
 
 /* status codes */
 enum {
@@ -127,6 +127,16 @@ typedef struct {
     int32_t parity;     /* q[parity] holds the current distributions */
     int32_t reserved;
     int64_t step;       /* LBM steps taken since el_init_lattice */
+    const void* solid;  /* optional obstacles: N bytes, 1 at solid nodes inside the channel,
+                           0 at fluid nodes (NULL: none).  Read-only, caller-owned.  The
+                           populations a fluid node sends towards an obstacle node are bounced
+                           back (halfway, Sec. II C); an obstacle node keeps the director
+                           el_init_lattice gave it (n0 there: e.g. the surface normal for
+                           homeotropic anchoring), has u = 0, zero stress and no F^LC, and
+                           its q are never read; gradients at fluid nodes read those fixed
+                           values (Sec. II B).  Observables sum fluid nodes only.  Not
+                           supported by el_init_flow, the ensemble or the y-slab calls
+                           (EL_EINVAL); the LBM then takes the generic node kernel. */
 } el_state;
 
 enum { EL_BUF_Q = 0, EL_BUF_VEC3 = 1, EL_BUF_SCRATCH = 2, EL_BUF_HALO = 3, EL_BUF_FD_HALO = 4 };
@@ -220,7 +230,12 @@ size_t el_buffer_bytes(const el_params* p, int32_t which);
  * within a few thousand steps, above it decays), while over an even number of
  * steps the kicks cancel.  The paper's split of alpha4 between the LBM and
  * the force (alpha4' = rho c_s^2 (tau - 1/2)) passes it.  Passing does not
- * guarantee long runs: watch el_obs.nonfinite and max_u. */
+ * guarantee long runs: with that alpha4' the coupled director and flow
+ * update can still grow when the force is held long against a stiff director
+ * (a 32x32x48 tube channel at tau = 1.8977 grew at r = 10 with K = 5e-3 and
+ * 2.5e-3, not with K = 1e-3 or at r <= 5), and an even r leaves a small
+ * sign-alternating velocity component undamped.  Watch el_obs.nonfinite and
+ * max_u. */
 int el_validate(const el_params* p);
 
 /* Initialisation (Sec. II D, first step): q = rest state (0 when shifted,
@@ -475,7 +490,9 @@ typedef struct {
 /* Network input of one sample (director n of a lattice, T SoA [3][N]):
  * channels (n_x, n_y, n_z, u_P(z)/V0, 0, 0, 0, 0) with the analytic
  * Poiseuille velocity u_P = g_x/(2 nu) (z - 1/2)(nz - 3/2 - z) of the channel
- * (nu = (tau - 1/2)/3, wall midway), and the halo planes (0, 0, 1, 0, ...).
+ * (nu = (tau - 1/2)/3 + alpha4'/2: the LBM viscosity and the isotropic term
+ * of the coupling force; wall midway), and the halo planes (0, 0, 1, 0, ...).
+ * Rounded to BF16 (nearest, ties to even).
  * act0 holds nsamples samples of 8 channels; V0 > 0 is the velocity unit. */
 int el_nn_input(const el_params* p, const void* n, void* act0, int32_t sample, int32_t nsamples, float V0,
                 void* stream);
@@ -514,9 +531,17 @@ int el_nn_adam(float* w, float* m, float* v, const float* grad, int32_t n, float
 
 /* Velocity of one sample from the network output res (FP32 [3][n_all]):
  * u = V0 res + u_P(z) x-hat (u_P as in el_nn_input), written as T SoA
- * [3][N] of the lattice p describes (ready for el_init_flow). */
+ * [3][N] of the lattice p describes (ready for el_init_flow).  EL_EINVAL for
+ * NULL pointers, EL_PERIODIC_Z, a sample outside 0..nsamples-1 or V0 <= 0. */
 int el_nn_velocity(const el_params* p, const float* res, int32_t sample, int32_t nsamples, float V0, void* u,
                    void* stream);
+
+/* Training target of one sample from a solver velocity u (T SoA [3][N] of
+ * the lattice p describes): res = (u - u_P(z) x-hat)/V0 into the FP32
+ * channel-major res [3][n_all] at sample `sample` (the inverse of
+ * el_nn_velocity).  Errors as for el_nn_velocity. */
+int el_nn_target(const el_params* p, const void* u, int32_t sample, int32_t nsamples, float V0, float* res,
+                 void* stream);
 
 #ifdef __cplusplus
 }

@@ -62,19 +62,37 @@ def conv_backward_weight(x, dy, zpad=None):
     return dw, dy.sum(axis=(0, 2, 3, 4))
 
 
-def network_forward(x0, layers, zpad0):
-    """layers: list of (w, b, relu); returns all activations (input first)."""
+def bf16_round(a):
+    """Round to the nearest bfloat16 (8 significand bits, ties to even), via
+    float32: the value's float32 bit pattern has its low 16 bits rounded
+    away.  Returned as float64."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    r = ((u + np.uint64(0x7FFF) + lsb) & np.uint64(0xFFFF0000)).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+def network_forward(x0, layers, zpad0, store=None):
+    """layers: list of (w, b, relu); returns all activations (input first).
+    store, if given, is applied to every hidden activation as it is kept (the
+    output layer's values are not)."""
     acts = [np.asarray(x0, dtype=np.float64)]
     for i, (w, b, relu) in enumerate(layers):
         zp = zpad0 if i == 0 else None
-        acts.append(conv_forward(acts[-1], w, b, zp, relu))
+        y = conv_forward(acts[-1], w, b, zp, relu)
+        acts.append(store(y) if (store is not None and i < len(layers) - 1) else y)
     return acts
 
 
-def network_loss_and_grads(x0, layers, zpad0, target):
+def network_loss_and_grads(x0, layers, zpad0, target, store=None):
     """MSE = mean over samples, 3 channels and voxels of (y - target)^2, and
-    its gradient with respect to every weight and bias."""
-    acts = network_forward(x0, layers, zpad0)
+    its gradient with respect to every weight and bias.  store, if given, is
+    applied to every kept hidden activation and to every activation gradient
+    (the output gradient, and each backward-data result after its ReLU
+    mask), the points where a network keeping those in a narrower format
+    rounds them."""
+    acts = network_forward(x0, layers, zpad0, store)
     out = acts[-1]
     n = out.size
     loss = float(((out - target) ** 2).sum() / n)
@@ -84,6 +102,8 @@ def network_loss_and_grads(x0, layers, zpad0, target):
         w, b, relu = layers[i]
         if relu:
             g = g * (acts[i + 1] > 0)
+        if store is not None:
+            g = store(g)
         zp = zpad0 if i == 0 else None
         grads[i] = conv_backward_weight(acts[i], g, zp)
         if i > 0:

@@ -41,6 +41,12 @@
  *       that of the fluid node next to it across the wall (zero normal
  *       gradient, the natural condition of a free surface), u = 0 and
  *       sigma = 0 as in R7.
+ *   R7'' obstacles (solid nodes inside the channel, or_set_obstacles): the
+ *       populations a fluid node sends towards one are bounced back into the
+ *       opposite direction at the node (halfway bounce-back, Sec. II C); the
+ *       obstacle node's director is held at its initial value (homeotropic
+ *       anchoring when that is the surface normal), u = 0 and sigma = 0
+ *       there; gradients at fluid nodes read those fixed values (Sec. II B).
  *   R8  collide, then stream; moments after streaming; reported u includes
  *       F/(2 rho).
  *   R9  total force density F = rho g + F^LC.
@@ -144,6 +150,7 @@ struct or_state {
     double *q, *qn; /* 19*N each */
     double *n, *nP, *dn_old, *u, *F; /* 3*N each; F is F^LC */
     double *sig;    /* 9*N scratch for the stress */
+    uint8_t* obst;  /* N: 1 at obstacle nodes inside the channel, or NULL */
     int64_t t;
 };
 
@@ -175,7 +182,7 @@ static int z_hi(const or_params* p) { return p->periodic_z ? p->nz : p->nz - 1; 
 
 /* Neighbour along axis b (0,1,2) with step s (+1/-1): periodic in x, y (and in
  * z when periodic_z).  Writes the coordinates; returns 1 if the neighbour is a
- * solid node. */
+ * wall node. */
 static int neighbour(const or_params* p, int x, int y, int z, int b, int s, int* xo, int* yo, int* zo)
 {
     int c[3] = {x, y, z};
@@ -187,6 +194,13 @@ static int neighbour(const or_params* p, int x, int y, int z, int b, int s, int*
     *yo = c[1];
     *zo = c[2];
     return is_solid(p, c[2]);
+}
+
+/* 1 at an obstacle node: a solid node inside the channel (R7'', see
+ * or_set_obstacles). */
+static int obstacle(const or_state* st, int x, int y, int z)
+{
+    return st->obst != NULL && st->obst[idx(&st->p, x, y, z)] != 0;
 }
 
 or_state* or_create(const or_params* p)
@@ -202,6 +216,7 @@ or_state* or_create(const or_params* p)
     s->u = (double*)calloc((size_t)(3 * s->N), sizeof(double));
     s->F = (double*)calloc((size_t)(3 * s->N), sizeof(double));
     s->sig = (double*)calloc((size_t)(9 * s->N), sizeof(double));
+    s->obst = NULL;
     return s;
 }
 
@@ -216,6 +231,7 @@ void or_destroy(or_state* s)
     free(s->u);
     free(s->F);
     free(s->sig);
+    free(s->obst);
     free(s);
 }
 
@@ -255,6 +271,10 @@ void or_moments(or_state* s)
             for (int x = 0; x < p->nx; ++x) {
                 int64_t k = idx(p, x, y, z);
                 double rho, drho, u[3], Ft[3];
+                if (obstacle(s, x, y, z)) { /* no slip: an obstacle node is at rest */
+                    for (int a = 0; a < 3; ++a) s->u[(int64_t)a * s->N + k] = 0.0;
+                    continue;
+                }
                 node_moments(s, s->q, k, &rho, &drho, u, Ft);
                 for (int a = 0; a < 3; ++a) s->u[(int64_t)a * s->N + k] = u[a];
             }
@@ -275,6 +295,7 @@ static void lbm_step(or_state* s)
             for (int x = 0; x < p->nx; ++x) {
                 int64_t k = idx(p, x, y, z);
                 double rho, drho, u[3], Ft[3], eq[19], S[19];
+                if (obstacle(s, x, y, z)) continue; /* solid: no collision, nothing streamed */
                 node_moments(s, s->q, k, &rho, &drho, u, Ft);
                 or_equilibrium(rho, drho, u, p->shifted, eq);
                 or_guo_source(u, Ft, S);
@@ -285,7 +306,7 @@ static void lbm_step(or_state* s)
                     int yd = wrap(y + E[i][1], p->ny);
                     int zd = z + E[i][2];
                     if (p->periodic_z) zd = wrap(zd, p->nz);
-                    if (is_solid(p, zd))
+                    if (is_solid(p, zd) || obstacle(s, xd, yd, zd))
                         s->qn[(int64_t)OPP[i] * s->N + k] = post;
                     else
                         s->qn[(int64_t)i * s->N + idx(p, xd, yd, zd)] = post;
@@ -329,6 +350,8 @@ static double nb(const or_state* st, const double* f, int field_kind, int c, int
             return f[(int64_t)c * st->N + idx(&st->p, xo, yo, mirror_layer(&st->p, zo))];
         return solid_value(field_kind, c);
     }
+    /* an obstacle node is stored: its director is the fixed one, and u and
+     * sigma are held at zero there by the moments and the force */
     return f[(int64_t)c * st->N + idx(&st->p, xo, yo, zo)];
 }
 
@@ -611,6 +634,7 @@ static void compute_force(or_state* st, int term_mask, double* F_out)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
                 double sg[3][3];
+                if (obstacle(st, x, y, z)) continue; /* sigma = 0 at solid nodes */
                 stress_node(st, term_mask, x, y, z, sg);
                 for (int a = 0; a < 3; ++a)
                     for (int b = 0; b < 3; ++b) st->sig[(int64_t)(a * 3 + b) * st->N + idx(p, x, y, z)] = sg[a][b];
@@ -619,6 +643,10 @@ static void compute_force(or_state* st, int term_mask, double* F_out)
     for (int z = z_lo(p); z < z_hi(p); ++z)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
+                if (obstacle(st, x, y, z)) {
+                    for (int a = 0; a < 3; ++a) F_out[(int64_t)a * st->N + idx(p, x, y, z)] = 0.0;
+                    continue;
+                }
                 for (int a = 0; a < 3; ++a) {
                     double div = 0.0;
                     for (int b = 0; b < 3; ++b)
@@ -651,6 +679,13 @@ void or_step_director(or_state* s)
             for (int x = 0; x < p->nx; ++x) {
                 int64_t k = idx(p, x, y, z);
                 double r[3], v[3];
+                if (obstacle(s, x, y, z)) { /* fixed director at solid nodes */
+                    for (int a = 0; a < 3; ++a) {
+                        s->dn_old[(int64_t)a * s->N + k] = 0.0;
+                        s->nP[(int64_t)a * s->N + k] = s->n[(int64_t)a * s->N + k];
+                    }
+                    continue;
+                }
                 director_rhs_node(s, s->n, x, y, z, r);
                 for (int a = 0; a < 3; ++a) {
                     s->dn_old[(int64_t)a * s->N + k] = r[a];
@@ -665,6 +700,7 @@ void or_step_director(or_state* s)
             for (int x = 0; x < p->nx; ++x) {
                 int64_t k = idx(p, x, y, z);
                 double r[3], v[3];
+                if (obstacle(s, x, y, z)) continue;
                 director_rhs_node(s, s->nP, x, y, z, r);
                 for (int a = 0; a < 3; ++a)
                     v[a] = s->n[(int64_t)a * s->N + k] + 0.5 * dt * (s->dn_old[(int64_t)a * s->N + k] + r[a]);
@@ -811,6 +847,24 @@ void or_init_flow(or_state* s, const double* u0)
     or_moments(s);
 }
 
+/* Obstacles (R7''): mask in external layout, 1 at solid nodes inside the
+ * channel; NULL removes them.  An obstacle node takes part in nothing but
+ * the stencils of its fluid neighbours: halfway bounce-back of the
+ * populations sent towards it, its director held at the value it has
+ * (homeotropic anchoring when that is the surface normal), u = 0, sigma = 0. */
+void or_set_obstacles(or_state* s, const uint8_t* mask)
+{
+    const or_params* p = &s->p;
+    free(s->obst);
+    s->obst = NULL;
+    if (!mask) return;
+    s->obst = (uint8_t*)calloc((size_t)s->N, 1);
+    for (int z = z_lo(p); z < z_hi(p); ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x)
+                s->obst[idx(p, x, y, z)] = mask[idx(p, x, y, z - z_lo(p))] ? 1 : 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Test hooks. */
 
@@ -822,6 +876,7 @@ void or_molecular_field(const or_state* s, double* h_out)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
                 double h[3];
+                if (obstacle(s, x, y, z)) continue;
                 molecular_field(s, s->n, x, y, z, h);
                 for (int a = 0; a < 3; ++a) full[(int64_t)a * s->N + idx(p, x, y, z)] = h[a];
             }
@@ -840,6 +895,7 @@ void or_director_rhs(const or_state* s, const double* m, double* out)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
                 double r[3];
+                if (obstacle(s, x, y, z)) continue;
                 director_rhs_node(s, mfull, x, y, z, r);
                 for (int a = 0; a < 3; ++a) full[(int64_t)a * s->N + idx(p, x, y, z)] = r[a];
             }
@@ -856,6 +912,7 @@ void or_stress(const or_state* s, int32_t term_mask, double* sigma_out)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
                 double sg[3][3];
+                if (obstacle(s, x, y, z)) continue;
                 stress_node(s, term_mask, x, y, z, sg);
                 for (int a = 0; a < 3; ++a)
                     for (int b = 0; b < 3; ++b) full[(int64_t)(a * 3 + b) * s->N + idx(p, x, y, z)] = sg[a][b];
@@ -886,6 +943,7 @@ void or_observables(const or_state* s, or_obs* out)
             for (int x = 0; x < p->nx; ++x) {
                 int64_t k = idx(p, x, y, z);
                 double sum = 0.0, j[3] = {0.0, 0.0, 0.0};
+                if (obstacle(s, x, y, z)) continue; /* fluid nodes only */
                 for (int i = 0; i < 19; ++i) {
                     double qi = s->q[(int64_t)i * s->N + k];
                     if (!isfinite(qi)) out->nonfinite = 1;
@@ -924,7 +982,7 @@ void or_tube_centroids(const or_state* s, int32_t ntubes, const double* seeds, d
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
                 double w = -s->n[2 * s->N + idx(p, x, y, z)];
-                if (!(w > 0.0)) continue;
+                if (!(w > 0.0) || obstacle(s, x, y, z)) continue;
                 int best = 0;
                 double best_d2 = 0.0;
                 for (int t = 0; t < ntubes; ++t) {

@@ -77,6 +77,10 @@ void or_init(or_state* s, const double* n0);
  * definition). */
 void or_init_flow(or_state* s, const double* u0);
 
+/* Obstacles: mask (external layout, one byte per node, 1 = solid) of solid
+ * nodes inside the channel, or NULL for none.  Call before or_init. */
+void or_set_obstacles(or_state* s, const uint8_t* mask);
+
 /* nsteps LBM steps with F^LC held fixed; u is recomputed after every step. */
 void or_step_lbm(or_state* s, int32_t nsteps);
 

@@ -81,6 +81,7 @@ def load_library(path: str):
     lib.or_force_masked.argtypes = [C.c_void_p, C.c_int32, D]
     lib.or_observables.argtypes = [C.c_void_p, C.POINTER(_Obs)]
     lib.or_tube_centroids.argtypes = [C.c_void_p, C.c_int32, D, D, D]
+    lib.or_set_obstacles.argtypes = [C.c_void_p, C.c_void_p]
     lib.or_lattice.argtypes = [D, D, C.POINTER(C.c_int32)]
     lib.or_equilibrium.argtypes = [C.c_double, C.c_double, D, C.c_int32, D]
     lib.or_guo_source.argtypes = [D, D, D]
@@ -199,6 +200,16 @@ class Oracle:
 
     def _arr(self, ncomp):
         return np.zeros((ncomp,) + self.shape)
+
+    def set_obstacles(self, mask):
+        """Solid nodes inside the channel: a (nzf, ny, nx) mask (nonzero =
+        solid), or None.  Call before init()."""
+        if mask is None:
+            self.lib.or_set_obstacles(self.h, None)
+            return
+        m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8).reshape(self.shape)
+        self._mask = m
+        self.lib.or_set_obstacles(self.h, m.ctypes.data_as(C.c_void_p))
 
     def init(self, n0: np.ndarray):
         a = np.ascontiguousarray(n0, dtype=np.float64).reshape((3,) + self.shape)

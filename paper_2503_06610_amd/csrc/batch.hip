@@ -607,6 +607,7 @@ int el_batch_create(const el_params* params, el_state* states, int32_t nchan, co
             return fail(EL_EINVAL, "channel %d has another precision than channel 0", c);
         if (params[c].flags & EL_FRANK3)
             return fail(EL_EINVAL, "channel %d: the ensemble does not support EL_FRANK3", c);
+        if (states[c].solid) return fail(EL_EINVAL, "channel %d: the ensemble does not support obstacles", c);
     }
     el_batch* b = new el_batch();
     b->nchan = nchan;

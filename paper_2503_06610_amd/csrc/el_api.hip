@@ -112,8 +112,20 @@ using namespace elh;
 template <typename T, bool SHIFT>
 int launch_lbm_steps(const el_params* p, el_state* s, int nsteps, hipStream_t st)
 {
-    const el::LbmArgs<T> a = lbm_args<T>(p);
+    el::LbmArgs<T> a = lbm_args<T>(p);
     const int grid = grid_for(a.g.N);
+    if (s->solid) {
+        // obstacles: the generic node kernel with the destination check
+        a.solid = static_cast<const unsigned char*>(s->solid);
+        for (int k = 0; k < nsteps; ++k) {
+            hipLaunchKernelGGL((el::k_lbm_push<T, SHIFT, true>), dim3(grid), dim3(BLOCK), 0, st,
+                               static_cast<const T*>(s->q[s->parity]), static_cast<T*>(s->q[1 - s->parity]),
+                               static_cast<const T*>(s->F), a);
+            s->parity = 1 - s->parity;
+            s->step += 1;
+        }
+        return check_launch("LBM step kernel");
+    }
     // whole-row blocks with the x shifts through LDS: one row per block when a
     // row is a whole number of wavefronts, else as many rows as fit in 256
     // threads (several rows per block when nx is a multiple of 64 measured
@@ -152,16 +164,25 @@ int launch_lbm_steps(const el_params* p, el_state* s, int nsteps, hipStream_t st
 template <typename T, bool SHIFT>
 int launch_moments(const el_params* p, el_state* s, hipStream_t st)
 {
-    const el::LbmArgs<T> a = lbm_args<T>(p);
-    hipLaunchKernelGGL((el::k_moments<T, SHIFT>), dim3(grid_for(a.g.N)), dim3(BLOCK), 0, st,
-                       static_cast<const T*>(s->q[s->parity]), static_cast<const T*>(s->F), static_cast<T*>(s->u), a);
+    el::LbmArgs<T> a = lbm_args<T>(p);
+    if (s->solid) {
+        a.solid = static_cast<const unsigned char*>(s->solid);
+        hipLaunchKernelGGL((el::k_moments<T, SHIFT, true>), dim3(grid_for(a.g.N)), dim3(BLOCK), 0, st,
+                           static_cast<const T*>(s->q[s->parity]), static_cast<const T*>(s->F),
+                           static_cast<T*>(s->u), a);
+    } else {
+        hipLaunchKernelGGL((el::k_moments<T, SHIFT>), dim3(grid_for(a.g.N)), dim3(BLOCK), 0, st,
+                           static_cast<const T*>(s->q[s->parity]), static_cast<const T*>(s->F),
+                           static_cast<T*>(s->u), a);
+    }
     return check_launch("k_moments");
 }
 
 template <typename T>
 int launch_force(const el_params* p, el_state* s, hipStream_t st)
 {
-    const el::FdArgs<T> a = fd_args<T>(p);
+    el::FdArgs<T> a = fd_args<T>(p);
+    a.solid = static_cast<const unsigned char*>(s->solid);
     if (!coupling(p)) {
         hipLaunchKernelGGL((el::k_fill<T>), dim3(grid_for(3 * a.g.N)), dim3(BLOCK), 0, st, static_cast<T*>(s->F),
                            T(0), 3 * a.g.N);
@@ -170,7 +191,7 @@ int launch_force(const el_params* p, el_state* s, hipStream_t st)
     const int tiles_x = (a.g.nx + el::FORCE_TX - 1) / el::FORCE_TX;
     const int tiles_y = (a.g.ny + el::FORCE_TY - 1) / el::FORCE_TY;
     const int chunks = (a.g.nzf + el::FORCE_ZC - 1) / el::FORCE_ZC;
-    if (!frank3(p) && one_pass_force(p, tiles_x * tiles_y * chunks)) {
+    if (!frank3(p) && !s->solid && one_pass_force(p, tiles_x * tiles_y * chunks)) {
         hipLaunchKernelGGL((el::k_fd_force<T, el::FORCE_TY>), dim3(tiles_x * tiles_y * chunks),
                            dim3(el::FORCE_TX * el::FORCE_TY), 0, st, static_cast<const T*>(s->n),
                            static_cast<const T*>(s->u), static_cast<T*>(s->F), a, el::FORCE_ZC, tiles_x, tiles_y);
@@ -192,7 +213,8 @@ int launch_force(const el_params* p, el_state* s, hipStream_t st)
 template <typename T>
 int launch_director(const el_params* p, el_state* s, hipStream_t st)
 {
-    const el::FdArgs<T> a = fd_args<T>(p);
+    el::FdArgs<T> a = fd_args<T>(p);
+    a.solid = static_cast<const unsigned char*>(s->solid);
     if (p->flags & EL_FREEZE_DIRECTOR) return launch_force<T>(p, s, st);
     const int grid = grid_for(a.g.N);
     if (frank3(p)) {
@@ -266,6 +288,7 @@ int observables_impl(const el_params* p, const el_state* s, const el::TubeSeeds&
     a.gx = p->g[0];
     a.gy = p->g[1];
     a.gz = p->g[2];
+    a.solid = static_cast<const unsigned char*>(s->solid);
     int blocks = grid_for(a.g.N);
     if (blocks > el::OBS_MAX_BLOCKS) blocks = el::OBS_MAX_BLOCKS;
     double* partial = static_cast<double*>(s->scratch);
@@ -468,6 +491,7 @@ int el_init_flow(const el_params* p, el_state* s, const void* u0, void* stream)
     if (rc != EL_OK) return rc;
     if ((rc = state_checks(p, s)) != EL_OK) return rc;
     if (!u0) return fail(EL_EINVAL, "u0 is NULL");
+    if (s->solid) return fail(EL_EINVAL, "el_init_flow does not support obstacles");
     hipStream_t st = static_cast<hipStream_t>(stream);
     EL_DISPATCH(p, (init_flow_impl<T, SH>(p, s, u0, st)))
 }
@@ -545,6 +569,7 @@ int el_halo_pack(const el_params* p, const el_state* s, void* out, void* stream)
     if (rc != EL_OK) return rc;
     if ((rc = state_checks(p, s)) != EL_OK) return rc;
     if (!out) return fail(EL_EINVAL, "halo buffer is NULL");
+    if (s->solid) return fail(EL_EINVAL, "the y-slab exchange does not support obstacles");
     const el::Geom g = geom_of(p);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const dim3 grid((5 * g.nx * g.nzf + BLOCK - 1) / BLOCK);
@@ -563,6 +588,7 @@ int el_halo_unpack(const el_params* p, el_state* s, const void* lower, const voi
     if (rc != EL_OK) return rc;
     if ((rc = state_checks(p, s)) != EL_OK) return rc;
     if (!lower || !upper) return fail(EL_EINVAL, "halo buffer is NULL");
+    if (s->solid) return fail(EL_EINVAL, "the y-slab exchange does not support obstacles");
     const el::Geom g = geom_of(p);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const dim3 grid((5 * g.nx * g.nzf + BLOCK - 1) / BLOCK);
@@ -583,6 +609,7 @@ int el_fd_halo_pack(const el_params* p, const el_state* s, int32_t stage, void* 
     if (stage < 0 || stage > 3) return fail(EL_EINVAL, "FD stage %d (0..3)", stage);
     if (!out) return fail(EL_EINVAL, "halo buffer is NULL");
     if (frank3(p)) return fail(EL_EINVAL, "the y-slab FD stages do not support EL_FRANK3");
+    if (s->solid) return fail(EL_EINVAL, "the y-slab FD stages do not support obstacles");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (is_f64(p)) return fd_face_pack_impl<double>(p, s, stage, static_cast<double*>(out), st);
     return fd_face_pack_impl<float>(p, s, stage, static_cast<float*>(out), st);
@@ -596,6 +623,7 @@ int el_fd_stage(const el_params* p, el_state* s, int32_t stage, const void* lowe
     if (stage < 0 || stage > 3) return fail(EL_EINVAL, "FD stage %d (0..3)", stage);
     if (!lower || !upper) return fail(EL_EINVAL, "halo buffer is NULL");
     if (frank3(p)) return fail(EL_EINVAL, "the y-slab FD stages do not support EL_FRANK3");
+    if (s->solid) return fail(EL_EINVAL, "the y-slab FD stages do not support obstacles");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (is_f64(p))
         return fd_stage_impl<double>(p, s, stage, static_cast<const double*>(lower), static_cast<const double*>(upper),

@@ -24,6 +24,8 @@ struct FdArgs {
     T a1, a2, a3, a4p, a5, a6;
     T ks, kt, kb;  // three-constant corrections K11 - Km, K22 - Km, K33 - Km
     int renorm_predictor;
+    const unsigned char* solid;  // obstacle mask (1 = solid node inside the channel), or nullptr:
+                                 // the director is held there, sigma and F are zero
 };
 
 // 7-point stencil of a 3-vector field: v[0] centre, v[1 + 2b] = minus side,
@@ -275,10 +277,18 @@ template <typename T, bool F3 = false>
 __device__ __forceinline__ void predictor_node(const T* __restrict__ n, const T* __restrict__ u, T* __restrict__ nP,
                                                T* __restrict__ dndt, const FdArgs<T>& a, int k)
 {
+    const size_t N = (size_t)a.g.N;
+    if (a.solid && a.solid[k]) {  // obstacle node: fixed director
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            nP[c * N + k] = n[c * N + k];
+            dndt[c * N + k] = T(0);
+        }
+        return;
+    }
     int x, y, z;
     node_coords(a.g, k, x, y, z);
     const Nbr nb = make_nbr(a.g, x, y, z);
-    const size_t N = (size_t)a.g.N;
     Stencil3<T> m, uu;
     gather3<T, 0>(n, nb, N, m);
     gather3<T, 1>(u, nb, N, uu);
@@ -307,6 +317,7 @@ template <typename T, bool F3 = false>
 __device__ __forceinline__ void corrector_node(T* __restrict__ n, const T* __restrict__ nP, const T* __restrict__ u,
                                                const T* __restrict__ dndt, const FdArgs<T>& a, int k)
 {
+    if (a.solid && a.solid[k]) return;  // obstacle node: fixed director
     int x, y, z;
     node_coords(a.g, k, x, y, z);
     const Nbr nb = make_nbr(a.g, x, y, z);
@@ -437,10 +448,15 @@ template <typename T, bool F3 = false>
 __device__ __forceinline__ void stress_node(const T* __restrict__ n, const T* __restrict__ u, T* __restrict__ sig,
                                             const FdArgs<T>& a, int k)
 {
+    const size_t N = (size_t)a.g.N;
+    if (a.solid && a.solid[k]) {  // zero stress at obstacle nodes
+#pragma unroll
+        for (int i = 0; i < 9; ++i) sig[i * N + k] = T(0);
+        return;
+    }
     int x, y, z;
     node_coords(a.g, k, x, y, z);
     const Nbr nb = make_nbr(a.g, x, y, z);
-    const size_t N = (size_t)a.g.N;
     Stencil3<T> m, uu;
     gather3<T, 0>(n, nb, N, m);
     gather3<T, 1>(u, nb, N, uu);
@@ -464,10 +480,14 @@ template <typename T>
 __device__ __forceinline__ void divergence_node(const T* __restrict__ sig, T* __restrict__ F, const FdArgs<T>& a,
                                                 int k)
 {
+    const size_t N = (size_t)a.g.N;
+    if (a.solid && a.solid[k]) {  // no force on obstacle nodes
+        F[k] = F[N + k] = F[2 * N + k] = T(0);
+        return;
+    }
     int x, y, z;
     node_coords(a.g, k, x, y, z);
     const Nbr nb = make_nbr(a.g, x, y, z);
-    const size_t N = (size_t)a.g.N;
     const int plus[3] = {nb.xp, nb.yp, nb.zp};
     const int minus[3] = {nb.xm, nb.ym, nb.zm};
 #pragma unroll

@@ -110,6 +110,7 @@ el::LbmArgs<T> lbm_args(const el_params* p)
     a.gy = T(p->g[1]);
     a.gz = T(p->g[2]);
     a.coupling = coupling(p) ? 1 : 0;
+    a.solid = nullptr;
     return a;
 }
 
@@ -147,6 +148,7 @@ el::FdArgs<T> fd_args(const el_params* p)
     a.a5 = T(p->alpha[4]);
     a.a6 = T(p->alpha[5]);
     a.renorm_predictor = (p->flags & EL_NO_RENORM_PREDICTOR) ? 0 : 1;
+    a.solid = nullptr;
     return a;
 }
 

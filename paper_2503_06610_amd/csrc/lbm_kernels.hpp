@@ -54,6 +54,7 @@ struct LbmArgs {
     T cS;        // 1 - 1/(2 tau), weight of the Guo source
     T gx, gy, gz;  // body acceleration (force density rho g)
     int coupling;  // 0: F^LC is treated as zero and not read
+    const unsigned char* solid;  // obstacle mask (1 = solid node inside the channel), or nullptr
 };
 
 // Density and momentum of one node: rho - 1 = sum q (shifted) or rho = sum f,
@@ -130,12 +131,15 @@ __device__ __forceinline__ void lbm_collide(const T* __restrict__ qa, const T* _
 
 // One LBM step for fluid node k: collide, then push to the neighbours in qb.
 // A population whose destination is a wall node returns to its own node in
-// the opposite direction (wall midway between fluid and solid node).
-template <typename T, bool SHIFT>
+// the opposite direction (wall midway between fluid and solid node).  MASK:
+// the same for destinations that are obstacle nodes (a.solid), and obstacle
+// nodes themselves neither collide nor stream.
+template <typename T, bool SHIFT, bool MASK = false>
 __device__ __forceinline__ void lbm_node(const T* __restrict__ qa, T* __restrict__ qb, const T* __restrict__ Flc,
                                          const LbmArgs<T>& a, int k)
 {
     const Geom& g = a.g;
+    if (MASK && a.solid[k]) return;
     const int x = k % g.nx;
     const int t = k / g.nx;
     const int y = t % g.ny;
@@ -160,10 +164,10 @@ __device__ __forceinline__ void lbm_node(const T* __restrict__ qa, T* __restrict
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
         const bool to_wall = (EZ(i) == 1 && wall_p) || (EZ(i) == -1 && wall_m);
-        if (to_wall) {
+        const int d = xs[EX(i) + 1] + ys[EY(i) + 1] + zs[EZ(i) + 1];
+        if (to_wall || (MASK && i != 0 && a.solid[d])) {
             qb[OPP(i) * N + k] = post[i];
         } else {
-            const int d = xs[EX(i) + 1] + ys[EY(i) + 1] + zs[EZ(i) + 1];
             qb[i * N + d] = post[i];
         }
     }
@@ -242,21 +246,28 @@ __global__ void __launch_bounds__(1024) k_lbm_push_row(const T* __restrict__ qa,
     lbm_rows<T, SHIFT, ONE_ROW, NTS>(qa, qb, Flc, a, (int)blockIdx.x * R, R, reinterpret_cast<T*>(lbm_smem));
 }
 
-template <typename T, bool SHIFT>
+template <typename T, bool SHIFT, bool MASK = false>
 __global__ void __launch_bounds__(256) k_lbm_push(const T* __restrict__ qa, T* __restrict__ qb,
                                                  const T* __restrict__ Flc, LbmArgs<T> a)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.g.N) return;
-    lbm_node<T, SHIFT>(qa, qb, Flc, a, k);
+    lbm_node<T, SHIFT, MASK>(qa, qb, Flc, a, k);
 }
 
-// u = (sum e q + F/2)/rho, F = rho g + F^LC, at fluid node k.
-template <typename T, bool SHIFT>
+// u = (sum e q + F/2)/rho, F = rho g + F^LC, at fluid node k; u = 0 at an
+// obstacle node (MASK).
+template <typename T, bool SHIFT, bool MASK = false>
 __device__ __forceinline__ void moments_node(const T* __restrict__ q_in, const T* __restrict__ Flc,
                                              T* __restrict__ u, const LbmArgs<T>& a, int k)
 {
     const size_t N = (size_t)a.g.N;
+    if (MASK && a.solid[k]) {
+        u[k] = T(0);
+        u[N + k] = T(0);
+        u[2 * N + k] = T(0);
+        return;
+    }
     T q[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) q[i] = q_in[i * N + k];
@@ -275,13 +286,13 @@ __device__ __forceinline__ void moments_node(const T* __restrict__ q_in, const T
 }
 
 // Velocity of the current state: u = (sum e q + F/2)/rho, F = rho g + F^LC.
-template <typename T, bool SHIFT>
+template <typename T, bool SHIFT, bool MASK = false>
 __global__ void __launch_bounds__(256) k_moments(const T* __restrict__ q_in, const T* __restrict__ Flc,
                                                 T* __restrict__ u, LbmArgs<T> a)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.g.N) return;
-    moments_node<T, SHIFT>(q_in, Flc, u, a, k);
+    moments_node<T, SHIFT, MASK>(q_in, Flc, u, a, k);
 }
 
 // Fills n values with v (used instead of a memset so the launch sequence can

@@ -300,6 +300,7 @@ int el_nn_velocity(const el_params* p, const float* res, int32_t sample, int32_t
     int rc = basic_checks(p);
     if (rc != EL_OK) return rc;
     if (!res || !u) return fail(EL_EINVAL, "NULL pointer");
+    if (periodic_z(p)) return fail(EL_EINVAL, "the surrogate needs walls");
     if (sample < 0 || sample >= nsamples) return fail(EL_EINVAL, "sample %d of %d", sample, nsamples);
     if (!(V0 > 0.0f)) return fail(EL_EINVAL, "V0 must be positive");
     el_nn_vol v{p->nx, p->ny, p->nz - 2, nsamples};
@@ -315,6 +316,30 @@ int el_nn_velocity(const el_params* p, const float* res, int32_t sample, int32_t
         hipLaunchKernelGGL((el::nn::k_nn_velocity<float>), dim3(grid), dim3(256), 0, st, res, static_cast<float*>(u),
                            g, sample, V0, c);
     return check_launch("k_nn_velocity");
+}
+
+int el_nn_target(const el_params* p, const void* u, int32_t sample, int32_t nsamples, float V0, float* res,
+                 void* stream)
+{
+    int rc = basic_checks(p);
+    if (rc != EL_OK) return rc;
+    if (!res || !u) return fail(EL_EINVAL, "NULL pointer");
+    if (periodic_z(p)) return fail(EL_EINVAL, "the surrogate needs walls");
+    if (sample < 0 || sample >= nsamples) return fail(EL_EINVAL, "sample %d of %d", sample, nsamples);
+    if (!(V0 > 0.0f)) return fail(EL_EINVAL, "V0 must be positive");
+    el_nn_vol v{p->nx, p->ny, p->nz - 2, nsamples};
+    VolGeom g;
+    if ((rc = vol_of(&v, &g)) != EL_OK) return rc;
+    const float c = poiseuille_coeff(p, V0);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int grid = (int)((g.n_int + 255) / 256);
+    if (is_f64(p))
+        hipLaunchKernelGGL((el::nn::k_nn_target<double>), dim3(grid), dim3(256), 0, st, static_cast<const double*>(u),
+                           res, g, sample, 1.0f / V0, c);
+    else
+        hipLaunchKernelGGL((el::nn::k_nn_target<float>), dim3(grid), dim3(256), 0, st, static_cast<const float*>(u),
+                           res, g, sample, 1.0f / V0, c);
+    return check_launch("k_nn_target");
 }
 
 }  // extern "C"

@@ -1086,5 +1086,23 @@ __global__ void __launch_bounds__(256) k_nn_velocity(const float* __restrict__ r
     u[2 * N + k] = (T)(V0 * res[2 * g.n_all + v]);
 }
 
+// Training target from a solver velocity: res = u/V0 - u_P(z)/V0 x-hat, the
+// inverse of k_nn_velocity, into the FP32 channel-major [3][n_all] layout.
+template <typename T>
+__global__ void __launch_bounds__(256) k_nn_target(const T* __restrict__ u, float* __restrict__ res, VolGeom g,
+                                                  int sample, float inv_V0, float c)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= g.n_int) return;
+    const long long plane = (long long)g.nx * g.ny;
+    const float z = (float)(k / plane + 1);
+    const float p = c * (z - 0.5f) * ((float)(g.nzf + 2) - 1.5f - z);
+    const long long v = (long long)sample * g.n_int + k;
+    const long long N = (long long)g.n_int;
+    res[v] = (float)u[k] * inv_V0 - p;
+    res[g.n_all + v] = (float)u[N + k] * inv_V0;
+    res[2 * g.n_all + v] = (float)u[2 * N + k] * inv_V0;
+}
+
 }  // namespace nn
 }  // namespace el

@@ -61,6 +61,7 @@ struct ObsArgs {
     int shifted;
     int coupling;
     double gx, gy, gz;
+    const unsigned char* solid;  // obstacle mask (excluded from the sums), or nullptr
 };
 
 // The tube seeds of one observables call: by value (el_observables) or read
@@ -115,6 +116,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_obs_partial(const T* __restrict
     const size_t N = (size_t)a.g.N;
     const double two_pi = 6.283185307179586476925286766559;
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < a.g.N; k += gridDim.x * blockDim.x) {
+        if (a.solid && a.solid[k]) continue;  // fluid nodes only
         double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
         bool bad = false;
 #pragma unroll

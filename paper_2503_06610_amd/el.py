@@ -32,7 +32,7 @@ EXPORTED = ("el_version", "el_strerror", "el_last_error", "el_buffer_bytes", "el
             "el_batch_step", "el_batch_capture",
             "el_batch_moments", "el_batch_observables", "el_batch_sync", "el_batch_get_tuning", "el_batch_destroy",
             "el_nn_input", "el_nn_conv_forward", "el_nn_conv_backward_data", "el_nn_work_bytes",
-            "el_nn_conv_backward_weight", "el_nn_mse", "el_nn_adam", "el_nn_velocity", "el_halo_pack",
+            "el_nn_conv_backward_weight", "el_nn_mse", "el_nn_adam", "el_nn_velocity", "el_nn_target", "el_halo_pack",
             "el_halo_unpack", "el_stream_copy", "el_fd_halo_pack", "el_fd_stage")
 
 
@@ -53,7 +53,7 @@ class el_params(C.Structure):
 class el_state(C.Structure):
     _fields_ = [("q", C.c_void_p * 2), ("n", C.c_void_p), ("n_pred", C.c_void_p), ("dndt", C.c_void_p),
                 ("u", C.c_void_p), ("F", C.c_void_p), ("scratch", C.c_void_p), ("parity", C.c_int32),
-                ("reserved", C.c_int32), ("step", C.c_int64)]
+                ("reserved", C.c_int32), ("step", C.c_int64), ("solid", C.c_void_p)]
 
 
 EL_MAX_TUBES = 8
@@ -165,6 +165,7 @@ def load(path: str = LIB_PATH):
         "el_nn_adam": (C.c_int, [V, V, V, V, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32,
                                  V, V, C.c_int32, C.c_int32, V]),
         "el_nn_velocity": (C.c_int, [P, V, C.c_int32, C.c_int32, C.c_float, V, V]),
+        "el_nn_target": (C.c_int, [P, V, C.c_int32, C.c_int32, C.c_float, V, V]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -224,7 +225,8 @@ class Lattice:
     """Device buffers of one channel (torch tensors) and the C-ABI calls on them."""
 
     def __init__(self, prob, precision: str = "f32_shifted", device: str = "cuda", allow_unstable: bool = False,
-                 freeze_director: bool = False, force_kernel: str = "auto"):
+                 freeze_director: bool = False, force_kernel: str = "auto", solid=None):
+        """solid: optional obstacle mask, shape (nzf, ny, nx), nonzero = solid node."""
         import torch
         self.lib = load()
         self.prob = prob
@@ -256,6 +258,11 @@ class Lattice:
         self.state.scratch = self.scratch.data_ptr()
         self.state.parity = 0
         self.state.step = 0
+        self.solid = None
+        if solid is not None:
+            m = np.ascontiguousarray(np.asarray(solid) != 0, dtype=np.uint8).reshape(prob.shape(1)[1:])
+            self.solid = torch.from_numpy(m).to(dev)
+            self.state.solid = self.solid.data_ptr()
 
     # -- the C-ABI entry points ---------------------------------------------
     def init_lattice(self, n0, stream=None):

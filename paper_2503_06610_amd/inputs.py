@@ -177,6 +177,38 @@ def director_tubes(prob: Problem, centres, radius: float, z_modulated: bool = Fa
     return out
 
 
+def obstacle_cylinder(prob: Problem, centre, radius: float) -> np.ndarray:
+    """Obstacle mask (nzf, ny, nx), 1 inside a cylinder along z through all
+    fluid layers: periodic distance to centre (xc, yc) below radius."""
+    X, Y = np.meshgrid(np.arange(prob.nx, dtype=np.float64), np.arange(prob.ny, dtype=np.float64))
+    dx = (X - centre[0] + prob.nx / 2.0) % prob.nx - prob.nx / 2.0
+    dy = (Y - centre[1] + prob.ny / 2.0) % prob.ny - prob.ny / 2.0
+    inside = (np.hypot(dx, dy) < radius).astype(np.uint8)
+    return np.ascontiguousarray(np.broadcast_to(inside, (prob.nzf, prob.ny, prob.nx)))
+
+
+def director_obstacle_anchoring(n0: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """n0 with homeotropic anchoring at obstacle nodes: the director of a solid
+    node is the outward normal of the obstacle there, taken as the normalised
+    sum of the unit offsets towards its fluid face neighbours in the (x, y)
+    plane (z-hat where no fluid neighbour lies in the plane)."""
+    solid = mask.astype(bool)
+    nrm = np.zeros((3,) + mask.shape)
+    for axis, comp in ((2, 0), (1, 1)):  # x (last axis) -> component 0, y -> component 1
+        for step in (1, -1):
+            fluid_nb = ~np.roll(solid, -step, axis=axis)
+            nrm[comp] += step * fluid_nb
+    length = np.sqrt((nrm * nrm).sum(0))
+    out = np.array(n0, dtype=np.float64, copy=True)
+    has = solid & (length > 0)
+    for c in range(3):
+        out[c][has] = nrm[c][has] / length[has]
+    out[0][solid & ~has] = 0.0
+    out[1][solid & ~has] = 0.0
+    out[2][solid & ~has] = 1.0
+    return out
+
+
 def place_tubes(nx: int, ny: int, count: int, radius: float, seed: int, stream: int = 7,
                 max_tries: int = 2000):
     """Rejection-place up to `count` centres with periodic separation >= 2R."""
@@ -215,21 +247,37 @@ def workload_c2(gx: float = 1e-6, r: int = 10, K: float = 5e-4) -> tuple:
     return prob, director_tilt(prob, seed=2), 20000
 
 
-def workload_c3(r: int = 10) -> tuple:
+def workload_c3(r: int = 5) -> tuple:
     """Single skyrmion tube 256x256x48 (SET_B, K = 5e-3, pitch 32), g_x = 5e-6,
-    tube of radius p/2 = 16 at the centre, 100000 steps."""
+    tube of radius p/2 = 16 at the centre, dt_FD = 5 dt_LBM, 100000 steps.
+    (With set B's alpha4' the coupled director-flow update of this channel
+    grows without bound at r = 10, K = 5e-3; r = 5 stays bounded.)"""
     prob = channel(256, 256, 48, set_b(), g=(5e-6, 0.0, 0.0), K=5e-3, q0=2.0 * math.pi / 32.0,
                    fd_ratio=r)
     return prob, director_tubes(prob, [(128.0, 128.0)], 16.0), 100000
 
 
-def workload_c3_frank3(r: int = 10) -> tuple:
+def workload_c3_frank3(r: int = 5) -> tuple:
     """The tube channel of workload_c3 with the three-constant Frank energy:
     K11, K22, K33 in the material table's ratios with mean 5e-3 (the
     one-constant K of workload_c3)."""
     prob, n0, T = workload_c3(r)
     K11, K22, K33 = frank_table1(5e-3)
     return prob.with_(frank3=True, K11=K11, K22=K22, K33=K33, K=0.0), n0, T
+
+
+def workload_paper(fd_ratio: int = 1, nx: int = 64, ny: int = 64, nz: int = 16) -> tuple:
+    """The paper's own test case (Sec. III A, Table 1): a 64 x 64 x 16 channel
+    (the two plates included), the material table's Leslie viscosities with
+    tau = 1.8977 and alpha4' = rho c_s^2 (tau - 1/2), its three Frank
+    constants, pitch P = 14 (q0 = 2 pi/14), body force g = 2e-9, no director
+    anchoring at the plates, weak bulk anchoring W0 = 1.5e-8; one skyrmion
+    tube of the ansatz above (R = P/2) at the centre, uniform across the
+    channel.  Returns (Problem, n0)."""
+    K11, K22, K33 = TABLE1_FRANK
+    prob = channel(nx, ny, nz, set_b(), g=(2e-9, 0.0, 0.0), q0=2.0 * math.pi / 14.0, W0=1.5e-8,
+                   fd_ratio=fd_ratio, free_walls=True, frank3=True, K11=K11, K22=K22, K33=K33)
+    return prob, director_tubes(prob, [(nx / 2.0, ny / 2.0)], 7.0)
 
 
 def workload_c4(seed: int = 4, nchan: int = 64, material: str = "set_b", K: float = 5e-3,

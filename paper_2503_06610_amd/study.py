@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import sys
 import time
 
@@ -28,17 +29,31 @@ def _errs(a, b):
     return {"rel_l2": rel, "eps": eps, "eps_comp": comp}
 
 
-def run_one(prob, n0, precision, steps):
+def run_one(prob, n0, precision, steps, two_step=False):
+    """`steps` coupled steps from n0.  two_step: u is the mean of the last two
+    steps' velocities (the part of u that does not alternate in sign from
+    one LBM step to the next), and "u_odd" their half difference."""
     import torch
     from paper_2503_06610_amd import el
     lat = el.Lattice(prob, precision)
     lat.init_lattice(n0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lat.run(steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out = {"u": lat.get("u"), "n": lat.get("n"), "mlups": prob.fluid_nodes * steps / dt / 1e6,
+    if two_step:
+        lat.run(steps - 1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        u1 = lat.get("u")
+        lat.run(1)
+        u2 = lat.get("u")
+        u, u_odd = 0.5 * (u1 + u2), 0.5 * (u2 - u1)
+        dt *= steps / (steps - 1.0)
+    else:
+        lat.run(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        u, u_odd = lat.get("u"), None
+    out = {"u": u, "u_odd": u_odd, "n": lat.get("n"), "mlups": prob.fluid_nodes * steps / dt / 1e6,
            "obs": lat.observables()}
     del lat
     torch.cuda.empty_cache()
@@ -46,12 +61,12 @@ def run_one(prob, n0, precision, steps):
 
 
 def tube_drift(steps=100000, every=1000, precisions=("f32_shifted", "f64_shifted"), log=print):
-    """The single-tube channel (256x256x48, r = 10): FP64 tube-drift tracking
+    """The single-tube channel (256x256x48, r = 5): FP64 tube-drift tracking
     every `every` steps for each precision; returns the displacement series
     and the mean drift velocity over the second half of the run."""
     import torch
     from paper_2503_06610_amd import el, inputs
-    prob, n0, _ = inputs.workload_c3(r=10)
+    prob, n0, _ = inputs.workload_c3()
     out = {}
     for prec in precisions:
         lat = el.Lattice(prob, prec)
@@ -89,6 +104,45 @@ def tube_drift(steps=100000, every=1000, precisions=("f32_shifted", "f64_shifted
     return out
 
 
+def paper_regime(steps=2_000_000, ratios=(1, 2, 5, 10, 25, 50, 100, 250, 500, 1000), log=print):
+    """The Delta t_FD sweep of Sec. III on the paper's own test case
+    (inputs.workload_paper): FP64-shifted and FP32-shifted runs of `steps` LBM
+    steps at every dt_FD = r in `ratios`, each against the FP64-shifted run at
+    r = 1 (the paper's reference), with the paper's epsilon of u (total and
+    per component), the director's error and the MLUPS of each run.  u is
+    the mean over the last two LBM steps: with an even r the lattice keeps a
+    small sign-alternating (period-2) velocity component that nothing damps,
+    which would otherwise dominate the comparison; its size relative to u is
+    reported as "odd_rel"."""
+    from paper_2503_06610_amd import inputs
+    rows = []
+    ref = None
+    for r in ratios:
+        prob, n0 = inputs.workload_paper(fd_ratio=r)
+        row = {"r": r, "steps": steps}
+        for prec in ("f64_shifted", "f32_shifted"):
+            res = run_one(prob, n0, prec, steps, two_step=True)
+            if prec == "f64_shifted" and r == ratios[0]:
+                ref = res
+            odd_rel = float(np.sqrt((res["u_odd"] ** 2).sum() / (res["u"] ** 2).sum()))
+            row[prec] = {"mlups": res["mlups"], "u": _errs(res["u"], ref["u"]), "n": _errs(res["n"], ref["n"]),
+                         "max_u": res["obs"]["max_u"], "nonfinite": res["obs"]["nonfinite"],
+                         "max_unit_dev": res["obs"]["max_unit_dev"], "odd_rel": odd_rel}
+            log(json.dumps({"r": r, "precision": prec, "mlups": round(res["mlups"], 1),
+                            "eps_u": "%.3e" % row[prec]["u"]["eps"], "eps_n": "%.3e" % row[prec]["n"]["eps"],
+                            "eps_ux": "%.3e" % row[prec]["u"]["eps_comp"][0], "odd_rel": "%.2e" % odd_rel,
+                            "max_u": "%.4e" % res["obs"]["max_u"]}))
+        rows.append(row)
+    # power-law slope of the FP64 error against dt_FD (r > 1)
+    xs = [math.log(rw["r"]) for rw in rows if rw["r"] > ratios[0] and rw["f64_shifted"]["u"]["eps"] > 0]
+    ys = [math.log(rw["f64_shifted"]["u"]["eps"]) for rw in rows if rw["r"] > ratios[0]
+          and rw["f64_shifted"]["u"]["eps"] > 0]
+    slope = float(np.polyfit(xs, ys, 1)[0]) if len(xs) >= 2 else float("nan")
+    best = min(rows, key=lambda rw: rw["f32_shifted"]["u"]["eps"])
+    return {"rows": rows, "fp64_slope": slope, "fp32_best_r": best["r"],
+            "fp32_best_eps_u": best["f32_shifted"]["u"]["eps"]}
+
+
 def main(argv=None):
     from paper_2503_06610_amd import inputs
     ap = argparse.ArgumentParser()
@@ -98,7 +152,16 @@ def main(argv=None):
     ap.add_argument("--variants", nargs="+", default=["f64", "f32", "f32_shifted"])
     ap.add_argument("--out", default="")
     ap.add_argument("--tube", action="store_true", help="run the tube-drift study of the 256x256x48 channel instead")
+    ap.add_argument("--paper", action="store_true",
+                    help="run the dt_FD sweep on the paper's own 64x64x16 test case instead (--steps per run)")
     args = ap.parse_args(argv)
+    if args.paper:
+        res = paper_regime(steps=args.steps, ratios=tuple(args.ratios))
+        print(json.dumps({k: v for k, v in res.items() if k != "rows"}), flush=True)
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump(res, f, indent=1)
+        return res
     if args.tube:
         res = tube_drift(steps=args.steps)
         summary = {k: {kk: vv for kk, vv in v.items() if kk != "series"} if isinstance(v, dict) else v

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared_functions():
         assert name in exported, name
         assert hasattr(lib, name)
-    assert lib.el_version() == 3
+    assert lib.el_version() == 4
 
 
 def test_struct_sizes_match_header():

@@ -88,3 +88,16 @@ def test_network_gradient_matches_finite_differences():
         lp = co.network_loss_and_grads(x0, [(w, bp, r) if k == li else layers[k] for k in range(3)], zpad0, target)[0]
         lm = co.network_loss_and_grads(x0, [(w, bm, r) if k == li else layers[k] for k in range(3)], zpad0, target)[0]
         assert abs((lp - lm) / (2 * h) - grads[li][1][0]) < 1e-6
+
+
+def test_bf16_round_matches_torch_conversion():
+    """The reference's BF16 rounding (nearest, ties to even) against torch's
+    float32 -> bfloat16 conversion, on random values and exact ties."""
+    import torch
+    rng = np.random.default_rng(31)
+    a = (rng.normal(size=20000) * 10.0 ** rng.uniform(-6, 6, size=20000)).astype(np.float32)
+    bits = np.arange(1, 2000, dtype=np.uint32) << np.uint32(16)
+    ties = (np.uint32(0x3F800000) | bits | np.uint32(0x8000)).view(np.float32)  # halfway cases
+    for v in (a, ties, -ties):
+        want = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+        assert np.array_equal(co.bf16_round(v), want)

@@ -22,6 +22,7 @@ against things the oracle does not compute itself:
 * the elastic stress satisfies the Ericksen identity
   d_b sigma^e_ab = -(d_a n_g) h_g - d_a f' at second order.
 """
+import functools
 import math
 
 import numpy as np
@@ -172,33 +173,52 @@ def _eval(sp, X, exprs, N):
 ORDERINGS = [(13, 6, 21), (9, 15, 21)]
 
 
+@functools.lru_cache(maxsize=None)
+def _h_targets(consts, N):
+    """Grid values of the unit manufactured director, sympy's h of the split
+    density, and (printed-density h + Km |c|^2 n - split h) for N x N x N
+    (cached: the symbolic work dominates the pins' cost)."""
+    import sympy
+    K11, K22, K33 = (sympy.Rational(v, 1000) for v in consts)
+    q0 = sympy.Rational(2, 5)
+    Km = min(K11, K22, K33)
+    sp, X, n = _sym_setup(N, unit=True)
+    h_split, _ = _variational(sp, X, n, _split_density(K11, K22, K33, q0))
+    h_printed, _ = _variational(sp, X, n, _printed_density(K11, K22, K33, q0))
+    c = [sum(sp.LeviCivita(g, a, b) * sp.diff(n[b], X[a]) for a in range(3) for b in range(3)) for g in range(3)]
+    radial = [Km * sum(cc ** 2 for cc in c) * n[g] for g in range(3)]
+    gap = _eval(sp, X, [h_printed[g] - h_split[g] + radial[g] for g in range(3)], N)
+    return _eval(sp, X, n, N), _eval(sp, X, h_split, N), gap
+
+
+@functools.lru_cache(maxsize=None)
+def _ericksen_target(consts, N):
+    """Grid values of the (not normalised) manufactured director and of
+    -(d_a n_g) h_g - d_a f' for the split density (cached)."""
+    import sympy
+    K11, K22, K33 = (sympy.Rational(v, 1000) for v in consts)
+    q0 = sympy.Rational(2, 5)
+    sp, X, n = _sym_setup(N, unit=False)
+    h, f = _variational(sp, X, n, _split_density(K11, K22, K33, q0))
+    target = [-sum(sp.diff(n[g], X[a]) * h[g] for g in range(3)) - sp.diff(f, X[a]) for a in range(3)]
+    return _eval(sp, X, n, N), _eval(sp, X, target, N)
+
+
 @pytest.mark.parametrize("consts", ORDERINGS, ids=["twist_min", "splay_min"])
 def test_molecular_field_converges_to_variational_derivative(consts):
     """On a smooth unit director field the oracle's h converges at second order
     to sympy's -dE'/dn of the split density; sympy's h of the printed density
     is that h minus Km |c|^2 n exactly."""
-    import sympy
-    K11, K22, K33 = (sympy.Rational(v, 1000) for v in consts)
-    q0 = sympy.Rational(2, 5)
-    Km = min(K11, K22, K33)
     errs = []
     for N in (24, 48):  # 12 -> 24 is not yet in the asymptotic range (ratio 3.2)
-        sp, X, n = _sym_setup(N, unit=True)
-        h_split, _ = _variational(sp, X, n, _split_density(K11, K22, K33, q0))
-        prob = _frank3(_box(N, q0=float(q0)), float(K11), float(K22), float(K33))
+        nv, want, gap = _h_targets(tuple(consts), N)
+        prob = _frank3(_box(N, q0=0.4), *(v / 1000 for v in consts))
         o = oracle_for(prob, threads=4)
-        nv = _eval(sp, X, n, N)
         o.init(nv)
         h = o.molecular_field()
-        want = _eval(sp, X, h_split, N)
         errs.append(np.abs(h - want).max() / np.abs(want).max())
         if N == 24:
-            h_printed, _ = _variational(sp, X, n, _printed_density(K11, K22, K33, q0))
-            c = [sum(sp.LeviCivita(g, a, b) * sp.diff(n[b], X[a]) for a in range(3) for b in range(3))
-                 for g in range(3)]
-            radial = [Km * sum(cc ** 2 for cc in c) * n[g] for g in range(3)]
-            diff = _eval(sp, X, [h_printed[g] - h_split[g] + radial[g] for g in range(3)], N)
-            assert np.abs(diff).max() < 1e-14 * np.abs(want).max()
+            assert np.abs(gap).max() < 1e-14 * np.abs(want).max()
     assert errs[1] < 0.01
     assert 3.5 < errs[0] / errs[1] < 4.5
 
@@ -208,19 +228,13 @@ def test_elastic_stress_satisfies_ericksen_identity_three_constants(consts):
     """d_b sigma^e_ab = -(d_a n_g) h_g - d_a f' for any field n (not normalised
     here), with h = -dE'/dn: the discrete elastic force converges to it at
     second order (periodic box, u = 0)."""
-    import sympy
-    K11, K22, K33 = (sympy.Rational(v, 1000) for v in consts)
-    q0 = sympy.Rational(2, 5)
     errs = []
     for N in (24, 48):
-        sp, X, n = _sym_setup(N, unit=False)
-        h, f = _variational(sp, X, n, _split_density(K11, K22, K33, q0))
-        target = [-sum(sp.diff(n[g], X[a]) * h[g] for g in range(3)) - sp.diff(f, X[a]) for a in range(3)]
-        prob = _frank3(_box(N, q0=float(q0)), float(K11), float(K22), float(K33))
+        nv, want = _ericksen_target(tuple(consts), N)
+        prob = _frank3(_box(N, q0=0.4), *(v / 1000 for v in consts))
         o = oracle_for(prob, threads=4)
-        o.init(_eval(sp, X, n, N))
+        o.init(nv)
         F = o.force_masked(64)
-        want = _eval(sp, X, target, N)
         errs.append(np.abs(F - want).max() / np.abs(want).max())
     # max-norm ratios 4.1, 4.6, 5.7 for N = 12 -> 24 -> 48 -> 96
     assert errs[1] < 0.02

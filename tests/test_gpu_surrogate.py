@@ -214,10 +214,76 @@ def test_mse_and_adam_match_reference():
     assert np.array_equal(wtn, np.transpose(wfn.reshape(32, 27, 32)[:, ::-1, :], (2, 1, 0)))
 
 
+def _poiseuille_over_v0(prob, V0):
+    """u_P(z)/V0 at the fluid layers, float32 as the kernels evaluate it: the
+    coefficient g/(2 nu V0) rounded once, nu = (tau - 1/2)/3 + alpha4'/2."""
+    nu = (prob.tau - 0.5) / 3.0 + 0.5 * prob.alpha4p
+    c = np.float32(prob.g[0] / (2.0 * nu) / float(np.float32(V0)))  # V0 crosses the ABI as a float
+    z = np.arange(1, prob.nz - 1, dtype=np.float32)
+    return c * (z - np.float32(0.5)) * (np.float32(prob.nz) - np.float32(1.5) - z)
+
+
+@pytest.mark.parametrize("precision", ["f32_shifted", "f64"])
+def test_input_velocity_and_target_glue_elementwise(precision):
+    """el_nn_input, el_nn_velocity and el_nn_target against their definitions
+    written out in numpy, element by element, for the second of three
+    samples: input channels (n_x, n_y, n_z, u_P/V0, 0, 0, 0, 0) rounded to
+    BF16 with halo planes (0, 0, 1, 0, ...); u = V0 (res + u_P/V0 x-hat);
+    res = u/V0 - u_P/V0 x-hat."""
+    import torch
+    from paper_2503_06610_amd import surrogate as sg
+    lib = _lib()
+    prob = inputs.channel(13, 6, 9, inputs.set_b(), g=(3e-6, 0.0, 0.0), K=5e-3, fd_ratio=2)
+    p = el.make_params(prob, precision)
+    dt = torch.float64 if precision == "f64" else torch.float32
+    nzf, N, ns, smp, V0 = prob.nzf, prob.fluid_nodes, 3, 1, sg.V0
+    n = inputs.director_tubes(prob, [(6.0, 3.0)], 2.5)
+    nt = torch.as_tensor(n).to(dt).cuda().contiguous()
+    per = (nzf + 2) * prob.ny * prob.nx
+    act = torch.full((ns * per * 8,), 7.0, dtype=torch.bfloat16, device="cuda")
+    assert lib.el_nn_input(C.byref(p), _vp(nt), _vp(act), smp, ns, C.c_float(V0), None) == 0
+    got = act.to(torch.float64).cpu().numpy().reshape(ns, nzf + 2, prob.ny, prob.nx, 8)
+    up = _poiseuille_over_v0(prob, V0)
+    want = np.zeros((nzf + 2, prob.ny, prob.nx, 8))
+    want[0, :, :, 2] = want[-1, :, :, 2] = 1.0
+    want[1:-1, :, :, :3] = np.transpose(nt.double().cpu().numpy(), (1, 2, 3, 0))
+    want[1:-1, :, :, 3] = up[:, None, None]
+    assert np.array_equal(got[smp], co.bf16_round(want))
+    assert np.all(got[0] == 7.0) and np.all(got[2] == 7.0)  # other samples untouched
+    # velocity from a network output, and the target back from that velocity
+    res = RNG.normal(size=(3, ns * N)).astype(np.float32)
+    rt = torch.as_tensor(res).cuda()
+    u = torch.zeros(prob.shape(3), dtype=dt, device="cuda")
+    assert lib.el_nn_velocity(C.byref(p), _vp(rt), smp, ns, C.c_float(V0), _vp(u), None) == 0
+    r = res[:, smp * N:(smp + 1) * N].reshape(3, nzf, prob.ny, prob.nx)
+    uw = np.zeros_like(r)
+    uw[0] = np.float32(V0) * (r[0] + up[:, None, None])
+    uw[1:] = np.float32(V0) * r[1:]
+    ug = u.cpu().numpy()
+    assert np.allclose(ug, uw.astype(ug.dtype), rtol=2e-7, atol=0.0)
+    tgt = torch.full((3, ns * N), 5.0, dtype=torch.float32, device="cuda")
+    assert lib.el_nn_target(C.byref(p), _vp(u), smp, ns, C.c_float(V0), _vp(tgt), None) == 0
+    tg = tgt.cpu().numpy()
+    tw = ug.astype(np.float32) * np.float32(1.0 / np.float32(V0))
+    tw[0] -= up[:, None, None]
+    assert np.allclose(tg[:, smp * N:(smp + 1) * N], tw.reshape(3, N), rtol=2e-6, atol=1e-6 * np.abs(tw).max())
+    assert np.all(tg[:, :smp * N] == 5.0) and np.all(tg[:, (smp + 1) * N:] == 5.0)
+    # the round trip recovers the network output
+    assert np.allclose(tg[:, smp * N:(smp + 1) * N], res[:, smp * N:(smp + 1) * N], rtol=0,
+                       atol=1e-5 * np.abs(res).max() + 1e-6 * np.abs(up).max())
+
+
 def test_network_weight_gradients_match_reference():
     """Forward + backward of the 4-layer network through the C ABI against the
-    FP64 reference with the same BF16 weights and input (the GPU keeps BF16
-    activations and gradients, so agreement is to BF16 accuracy)."""
+    FP64 reference with the same BF16 weights and input.  The GPU keeps the
+    hidden activations and the activation gradients in BF16 (round to nearest
+    even) and accumulates in FP32; the reference rounds the same quantities to
+    BF16 at the same points and accumulates in FP64.  What remains is FP32
+    against FP64 accumulation (relative ~1e-6) and the BF16 roundings it
+    flips where a value lies within that distance of a rounding boundary:
+    about 1e-6/2^-8 = 2.6e-4 of the stored values, each moved by one BF16 ulp
+    (2^-8 relative), so about sqrt(2.6e-4) 2^-8 = 6e-5 relative per stored
+    field, compounded over the four layers; bound 1e-3 on every gradient."""
     import torch
     from paper_2503_06610_amd import surrogate as sg
     net = sg.Surrogate(seed=3)
@@ -232,30 +298,28 @@ def test_network_weight_gradients_match_reference():
     for li, (cin, cout, cout_real, relu) in enumerate(sg.LAYERS):
         wf = net.wf[li].to(torch.float64).cpu().numpy().reshape(cout, 27, cin)[:cout_real, :, :sg.REAL_CIN[li]]
         layers.append((wf, net.b[li].cpu().double().numpy()[:cout_real], relu))
-    rloss, rgrads = co.network_loss_and_grads(x, layers, zpad, tgt)
+    rloss, rgrads = co.network_loss_and_grads(x, layers, zpad, tgt, store=co.bf16_round)
     _say(f"loss gpu {loss:.6e} ref {rloss:.6e}")
-    assert abs(loss - rloss) < 2e-2 * rloss
+    assert abs(loss - rloss) < 1e-5 * rloss
     for li, (cin, cout, cout_real, relu) in enumerate(sg.LAYERS):
         g = net.gw[li].cpu().double().numpy().reshape(cout, 27, cin)[:cout_real, :, :sg.REAL_CIN[li]]
         r = rgrads[li][0]
         rel = np.linalg.norm(g - r) / np.linalg.norm(r)
-        cos = float((g * r).sum() / np.linalg.norm(g) / np.linalg.norm(r))
-        _say(f"layer {li}: rel-L2 {rel:.3e} cos {cos:.6f}")
-        # BF16 activations and gradients, and ReLU masks taken from BF16 values
-        assert rel < 6e-2 and cos > 0.998
         gb = net.gb[li].cpu().double().numpy()[:cout_real]
-        assert np.linalg.norm(gb - rgrads[li][1]) <= 6e-2 * np.linalg.norm(rgrads[li][1])
+        relb = np.linalg.norm(gb - rgrads[li][1]) / np.linalg.norm(rgrads[li][1])
+        _say(f"layer {li}: weight gradient rel-L2 {rel:.3e}, bias gradient rel-L2 {relb:.3e}")
+        assert rel < 1e-3 and relb < 1e-3
 
 
 def test_training_and_warm_start_on_solver_data():
     """A small surrogate trained on solver pairs lowers its loss, starts a
     held-out channel closer to the converged flow than the analytic Poiseuille
-    profile does, and is still closer than a cold start after 30 steps.  For
-    this 32-pair network the remaining error sits mostly in the slowest
-    viscous mode, whose amplitude it barely reduces: from about 60 steps on
-    every start decays at the same rate, and the step counts to 1e-4 (printed)
-    agree to within a check interval.  The step savings of a network trained
-    at full size are measured by the warm-start study."""
+    profile does, and reaches 1e-4 of the converged flow in fewer LBM steps
+    than a cold start (errors of the settled velocity, the mean of two
+    consecutive steps: the FD force updates excite the lattice's
+    sign-alternating velocity modes whatever the start, and they decay
+    slowly).  The step savings of a network trained at full size are
+    measured by the warm-start study."""
     import torch
     from paper_2503_06610_amd import surrogate as sg
     nx, ny, nz = 32, 32, 16
@@ -269,8 +333,8 @@ def test_training_and_warm_start_on_solver_data():
     prob, n0 = sg.sample_problem(u01, nx, ny, nz)
     ref = el.Lattice(prob, "f32_shifted", freeze_director=True)
     ref.init_lattice(n0)
-    ref.run(3000)
-    u_ref = ref.get("u")
+    ref.run(5999)
+    u_ref = sg.settled_velocity(ref).double().cpu().numpy()
     results = {}
     for mode in ("cold", "poiseuille", "net"):
         lat = el.Lattice(prob, "f32_shifted", freeze_director=True)
@@ -280,10 +344,10 @@ def test_training_and_warm_start_on_solver_data():
         elif mode == "net":
             net.warm_start(lat)
         e0 = lat.error_norms(lat.u, u_ref)["rel_l2"]
-        lat.run(30)
-        e30 = lat.error_norms(lat.u, u_ref)["rel_l2"]
         steps, _, err = sg.steps_to_error(lat, u_ref, 1e-4, check_every=10)
-        results[mode] = (e0, e30, 30 + steps)
-    _say(f"warm start (error at 0 and 30 steps, steps to 1e-4): {results}")
+        results[mode] = (e0, steps, err)
+    _say(f"warm start (error at 0 steps, steps to 1e-4 of the settled velocity, final error): {results}")
     assert results["net"][0] < results["poiseuille"][0] < results["cold"][0]
-    assert results["net"][1] < 0.85 * results["cold"][1]
+    # equal final error (1e-4), fewer steps from the trained start
+    assert max(r[2] for r in results.values()) <= 1e-4
+    assert results["net"][1] < results["cold"][1]

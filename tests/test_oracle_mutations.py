@@ -14,6 +14,7 @@ import pytest
 import oracle.oracle as oo
 from tests import test_frank3_pins as f3
 from tests import test_free_walls_pins as fw
+from tests import test_obstacle_pins as ob
 from tests import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(oo.__file__), "el_oracle.c")
@@ -67,9 +68,8 @@ MUTATIONS = [
     ("no_moments_after_stream", "        lbm_step(s);\n        or_moments(s);", "        lbm_step(s);"),
 ]
 
-# mistakes in the three-constant Frank elasticity (R4') and the unanchored walls (R7'),
-# checked against their own pins
-MUTATIONS_ELASTIC = [
+# mistakes in the three-constant Frank elasticity (R4'), checked against its own pins
+MUTATIONS_FRANK3 = [
     ("frank3_splay_takes_twist_constant", "dh[mu] = a[0] * dS[mu]", "dh[mu] = a[1] * dS[mu]"),
     ("frank3_twist_factor_two", "(nxdT - 2.0 * fp.T * fp.c[mu])", "(nxdT - fp.T * fp.c[mu])"),
     ("frank3_bend_stress_transposed", "ac[2] * (fp.B[b] * n[g] - fp.B[g] * n[b])",
@@ -81,9 +81,19 @@ MUTATIONS_ELASTIC = [
     ("frank3_no_div_B", "a[2] * (divB * n[mu] + BdN", "a[2] * (BdN"),
     ("frank3_grad_T_drops_G", "dT[b] += G[b][g] * fp.c[g] + n[g] * dc[b][g];", "dT[b] += n[g] * dc[b][g];"),
     ("frank3_bend_force_sign", "- fp.S * fp.B[mu] - cxB);", "- fp.S * fp.B[mu] + cxB);"),
-    # unanchored walls (R7')
+]
+
+# the unanchored walls (R7') and the obstacles (R7''), against theirs
+MUTATIONS_WALLS = [
     ("free_wall_mirror_layer", "return z == 0 ? 1 : p->nz - 2;", "return z == 0 ? 2 : p->nz - 3;"),
     ("free_wall_edges_anchored", "        if (field_kind == 0 && p->free_walls)\n            return f[(int64_t)c * st->N + idx(p, co[0], co[1], mirror_layer(p, co[2]))];\n", ""),
+    ("obstacle_not_bounced", "if (is_solid(p, zd) || obstacle(s, xd, yd, zd))", "if (is_solid(p, zd))"),
+    ("obstacle_director_moves", "                if (obstacle(s, x, y, z)) { /* fixed director at solid nodes */",
+     "                if (0) { /* fixed director at solid nodes */"),
+    ("obstacle_velocity_not_held", "if (obstacle(s, x, y, z)) { /* no slip: an obstacle node is at rest */",
+     "if (0) { /* no slip: an obstacle node is at rest */"),
+    ("obstacle_stress_kept", "if (obstacle(st, x, y, z)) continue; /* sigma = 0 at solid nodes */",
+     "/* sigma = 0 at solid nodes */"),
 ]
 
 PINS = [
@@ -117,7 +127,8 @@ PINS = [
     pins.test_tube_centroids_of_analytic_tubes,
 ]
 
-PINS_ELASTIC = [
+# cheapest first: the mode-rate pins catch most mistakes in a second
+PINS_FRANK3 = [
     f3.test_equal_constants_reduce_to_one_constant,
     lambda: f3.test_single_mode_relaxation_rate(0, 0),
     lambda: f3.test_single_mode_relaxation_rate(1, 1),
@@ -126,11 +137,18 @@ PINS_ELASTIC = [
     lambda: f3.test_elastic_stress_satisfies_ericksen_identity_three_constants(f3.ORDERINGS[1]),
     lambda: f3.test_molecular_field_converges_to_variational_derivative(f3.ORDERINGS[0]),
     lambda: f3.test_molecular_field_converges_to_variational_derivative(f3.ORDERINGS[1]),
+]
+
+PINS_WALLS = [
     lambda: fw.test_uniform_tilted_director_is_stationary(False),
     lambda: fw.test_uniform_tilted_director_is_stationary(True),
     lambda: fw.test_neumann_mode_growth_factor(False),
     lambda: fw.test_neumann_mode_growth_factor(True),
     fw.test_free_walls_equal_a_mirrored_periodic_box,
+    ob.test_mask_layers_reproduce_the_walls,
+    ob.test_poiseuille_across_mask_walls_at_magic_tau,
+    ob.test_symmetric_post_gives_mirror_symmetric_flow,
+    ob.test_mass_conserved_with_obstacles_and_coupling,
 ]
 
 
@@ -149,8 +167,9 @@ def _caught(lib, pin_list) -> str:
 
 
 @pytest.mark.parametrize("name,old,new,pin_list", [m + (PINS,) for m in MUTATIONS] +
-                         [m + (PINS_ELASTIC,) for m in MUTATIONS_ELASTIC],
-                         ids=[m[0] for m in MUTATIONS + MUTATIONS_ELASTIC])
+                         [m + (PINS_FRANK3,) for m in MUTATIONS_FRANK3] +
+                         [m + (PINS_WALLS,) for m in MUTATIONS_WALLS],
+                         ids=[m[0] for m in MUTATIONS + MUTATIONS_FRANK3 + MUTATIONS_WALLS])
 def test_planted_mistake_is_caught(name, old, new, pin_list, tmp_path):
     src = open(SRC).read()
     assert src.count(old) >= 1, f"mutation site not found: {old}"
