@@ -336,6 +336,8 @@ class Lattice:
         FP64 reference (numpy or tensor) of the same shape."""
         import torch
         at = a.contiguous()
+        if at.dtype != self.dtype:
+            raise TypeError(f"error_norms: field is {at.dtype}, the lattice computes in {self.dtype}")
         ncomp = at.shape[0]
         rt = torch.as_tensor(ref, dtype=torch.float64).to(at.device).contiguous()
         out = torch.zeros(10, dtype=torch.float64, device=at.device)

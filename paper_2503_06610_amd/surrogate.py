@@ -206,31 +206,38 @@ def sample_problem(rng_u, nx=64, ny=64, nz=32):
     return prob, inputs.director_tubes(prob, centres, 16.0)
 
 
+def _window_mean(b, lats, w):
+    """Mean of each lattice's u over the next w steps of batch b."""
+    import torch
+    acc = None
+    for _ in range(w):
+        b.step(1)
+        b.moments()
+        torch.cuda.synchronize()
+        us = [lat.u.double() for lat in lats]
+        acc = us if acc is None else [a + u for a, u in zip(acc, us)]
+    return [a / w for a in acc]
+
+
 def relax(lats, steps, capture=True):
     """Advance frozen-director lattices with the batched runner, leaving in
-    each lattice's u its settled velocity (the mean of the last two steps,
-    see settled_velocity); returns the largest relative change of u over the
-    last 100 steps (an even count, so the period-2 component cancels)."""
+    each lattice's u its settled velocity (the mean over the last
+    settle_window steps, see settled_velocity); returns the largest relative
+    change of that mean over the last 100 steps."""
     import torch
+    w = settle_window(lats[0].prob)
+    assert all(settle_window(lat.prob) == w for lat in lats) and steps >= 100 + w
     b = el.Batch(lats)
     if capture:
         b.capture()
-    b.step(steps - 101)
-    b.moments()
-    torch.cuda.synchronize()
-    u_prev = [lat.u.clone() for lat in lats]
-    b.step(100)
-    b.moments()
+    b.step(steps - 100 - w)
+    u_prev = _window_mean(b, lats, w)
+    b.step(100 - w)
+    u_last = _window_mean(b, lats, w)
     b.sync()
-    torch.cuda.synchronize()
-    u_last = [lat.u.clone() for lat in lats]
     change = max(float((u - up).norm() / u.norm()) for u, up in zip(u_last, u_prev))
-    b.step(1)
-    b.moments()
-    b.sync()
-    torch.cuda.synchronize()
     for lat, u in zip(lats, u_last):
-        lat.u.copy_(0.5 * (u + lat.u))
+        lat.u.copy_(u)
     b.close()
     return change
 
@@ -307,27 +314,43 @@ def train(net, data, epochs, batch=8, log=print, seed=0):
     return history
 
 
+def settle_window(prob):
+    """Steps averaged into the settled velocity: two director updates, 2 dt_FD.
+    The LBM carries a sign-alternating (period-2) velocity component that the
+    FD force updates excite whatever the start; it is not damped at an even
+    dt_FD and only slowly at an odd one, where it also flips the sign of its
+    contribution to the held force at every update and so drives a period
+    2 dt_FD response.  A mean over 2 dt_FD consecutive steps (an even count
+    that spans whole update cycles) cancels both."""
+    return 2 * max(1, int(prob.fd_ratio))
+
+
 def settled_velocity(lat):
-    """Mean of u over the current and the next LBM step (advances the lattice
-    by one step): the flow without the lattice's sign-alternating (period-2)
-    component, which the FD force updates excite and which decays slowly (odd
-    dt_FD) or not at all (even dt_FD) whatever the start."""
-    u1 = lat.u.clone()
-    lat.run(1)
-    return 0.5 * (u1 + lat.u)
+    """Mean of u over the current step and the next settle_window - 1 LBM
+    steps (advances the lattice by that many): the flow without the
+    lattice's sign-alternating component and its response."""
+    w = settle_window(lat.prob)
+    acc = lat.u.double().clone()
+    for _ in range(w - 1):
+        lat.run(1)
+        acc += lat.u.double()
+    return (acc / w).to(lat.u.dtype)
 
 
 def steps_to_error(lat, u_ref, tol, check_every=100, max_steps=40000):
     """LBM steps (frozen director) until rel-L2 of the settled velocity
     (settled_velocity) against u_ref is <= tol; also the wall time of those
-    steps."""
+    steps.  check_every is rounded up to a multiple of the settling window;
+    a check at step s averages steps s - window + 1 .. s."""
     import torch
+    w = settle_window(lat.prob)
+    check_every = -(-max(check_every, w) // w) * w
     ref = torch.as_tensor(u_ref, dtype=torch.float64, device=lat.u.device)
     err = lat.error_norms(lat.u, ref)["rel_l2"]
     steps = 0
     t0 = time.perf_counter()
     while err > tol and steps < max_steps:
-        lat.run(check_every - 1)
+        lat.run(check_every - w + 1)
         err = lat.error_norms(settled_velocity(lat), ref)["rel_l2"]
         steps += check_every
     torch.cuda.synchronize()

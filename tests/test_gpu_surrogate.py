@@ -315,11 +315,12 @@ def test_training_and_warm_start_on_solver_data():
     """A small surrogate trained on solver pairs lowers its loss, starts a
     held-out channel closer to the converged flow than the analytic Poiseuille
     profile does, and reaches 1e-4 of the converged flow in fewer LBM steps
-    than a cold start (errors of the settled velocity, the mean of two
-    consecutive steps: the FD force updates excite the lattice's
-    sign-alternating velocity modes whatever the start, and they decay
-    slowly).  The step savings of a network trained at full size are
-    measured by the warm-start study."""
+    than a cold start.  Errors are those of the settled velocity, the mean
+    over two director updates (2 dt_FD steps): the FD force updates excite a
+    sign-alternating lattice mode of a few percent of u whatever the start,
+    which at this odd dt_FD decays over thousands of steps and drives a
+    period-2 dt_FD response; the window cancels both.  The step savings of a
+    network trained at full size are measured by the warm-start study."""
     import torch
     from paper_2503_06610_amd import surrogate as sg
     nx, ny, nz = 32, 32, 16
