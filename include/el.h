@@ -229,13 +229,12 @@ size_t el_buffer_bytes(const el_params* p, int32_t which);
  * them without bound (Table-1 viscosity ratios: alpha4' below the bound grows
  * within a few thousand steps, above it decays), while over an even number of
  * steps the kicks cancel.  The paper's split of alpha4 between the LBM and
- * the force (alpha4' = rho c_s^2 (tau - 1/2)) passes it.  Passing does not
- * guarantee long runs: with that alpha4' the coupled director and flow
- * update can still grow when the force is held long against a stiff director
- * (a 32x32x48 tube channel at tau = 1.8977 grew at r = 10 with K = 5e-3 and
- * 2.5e-3, not with K = 1e-3 or at r <= 5), and an even r leaves a small
- * sign-alternating velocity component undamped.  Watch el_obs.nonfinite and
- * max_u. */
+ * the force (alpha4' = 2 rho c_s^2 (tau - 1/2), half of alpha4 each) passes
+ * it.  Passing does not guarantee long runs: the coupled director and flow
+ * update can still grow or wander when the force is held long against a
+ * stiff director (a 32x32x48 tube channel with K = 5e-3 at r = 10), and an
+ * even r leaves a small sign-alternating velocity component undamped.  Watch
+ * el_obs.nonfinite and max_u. */
 int el_validate(const el_params* p);
 
 /* Initialisation (Sec. II D, first step): q = rest state (0 when shifted,
@@ -512,7 +511,9 @@ int el_nn_conv_backward_data(const el_nn_vol* v, int32_t cin, int32_t cout, cons
 size_t el_nn_work_bytes(const el_nn_vol* v, int32_t cin, int32_t cout);
 
 /* dw[co][tap][ci] = sum_v dy[v][co] x[v + d_tap][ci] and db[co] = sum_v dy[v][co]
- * (FP32, summed over fixed voxel chunks in a fixed order: deterministic).
+ * (FP32; partial sums over fixed blocks, added in a fixed order:
+ * deterministic).  When nx is a multiple of 32 a block sums 16 whole x-rows of
+ * one (sample, z), otherwise 1024 consecutive voxels.
  * (cin, cout) in {(8, 32), (32, 32), (32, 16)}. */
 int el_nn_conv_backward_weight(const el_nn_vol* v, int32_t cin, int32_t cout, const void* x, const void* dy,
                                void* work, size_t work_bytes, float* dw, float* db, void* stream);

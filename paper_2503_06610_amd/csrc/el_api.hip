@@ -70,8 +70,9 @@ int stability_checks(const el_params* p)
     // per |D|^2 is bounded below by alpha4' + min(0, alpha1 + c, c/2).  Found
     // with the FP64 oracle: odd r grows without bound below that bound and
     // decays above it (Table-1 ratios at tau = 0.8: alpha4' = 0.05 grows, 0.08
-    // decays, against 0.071; at tau = 1.8977 alpha4' = 0 grows for r = 1, 3, 5
-    // and alpha4' = 0.4659 decays); even r stays bounded either way.
+    // decays, against 0.071; Table-1 values at tau = 1.8977 with alpha4' = 0
+    // grow for r = 1, 3, 5, and with alpha4' = 0.4659 at tau = 1.19885 decay);
+    // even r stays bounded either way.
     if ((p->fd_ratio % 2) == 1 && coupling(p)) {
         const double g2 = p->alpha[2] + p->alpha[1];
         const double c = p->alpha[4] + p->alpha[5] - g2 * g2 / gamma1;

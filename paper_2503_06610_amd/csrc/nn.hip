@@ -134,7 +134,39 @@ void launch_wgrad(const VolGeom& g, hipStream_t st, int nb, const __bf16* x, con
 
 int wgrad_blocks(const VolGeom& g) { return (int)((g.n_all + NN_CHUNK - 1) / NN_CHUNK); }
 
+// The row kernel (k_conv_wgrad_rows) needs whole 32-voxel k-steps per row, at
+// most two x staging units and one dy unit per thread and row, and its rows
+// in LDS: nx in {32, 64} for 32 input channels.
+bool wgrad_by_rows(const VolGeom& g, int cin, int cout)
+{
+    return g.nx % 32 == 0 && 3 * (cin / 8) * (g.nx / 2) <= 512 && (cout / 8) * (g.nx / 2) <= 256 &&
+           el::nn::wrow_lds_bytes(cin, cout, g.nx) <= 80 * 1024;
+}
+
+int wgrad_rows_blocks(const VolGeom& g)
+{
+    return g.nsamples * g.nzf * ((g.ny + el::nn::WR_ROWS - 1) / el::nn::WR_ROWS);
+}
+
+template <int CIN, int MT>
+void launch_wgrad_rows(const VolGeom& g, hipStream_t st, const __bf16* x, const __bf16* dy, float* part)
+{
+    const int lds = el::nn::wrow_lds_bytes(CIN, 16 * MT, g.nx);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&el::nn::k_conv_wgrad_rows<CIN, MT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipLaunchKernelGGL((el::nn::k_conv_wgrad_rows<CIN, MT>), dim3(wgrad_rows_blocks(g)), dim3(256), lds, st, x, dy,
+                       part, g);
+}
+
 int pitch_of(int cin) { return ((27 * cin + 15) / 16) * 16; }
+
+// Partial weight-gradient rows: one per block of whichever kernel runs (the
+// buffer holds the larger count), then the bias partials (one per NN_CHUNK).
+size_t wgrad_part_floats(const VolGeom& g, int cin, int cout)
+{
+    const int nb = std::max(wgrad_blocks(g), wgrad_rows_blocks(g));
+    return (size_t)nb * (size_t)cout * (size_t)pitch_of(cin);
+}
 
 // g_x / (2 nu V0): the Poiseuille velocity is this times (z - 1/2)(nz - 3/2 - z) V0,
 // with nu = (tau - 1/2)/3 + alpha4'/2 (rho = 1): the LBM viscosity plus the
@@ -231,7 +263,7 @@ size_t el_nn_work_bytes(const el_nn_vol* vol, int32_t cin, int32_t cout)
 {
     VolGeom g;
     if (vol_of(vol, &g) != EL_OK) return 0;
-    return (size_t)wgrad_blocks(g) * (size_t)cout * (size_t)(pitch_of(cin) + 1) * sizeof(float);
+    return (wgrad_part_floats(g, cin, cout) + (size_t)wgrad_blocks(g) * (size_t)cout) * sizeof(float);
 }
 
 int el_nn_conv_backward_weight(const el_nn_vol* vol, int32_t cin, int32_t cout, const void* x, const void* dy,
@@ -244,25 +276,36 @@ int el_nn_conv_backward_weight(const el_nn_vol* vol, int32_t cin, int32_t cout, 
     if (work_bytes < el_nn_work_bytes(vol, cin, cout)) return fail(EL_ENOMEM, "work buffer too small");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int nb = wgrad_blocks(g);
+    const bool rows = wgrad_by_rows(g, cin, cout);
+    const int nbw = rows ? wgrad_rows_blocks(g) : nb;
     float* part = static_cast<float*>(work);
-    float* bpart = part + (size_t)nb * cout * pitch_of(cin);
+    float* bpart = part + wgrad_part_floats(g, cin, cout);
     const __bf16* X = static_cast<const __bf16*>(x);
     const __bf16* DY = static_cast<const __bf16*>(dy);
     if (cin == 8 && cout == 32) {
-        launch_wgrad<8, 2>(g, st, nb, X, DY, part);
+        if (rows)
+            launch_wgrad_rows<8, 2>(g, st, X, DY, part);
+        else
+            launch_wgrad<8, 2>(g, st, nb, X, DY, part);
         hipLaunchKernelGGL((el::nn::k_bias_grad<32>), dim3(nb), dim3(256), 0, st, DY, bpart, g, NN_CHUNK);
     } else if (cin == 32 && cout == 32) {
-        launch_wgrad<32, 2>(g, st, nb, X, DY, part);
+        if (rows)
+            launch_wgrad_rows<32, 2>(g, st, X, DY, part);
+        else
+            launch_wgrad<32, 2>(g, st, nb, X, DY, part);
         hipLaunchKernelGGL((el::nn::k_bias_grad<32>), dim3(nb), dim3(256), 0, st, DY, bpart, g, NN_CHUNK);
     } else if (cin == 32 && cout == 16) {
-        launch_wgrad<32, 1>(g, st, nb, X, DY, part);
+        if (rows)
+            launch_wgrad_rows<32, 1>(g, st, X, DY, part);
+        else
+            launch_wgrad<32, 1>(g, st, nb, X, DY, part);
         hipLaunchKernelGGL((el::nn::k_bias_grad<16>), dim3(nb), dim3(256), 0, st, DY, bpart, g, NN_CHUNK);
     } else {
         return fail(EL_EINVAL, "unsupported weight gradient %d -> %d", cin, cout);
     }
     const int nw = cout * 27 * cin;
     hipLaunchKernelGGL(el::nn::k_sum_partials, dim3((nw + 15) / 16), dim3(256), 0, st,
-                       static_cast<const float*>(part), nb, cout, pitch_of(cin), 27 * cin, dw);
+                       static_cast<const float*>(part), nbw, cout, pitch_of(cin), 27 * cin, dw);
     hipLaunchKernelGGL(el::nn::k_sum_partials, dim3((cout + 15) / 16), dim3(256), 0, st, static_cast<const float*>(bpart), nb, 1,
                        cout, cout, db);
     return check_launch("weight-gradient kernels");

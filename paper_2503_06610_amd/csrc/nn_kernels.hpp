@@ -897,6 +897,230 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const __bf16* __restrict__ x
     }
 }
 
+// Weight gradient by rows.  dW[co][tap][ci] = sum_v dy[v][co] x[v + d_tap][ci]
+// is summed over whole x-rows, so the x shift of a tap can move to dy: over a
+// periodic row, sum_w dy[w][co] x[w + tx][ci] = sum_w dy[w - tx][co] x[w][ci].
+// A block owns WR_ROWS consecutive rows y of one (sample, z) and walks them in
+// y order.  In LDS it keeps the x rows at (y + ty, z + tz), ty, tz in -1..1,
+// transposed (channel-major, voxels along a row: an MFMA fragment is 16
+// contiguous bytes) in a ring of four rows over y, and the dy row transposed
+// with one wrapped voxel at each end; the A fragment of dy shifted by tx = +-1
+// is cut from two 16-byte reads with byte alignment.  The GEMM per row: M =
+// output channels (16-row tiles), N = (slot (tz, ty), input channel) columns,
+// K = the row's voxels in steps of 32.  Each wave owns one M tile and a set of
+// column tiles and multiplies them with all three shifts (with 8 input
+// channels a 16-column tile holds two slots).  While a row is multiplied, the
+// loads of the x rows two ahead and of the next dy row are in flight; they go
+// to LDS slots the row does not read, so one barrier per row suffices.  Each
+// block writes its partial rows to part[block][co][tap * CIN + ci] (row pitch
+// 16 NTT as for k_conv_wgrad), summed by k_sum_partials.  Needs nx a multiple
+// of 32.
+constexpr int WR_ROWS = 16;
+
+__host__ __device__ constexpr int wrow_len(int nx) { return nx + 8; }    // padded x row (elements)
+__host__ __device__ constexpr int wrow_dlen(int nx) { return nx + 16; }  // dy row: 8 before, 8 after
+
+__host__ __device__ constexpr int wrow_lds_bytes(int cin, int cout, int nx)
+{
+    return (12 * cin * wrow_len(nx) + 2 * cout * wrow_dlen(nx)) * 2;
+}
+
+// Per wave of k_conv_wgrad_rows<CIN, MT>: its M tile, column tile (16 input
+// channels of CIN = 32) and first B tile; B tiles are slots (CIN = 32) or slot
+// pairs (CIN = 8).
+template <int CIN, int MT>
+struct WrowPlan {
+    static constexpr int NB = CIN == 32 ? (MT == 2 ? 9 : 5) : 3;  // B tiles per wave (at most)
+    __device__ static void of(int wave, int& mt, int& ct, int& b0, int& nb)
+    {
+        if constexpr (CIN == 32 && MT == 2) {
+            mt = wave & 1, ct = wave >> 1, b0 = 0, nb = 9;
+        } else if constexpr (CIN == 32) {
+            mt = 0, ct = wave & 1, b0 = (wave >> 1) ? 5 : 0, nb = (wave >> 1) ? 4 : 5;
+        } else {
+            mt = wave & 1, ct = 0, b0 = (wave >> 1) ? 3 : 0, nb = (wave >> 1) ? 2 : 3;
+        }
+    }
+};
+
+__device__ __forceinline__ bf16x8 shift_fragment(const bf16x8& lo, const bf16x8& hi, bool right)
+{
+    // right: elements 7..14 of lo|hi (A[w] = dy[w - 1]); else elements 1..8
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 L = __builtin_bit_cast(u32x4, lo), H = __builtin_bit_cast(u32x4, hi);
+    u32x4 r;
+    if (right) {
+        r[0] = __builtin_amdgcn_alignbyte(H[0], L[3], 2);
+        r[1] = __builtin_amdgcn_alignbyte(H[1], H[0], 2);
+        r[2] = __builtin_amdgcn_alignbyte(H[2], H[1], 2);
+        r[3] = __builtin_amdgcn_alignbyte(H[3], H[2], 2);
+    } else {
+        r[0] = __builtin_amdgcn_alignbyte(L[1], L[0], 2);
+        r[1] = __builtin_amdgcn_alignbyte(L[2], L[1], 2);
+        r[2] = __builtin_amdgcn_alignbyte(L[3], L[2], 2);
+        r[3] = __builtin_amdgcn_alignbyte(H[0], L[3], 2);
+    }
+    return __builtin_bit_cast(bf16x8, r);
+}
+
+template <int CIN, int MT>
+__global__ void __launch_bounds__(256) k_conv_wgrad_rows(const __bf16* __restrict__ x, const __bf16* __restrict__ dy,
+                                                        float* __restrict__ part, VolGeom g)
+{
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    constexpr int COUT = 16 * MT;
+    constexpr int NTT = (27 * CIN + 15) / 16;  // column tiles of the partial rows' pitch
+    constexpr int GX = CIN / 8, GD = COUT / 8;   // 16-byte channel groups per voxel
+    constexpr int NB = WrowPlan<CIN, MT>::NB;
+    extern __shared__ __bf16 wr_lds[];
+    const int RL = wrow_len(g.nx), RD = wrow_dlen(g.nx);
+    __bf16* xs = wr_lds;                     // [ring 4][tz 3][CIN][RL]
+    __bf16* ds = wr_lds + 12 * CIN * RL;     // [buffer 2][COUT][RD]
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int m = lane & 15, grp = lane >> 4;
+    int mt, ct, b0, nb;
+    WrowPlan<CIN, MT>::of(wave, mt, ct, b0, nb);
+    const int ychunks = (g.ny + WR_ROWS - 1) / WR_ROWS;
+    const int b = blockIdx.x;
+    const int yc = b % ychunks;
+    const int z = (b / ychunks) % g.nzf;
+    const int smp = b / (ychunks * g.nzf);
+    const int y0 = yc * WR_ROWS, y1 = min(y0 + WR_ROWS, g.ny);
+    const long long sbase = (long long)smp * g.nx * g.ny * (g.nzf + 2);
+    const int half = g.nx / 2;
+    const int nxu = 3 * GX * half;  // x staging units per row: (tz, channel group, voxel pair)
+    const int ndu = GD * half;      // dy staging units per row
+    // a thread stages at most 2 x units and 1 dy unit per row (nx <= 128 with CIN = 32)
+    bf16x8 xa[2], xb[2], da, db;
+
+    auto load_x = [&](int yy) {
+        const int yw = yy < 0 ? yy + g.ny : (yy >= g.ny ? yy - g.ny : yy);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int u = tid + 256 * k;
+            if (u < nxu) {
+                const int pp = u % half, cc = (u / half) % GX, tz = u / (half * GX);
+                const long long row = sbase + ((long long)(z + tz) * g.ny + yw) * g.nx;  // halo'd plane of z + tz - 1
+                xa[k] = *reinterpret_cast<const bf16x8*>(x + (row + 2 * pp) * CIN + 8 * cc);
+                xb[k] = *reinterpret_cast<const bf16x8*>(x + (row + 2 * pp + 1) * CIN + 8 * cc);
+            }
+        }
+    };
+    auto store_x = [&](int yy) {
+        const int ring = (yy - y0 + 4) & 3;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int u = tid + 256 * k;
+            if (u < nxu) {
+                const int pp = u % half, cc = (u / half) % GX, tz = u / (half * GX);
+                __bf16* d = xs + ((ring * 3 + tz) * CIN + 8 * cc) * RL + 2 * pp;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) *reinterpret_cast<bf16x2*>(d + j * RL) = bf16x2{xa[k][j], xb[k][j]};
+            }
+        }
+    };
+    auto load_dy = [&](int yy) {
+        if (tid < ndu) {
+            const int pp = tid % half, cc = tid / half;
+            const long long row = sbase + ((long long)(z + 1) * g.ny + yy) * g.nx;
+            da = *reinterpret_cast<const bf16x8*>(dy + (row + 2 * pp) * COUT + 8 * cc);
+            db = *reinterpret_cast<const bf16x8*>(dy + (row + 2 * pp + 1) * COUT + 8 * cc);
+        }
+    };
+    auto store_dy = [&](int yy) {
+        if (tid < ndu) {
+            const int pp = tid % half, cc = tid / half;
+            __bf16* d = ds + (((yy - y0) & 1) * COUT + 8 * cc) * RD + 8;  // element e at position e + 8
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                *reinterpret_cast<bf16x2*>(d + j * RD + 2 * pp) = bf16x2{da[j], db[j]};
+                if (pp == half - 1) d[j * RD - 1] = db[j];   // element -1 = voxel nx - 1
+                if (pp == 0) d[j * RD + g.nx] = da[j];       // element nx = voxel 0
+            }
+        }
+    };
+
+    f32x4 acc[3][NB];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int yy = y0 - 1; yy <= y0 + 1 && yy <= y1; ++yy) {
+        load_x(yy);
+        store_x(yy);
+    }
+    load_dy(y0);
+    store_dy(y0);
+    __syncthreads();
+    for (int y = y0; y < y1; ++y) {
+        const bool next_x = y + 2 <= y1, next_dy = y + 1 < y1;
+        if (next_x) load_x(y + 2);
+        if (next_dy) load_dy(y + 1);
+        const __bf16* arow = ds + (((y - y0) & 1) * COUT + 16 * mt + m) * RD;
+        const int rings[3] = {(y - 1 - y0 + 4) & 3, (y - y0 + 4) & 3, (y + 1 - y0 + 4) & 3};
+        for (int kx = 0; kx < g.nx; kx += 32) {
+            const int P = kx + 8 * grp + 8;
+            const bf16x8 cm = *reinterpret_cast<const bf16x8*>(arow + P - 8);
+            const bf16x8 c0 = *reinterpret_cast<const bf16x8*>(arow + P);
+            const bf16x8 cp = *reinterpret_cast<const bf16x8*>(arow + P + 8);
+            bf16x8 a[3];
+            a[0] = shift_fragment(c0, cp, false);  // tx = -1: A[w] = dy[w + 1]
+            a[1] = c0;                             // tx = 0
+            a[2] = shift_fragment(cm, c0, true);   // tx = +1: A[w] = dy[w - 1]
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                if (j >= nb) break;
+                bf16x8 bb;
+                if constexpr (CIN == 32) {
+                    const int sl = b0 + j;
+                    bb = *reinterpret_cast<const bf16x8*>(
+                        xs + ((rings[sl % 3] * 3 + sl / 3) * CIN + 16 * ct + m) * RL + kx + 8 * grp);
+                } else {
+                    const int sl = 2 * (b0 + j) + (m >> 3);
+                    if (sl < 9) {
+                        bb = *reinterpret_cast<const bf16x8*>(
+                            xs + ((rings[sl % 3] * 3 + sl / 3) * CIN + (m & 7)) * RL + kx + 8 * grp);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) bb[e] = (__bf16)0.0f;
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 3; ++t)
+                    acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], bb, acc[t][j], 0, 0, 0);
+            }
+        }
+        if (next_x) store_x(y + 2);
+        if (next_dy) store_dy(y + 1);
+        __syncthreads();
+    }
+    // D[row = co = 16 mt + 4 grp + r][col m]; column (tap, ci) of the partial row
+    float* out = part + (long long)blockIdx.x * COUT * (16 * NTT);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j >= nb) break;
+        int sl, ci;
+        if constexpr (CIN == 32) {
+            sl = b0 + j;
+            ci = 16 * ct + m;
+        } else {
+            sl = 2 * (b0 + j) + (m >> 3);
+            ci = m & 7;
+        }
+        if (sl >= 9) continue;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int tap = (sl / 3) * 9 + (sl % 3) * 3 + t;  // (tz + 1) 9 + (ty + 1) 3 + (tx + 1)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[(long long)(16 * mt + 4 * grp + r) * (16 * NTT) + tap * CIN + ci] = acc[t][j][r];
+        }
+    }
+}
+
 // Sums nblocks partial rows: out[i] = sum_b part[b][i] over the first
 // `ncols` of each padded row of width `pitch` (drops the padding).  A block
 // covers 16 outputs with SUM_Q threads each; thread q adds the partials

@@ -54,17 +54,20 @@ class Material:
 
 
 def split_alpha4p(tau: float) -> float:
-    """alpha4' = rho c_s^2 (tau - 1/2) (rho = 1): the finite-difference force
-    carries the same isotropic viscosity term as the one the paper's split of
-    alpha4 assigns to the LBM ("the same viscosity both in LBM and in FD")."""
-    return (tau - 0.5) / 3.0
+    """alpha4' = 2 rho c_s^2 (tau - 1/2) (rho = 1): the finite-difference force
+    carries the same share of alpha4 as the LBM, whose viscous stress
+    2 rho nu D with nu = c_s^2 (tau - 1/2) contributes 2 rho c_s^2 (tau - 1/2)
+    to alpha4 ("the same viscosity both in LBM and in FD"; the printed split
+    alpha4 = alpha4' + rho c_s^2 (tau - 1/2) with the LBM's factor 2 restored).
+    The two shares then add up to alpha4."""
+    return 2.0 * (tau - 0.5) / 3.0
 
 
 def set_a() -> Material:
-    """Table-1 ratios scaled so that the LBM viscosity carries alpha4 at tau = 0.8:
-    alpha4 = 2 rho c_s^2 (tau - 1/2) = 0.2, hence every alpha is multiplied by
-    0.2/0.9318; alpha4' = rho c_s^2 (tau - 1/2) = 0.1 in the force."""
-    s = 0.2 / TABLE1_ALPHA[3]
+    """Table-1 ratios at tau = 0.8, scaled so that alpha4 is twice the LBM's
+    share: alpha4 = 4 rho c_s^2 (tau - 1/2) = 0.4, every alpha multiplied by
+    0.4/0.9318; alpha4' = 0.2 in the force."""
+    s = 0.4 / TABLE1_ALPHA[3]
     return Material(alpha=tuple(a * s for a in TABLE1_ALPHA), tau=0.8, alpha4p=split_alpha4p(0.8))
 
 
@@ -79,9 +82,10 @@ def frank_table1(mean: float) -> tuple:
 
 
 def set_b() -> Material:
-    """Table-1 viscosities; tau chosen so that 2 rho c_s^2 (tau - 1/2) = alpha4;
-    alpha4' = rho c_s^2 (tau - 1/2) = alpha4/2 in the force."""
-    tau = 0.5 + 1.5 * TABLE1_ALPHA[3]
+    """Table-1 viscosities; tau chosen so that the LBM carries half of alpha4,
+    2 rho c_s^2 (tau - 1/2) = alpha4/2 (tau = 1.19885), and the force the other
+    half, alpha4' = alpha4/2 = 0.4659."""
+    tau = 0.5 + 0.75 * TABLE1_ALPHA[3]
     return Material(alpha=TABLE1_ALPHA, tau=tau, alpha4p=split_alpha4p(tau))
 
 
@@ -269,7 +273,7 @@ def workload_c3_frank3(r: int = 5) -> tuple:
 def workload_paper(fd_ratio: int = 1, nx: int = 64, ny: int = 64, nz: int = 16) -> tuple:
     """The paper's own test case (Sec. III A, Table 1): a 64 x 64 x 16 channel
     (the two plates included), the material table's Leslie viscosities with
-    tau = 1.8977 and alpha4' = rho c_s^2 (tau - 1/2), its three Frank
+    set B's split of alpha4 (tau = 1.19885, alpha4' = 0.4659), its three Frank
     constants, pitch P = 14 (q0 = 2 pi/14), body force g = 2e-9, no director
     anchoring at the plates, weak bulk anchoring W0 = 1.5e-8; one skyrmion
     tube of the ansatz above (R = P/2) at the centre, uniform across the
@@ -285,7 +289,7 @@ def workload_c4(seed: int = 4, nchan: int = 64, material: str = "set_b", K: floa
     """Batched ensemble: nchan channels with Nx, Ny ~ U{48..160}, Nz ~ U{16..48}
     (walls included), 1-4 skyrmion tubes (pitch 32, R = 16, periodic separation
     >= 2R, fewer when they do not fit), g_x log-uniform in [1e-7, 1e-5], r drawn
-    from `ratios`; Leslie `material` (set_a: tau = 0.8; set_b: tau = 1.8977),
+    from `ratios`; Leslie `material` (set_a: tau = 0.8; set_b: tau = 1.19885),
     elastic constant K, q0 = 2 pi/32.  Returns a list of (Problem, n0), or of
     (Problem, n0, tube centres) with with_centres.
 

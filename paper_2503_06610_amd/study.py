@@ -60,14 +60,14 @@ def run_one(prob, n0, precision, steps, two_step=False):
     return out
 
 
-def tube_drift(steps=100000, every=1000, precisions=("f32_shifted", "f64_shifted"), log=print):
-    """The single-tube channel (256x256x48, r = 5): FP64 tube-drift tracking
+def tube_drift(steps=100000, every=1000, precisions=("f32_shifted", "f64_shifted"), r=5, log=print):
+    """The single-tube channel (256x256x48, dt_FD = r): FP64 tube-drift tracking
     every `every` steps for each precision; returns the displacement series
     and the mean drift velocity over the second half of the run."""
     import torch
     from paper_2503_06610_amd import el, inputs
-    prob, n0, _ = inputs.workload_c3()
-    out = {}
+    prob, n0, _ = inputs.workload_c3(r=r)
+    out = {"r": r}
     for prec in precisions:
         lat = el.Lattice(prob, prec)
         lat.init_lattice(n0)
@@ -152,6 +152,7 @@ def main(argv=None):
     ap.add_argument("--variants", nargs="+", default=["f64", "f32", "f32_shifted"])
     ap.add_argument("--out", default="")
     ap.add_argument("--tube", action="store_true", help="run the tube-drift study of the 256x256x48 channel instead")
+    ap.add_argument("--tube-fd-ratio", type=int, default=5, help="dt_FD/dt_LBM of the tube-drift study")
     ap.add_argument("--paper", action="store_true",
                     help="run the dt_FD sweep on the paper's own 64x64x16 test case instead (--steps per run)")
     args = ap.parse_args(argv)
@@ -163,7 +164,7 @@ def main(argv=None):
                 json.dump(res, f, indent=1)
         return res
     if args.tube:
-        res = tube_drift(steps=args.steps)
+        res = tube_drift(steps=args.steps, r=args.tube_fd_ratio)
         summary = {k: {kk: vv for kk, vv in v.items() if kk != "series"} if isinstance(v, dict) else v
                    for k, v in res.items()}
         print(json.dumps(summary), flush=True)

@@ -75,7 +75,7 @@ def test_validate_accepts_workloads():
     ("precision", 7, el.EL_EINVAL),
     ("flags", 512, el.EL_EINVAL),
     ("K", 0.5, el.EL_EUNSTABLE),
-    ("fd_ratio", 2, el.EL_EUNSTABLE),  # C1 with K = 0.01: r*12K/gamma1 = 2.6
+    ("fd_ratio", 4, el.EL_EUNSTABLE),  # C1 with K = 0.01: r*12K/gamma1 = 2.6
     ("alpha4p", 0.0, el.EL_EUNSTABLE),  # odd r (here 1) with an anti-dissipative explicit stress
 ])
 def test_validate_rejects(field, value, code):
@@ -89,7 +89,7 @@ def test_validate_rejects(field, value, code):
 @pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 10])
 @pytest.mark.parametrize("material", ["set_a", "set_b"])
 def test_validate_odd_r_needs_a_dissipative_explicit_stress(material, r):
-    """The presets split alpha4 as the paper does (alpha4' = rho c_s^2 (tau - 1/2)),
+    """The presets split alpha4 as the paper does (alpha4' = alpha4/2 in the force),
     which keeps the explicit viscous stress dissipative: every r is accepted.
     With alpha4' = 0 the Table-1 ratios make it anti-dissipative and every odd r
     is rejected (the period-2 velocity modes grow, test_stability_cpu.py); the
@@ -106,9 +106,11 @@ def test_validate_odd_r_needs_a_dissipative_explicit_stress(material, r):
 
 
 def test_validate_odd_r_bound_at_its_threshold():
-    """Table-1 ratios at tau = 0.8: the bound alpha4' + alpha1 + c = 0 sits at
-    alpha4' = 0.0709; the oracle grows at 0.05 and decays at 0.08."""
-    prob = inputs.channel(16, 16, 12, inputs.set_a(), g=(1e-5, 0.0, 0.0), K=1e-3, fd_ratio=1)
+    """Table-1 ratios scaled to alpha4 = 0.2 at tau = 0.8: the bound
+    alpha4' + alpha1 + c = 0 sits at alpha4' = 0.0709; the oracle grows at 0.05
+    and decays at 0.08 (test_stability_cpu)."""
+    mat = inputs.Material(alpha=tuple(a * 0.2 / inputs.TABLE1_ALPHA[3] for a in inputs.TABLE1_ALPHA), tau=0.8)
+    prob = inputs.channel(16, 16, 12, mat, g=(1e-5, 0.0, 0.0), K=1e-3, fd_ratio=1)
     assert el.validate(el.make_params(prob.with_(alpha4p=0.05), "f64")) == el.EL_EUNSTABLE
     assert el.validate(el.make_params(prob.with_(alpha4p=0.08), "f64")) == el.EL_OK
 

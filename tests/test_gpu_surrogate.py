@@ -156,19 +156,27 @@ def test_conv_backward_data_matches_reference(cout_real, cout):
     assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
 
 
+# volumes (samples, z, y, x): x = 10 takes the voxel-chunk kernel; x = 32 and 64
+# (multiples of 32) the row kernel, with a ragged last chunk of rows (y = 19, 17)
+BWD_WEIGHT_VOLS = [(S, Z, Y, X), (2, 3, 19, 32), (1, 2, 17, 64)]
+
+
+@pytest.mark.parametrize("vol", BWD_WEIGHT_VOLS)
 @pytest.mark.parametrize("cin_real,cin,cout_real,cout", [(4, 8, 32, 32), (32, 32, 32, 32), (32, 32, 3, 16)])
-def test_conv_backward_weight_matches_reference(cin_real, cin, cout_real, cout):
+def test_conv_backward_weight_matches_reference(cin_real, cin, cout_real, cout, vol):
     import torch
-    x = _bf(RNG.normal(size=(S, cin_real, Z, Y, X)))
+    s, z, y, x_ = vol
+    v = el.el_nn_vol(x_, y, z, s)
+    x = _bf(RNG.normal(size=(s, cin_real, z, y, x_)))
     zpad = _bf(RNG.normal(size=cin_real))
-    dy = _bf(RNG.normal(size=(S, cout_real, Z, Y, X)))
+    dy = _bf(RNG.normal(size=(s, cout_real, z, y, x_)))
     xa = _to_act(x, cin, zpad)
     dya = _to_act(dy, cout, np.zeros(cout_real))
-    nbytes = int(_lib().el_nn_work_bytes(C.byref(VOL), cin, cout))
+    nbytes = int(_lib().el_nn_work_bytes(C.byref(v), cin, cout))
     work = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
     dw = torch.zeros(cout * 27 * cin, dtype=torch.float32, device="cuda")
     db = torch.zeros(cout, dtype=torch.float32, device="cuda")
-    assert _lib().el_nn_conv_backward_weight(C.byref(VOL), cin, cout, _vp(xa), _vp(dya), _vp(work), nbytes,
+    assert _lib().el_nn_conv_backward_weight(C.byref(v), cin, cout, _vp(xa), _vp(dya), _vp(work), nbytes,
                                              _vp(dw), _vp(db), None) == 0
     got = dw.cpu().numpy().reshape(cout, 27, cin)
     rdw, rdb = co.conv_backward_weight(x, dy, zpad)
@@ -324,10 +332,10 @@ def test_training_and_warm_start_on_solver_data():
     import torch
     from paper_2503_06610_amd import surrogate as sg
     nx, ny, nz = 32, 32, 16
-    data = sg.generate_pairs(32, seed=9, group=32, steps=1500, nx=nx, ny=ny, nz=nz, log=_say)
+    data = sg.generate_pairs(64, seed=9, group=64, steps=1500, nx=nx, ny=ny, nz=nz, log=_say)
     assert data["max_change"] < 1e-5
     net = sg.Surrogate(seed=1, lr=2e-3)
-    hist = sg.train(net, data, epochs=40, batch=4, log=lambda m: None)
+    hist = sg.train(net, data, epochs=60, batch=4, log=lambda m: None)
     _say(f"loss {hist[0]:.3e} -> {hist[-1]:.3e}")
     assert hist[-1] < 0.3 * hist[0]
     u01 = inputs.uniform01(99, 21, 4)
