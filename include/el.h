@@ -428,8 +428,10 @@ typedef struct {
  * per (precision, node-count class, channel-count class, period or not, GPU
  * architecture) for the process; n_pred and dndt, the predictor-corrector's
  * intermediates, may be overwritten.  Allocates the small device tables of the
- * handle (hipMalloc, outside the hot path).  EL_EINVAL for a bad channel
- * (el_last_error names it) or mixed precisions. */
+ * handle (hipMalloc, outside the hot path).  Channels may mix one- and
+ * three-constant Frank energies (EL_FRANK3) and anchored or free walls.
+ * EL_EINVAL for a bad channel (el_last_error names it), a channel with
+ * obstacles (el_state.solid) or mixed precisions. */
 int el_batch_create(const el_params* params, el_state* states, int32_t nchan, const el_batch_tuning* tuning,
                     void* stream, el_batch** out);
 

@@ -31,6 +31,7 @@ struct ChanDesc {
     LbmArgs<T> lbm;
     FdArgs<T> fd;
     int fd_ratio;
+    int frank3;       // 1: three-constant Frank elasticity (EL_FRANK3)
     int frozen;       // 1: the FD step only refreshes F^LC (director fixed)
     int parity0;      // q[parity0] is current when the batch is created
     long long step0;  // LBM steps the channel had taken when the batch was created
@@ -131,7 +132,9 @@ __global__ void __launch_bounds__(1024) k_batch_moments(const ChanDesc<T>* __res
 // coupling); all = 1 runs every channel (autotuning), else the due tiles only.
 // remap = 1 (persistent grids): the XCDs take contiguous runs of the due
 // tiles, so stencil neighbours share an L2 and every XCD gets an equal share.
-template <typename T, int STAGE>
+// F3: some channel has three Frank constants (its nodes take the three-constant
+// node functions; the others the one-constant ones, as in single runs).
+template <typename T, int STAGE, bool F3>
 __global__ void __launch_bounds__(1024) k_batch_fd(const ChanDesc<T>* __restrict__ ch, const int2* __restrict__ tiles,
                                                   int ntiles, const DueGroup* __restrict__ groups, int ngroups,
                                                   const int* __restrict__ tdev, int all, int remap)
@@ -145,12 +148,24 @@ __global__ void __launch_bounds__(1024) k_batch_fd(const ChanDesc<T>* __restrict
         if (STAGE <= 1 && c.frozen) continue;
         const int k = tl.y + (int)threadIdx.x;
         if (k >= c.fd.g.N) continue;
+        const bool f3 = F3 && c.frank3;
         if (STAGE == 0) {
-            predictor_node<T>(c.n, c.u, c.nP, c.dndt, c.fd, k);
+            if (f3)
+                predictor_node<T, true>(c.n, c.u, c.nP, c.dndt, c.fd, k);
+            else
+                predictor_node<T>(c.n, c.u, c.nP, c.dndt, c.fd, k);
         } else if (STAGE == 1) {
-            corrector_node<T>(c.n, c.nP, c.u, c.dndt, c.fd, k);
+            if (f3)
+                corrector_node<T, true>(c.n, c.nP, c.u, c.dndt, c.fd, k);
+            else
+                corrector_node<T>(c.n, c.nP, c.u, c.dndt, c.fd, k);
         } else if (STAGE == 2) {
-            if (c.lbm.coupling) stress_node<T>(c.n, c.u, c.sig, c.fd, k);
+            if (c.lbm.coupling) {
+                if (f3)
+                    stress_node<T, true>(c.n, c.u, c.sig, c.fd, k);
+                else
+                    stress_node<T>(c.n, c.u, c.sig, c.fd, k);
+            }
         } else {
             if (c.lbm.coupling) {
                 divergence_node<T>(c.sig, c.F, c.fd, k);
@@ -192,6 +207,7 @@ struct el_batch {
     bool nts = false;       // streaming q stores (all channels' q buffers together > 192 MiB)
     std::vector<el::DueGroup> h_groups;  // host copy of the group table
     int period = 0;  // lcm of the channels' r when <= MAX_PERIOD (one graph per phase), else 0
+    bool frank3 = false;  // some channel has EL_FRANK3
     std::vector<hipGraph_t> graphs;
     std::vector<hipGraphExec_t> execs;
 };
@@ -286,6 +302,7 @@ int build_table(el_batch* b)
         d.lbm = lbm_args<T>(p);
         d.fd = fd_args<T>(p);
         d.fd_ratio = p->fd_ratio;
+        d.frank3 = frank3(p) ? 1 : 0;
         d.frozen = (p->flags & EL_FREEZE_DIRECTOR) ? 1 : 0;
         d.parity0 = s->parity;
         d.step0 = s->step;
@@ -330,9 +347,14 @@ void launch_moments(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, 
 template <typename T, int STAGE>
 void launch_fd(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int block, int grid, int all, int remap)
 {
-    hipLaunchKernelGGL((el::k_batch_fd<T, STAGE>), dim3(grid), dim3(block), 0, st,
-                       static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles,
-                       static_cast<const el::DueGroup*>(b->d_groups), b->ngroups, b->d_t, all, remap);
+    if (b->frank3)
+        hipLaunchKernelGGL((el::k_batch_fd<T, STAGE, true>), dim3(grid), dim3(block), 0, st,
+                           static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles,
+                           static_cast<const el::DueGroup*>(b->d_groups), b->ngroups, b->d_t, all, remap);
+    else
+        hipLaunchKernelGGL((el::k_batch_fd<T, STAGE, false>), dim3(grid), dim3(block), 0, st,
+                           static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles,
+                           static_cast<const el::DueGroup*>(b->d_groups), b->ngroups, b->d_t, all, remap);
 }
 
 // Tiles whose FD update is due in batched step t (host side of due_count).
@@ -345,17 +367,19 @@ int due_tiles_host(const el_batch* b, long long t)
 }
 
 // One batched step, batched step index t.  With a period (every channel's r
-// divides it) the moments and FD kernels get exactly one block per due tile,
-// and none at all when no channel is due; the kernels still find the due
-// tiles from the device step counter, which equals t.  Without a period they
-// run on persistent grids over the device-side due list.
+// divides it), or when the step is launched eagerly (exact = true), the
+// moments and FD kernels get exactly one block per due tile, and none at all
+// when no channel is due; the kernels still find the due tiles from the
+// device step counter, which equals t.  A step captured into the one graph of
+// a batch without a period runs them on persistent grids over the device-side
+// due list instead, since the graph replays the same grid at every step.
 template <typename T, bool SHIFT>
-int enqueue_step(el_batch* b, hipStream_t st, long long t)
+int enqueue_step(el_batch* b, hipStream_t st, long long t, bool exact)
 {
     const el_batch_tuning& tu = b->tuning;
     launch_lbm<T, SHIFT>(b, st, b->d_tiles_lbm, b->ntiles_lbm, tu.lbm_block, tu.lbm_blocks_per_cu, b->lbm_rows);
     int grid = 0;
-    if (b->period > 0)
+    if (b->period > 0 || exact)
         grid = due_tiles_host(b, t);
     else
         grid = grid_of(b->ntiles_fd, b->cus, tu.fd_blocks_per_cu > 0 ? tu.fd_blocks_per_cu : 8);
@@ -372,13 +396,13 @@ int enqueue_step(el_batch* b, hipStream_t st, long long t)
     return check_launch("batched step kernels");
 }
 
-int dispatch_step(el_batch* b, hipStream_t st, long long t)
+int dispatch_step(el_batch* b, hipStream_t st, long long t, bool exact)
 {
     switch (b->precision) {
-    case EL_F64: return enqueue_step<double, false>(b, st, t);
-    case EL_F64_SHIFTED: return enqueue_step<double, true>(b, st, t);
-    case EL_F32: return enqueue_step<float, false>(b, st, t);
-    default: return enqueue_step<float, true>(b, st, t);
+    case EL_F64: return enqueue_step<double, false>(b, st, t, exact);
+    case EL_F64_SHIFTED: return enqueue_step<double, true>(b, st, t, exact);
+    case EL_F32: return enqueue_step<float, false>(b, st, t, exact);
+    default: return enqueue_step<float, true>(b, st, t, exact);
     }
 }
 
@@ -605,8 +629,6 @@ int el_batch_create(const el_params* params, el_state* states, int32_t nchan, co
         }
         if (params[c].precision != params[0].precision)
             return fail(EL_EINVAL, "channel %d has another precision than channel 0", c);
-        if (params[c].flags & EL_FRANK3)
-            return fail(EL_EINVAL, "channel %d: the ensemble does not support EL_FRANK3", c);
         if (states[c].solid) return fail(EL_EINVAL, "channel %d: the ensemble does not support obstacles", c);
     }
     el_batch* b = new el_batch();
@@ -614,6 +636,7 @@ int el_batch_create(const el_params* params, el_state* states, int32_t nchan, co
     b->precision = params[0].precision;
     b->params.assign(params, params + nchan);
     b->states0.assign(states, states + nchan);
+    for (int c = 0; c < nchan; ++c) b->frank3 = b->frank3 || frank3(&params[c]);
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -644,7 +667,7 @@ int el_batch_step(el_batch* b, int32_t nsteps, void* stream)
             const hipGraphExec_t e = b->execs[b->period > 0 ? (size_t)(b->h_t % b->period) : 0];
             if (hipGraphLaunch(e, st) != hipSuccess) return fail(EL_EDEVICE, "hipGraphLaunch failed");
         } else {
-            int rc = dispatch_step(b, st, b->h_t);
+            int rc = dispatch_step(b, st, b->h_t, true);
             if (rc != EL_OK) return rc;
         }
         b->h_t += 1;
@@ -682,7 +705,7 @@ int el_batch_capture(el_batch* b, void* stream)
             drop_graphs(b);
             return fail(EL_EDEVICE, "hipStreamBeginCapture failed (is the stream already capturing?)");
         }
-        const int rc = dispatch_step(b, st, k);
+        const int rc = dispatch_step(b, st, k, false);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(st, &g);
         if (rc != EL_OK) {

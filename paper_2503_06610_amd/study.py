@@ -104,6 +104,78 @@ def tube_drift(steps=100000, every=1000, precisions=("f32_shifted", "f64_shifted
     return out
 
 
+def run_batched(probs_n0, precision, steps):
+    """The channels of probs_n0 as one ensemble (el_batch_*) for `steps` coupled
+    steps; per channel u (the mean of the last two steps), u_odd and n, and the
+    ensemble's MLUPS over all channels."""
+    import torch
+    from paper_2503_06610_amd import el
+    lats = []
+    for prob, n0 in probs_n0:
+        lat = el.Lattice(prob, precision)
+        lat.init_lattice(n0)
+        lats.append(lat)
+    b = el.Batch(lats)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, chunk = 0, 100_000
+    while done < steps - 1:
+        k = min(chunk, steps - 1 - done)
+        b.step(k)
+        done += k
+        if done % 200_000 == 0 or done == steps - 1:
+            torch.cuda.synchronize()
+            print(f"  {precision}: {done} steps, {time.perf_counter() - t0:.0f} s", flush=True)
+    b.moments()
+    b.sync()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) * steps / (steps - 1.0)
+    u1 = [lat.get("u") for lat in lats]
+    b.step(1)
+    b.moments()
+    b.sync()
+    out = []
+    for lat, a in zip(lats, u1):
+        u2 = lat.get("u")
+        out.append({"u": 0.5 * (a + u2), "u_odd": 0.5 * (u2 - a), "n": lat.get("n"), "obs": lat.observables()})
+    b.close()
+    nodes = sum(p.fluid_nodes for p, _ in probs_n0)
+    return out, nodes * steps / dt / 1e6
+
+
+def paper_regime_batched(steps=1_000_000, ratios=(1, 3, 5, 11, 25, 51, 101, 251, 501, 1001), log=print):
+    """The dt_FD sweep of paper_regime with every dt_FD of one precision run
+    together as one ensemble: the same arithmetic per channel as a single run
+    (the ensemble is bitwise equal to single runs), far fewer launches."""
+    from paper_2503_06610_amd import inputs
+    chans = [inputs.workload_paper(fd_ratio=r) for r in ratios]
+    res = {}
+    for prec in ("f64_shifted", "f32_shifted"):
+        res[prec], mlups = run_batched(chans, prec, steps)
+        log(json.dumps({"precision": prec, "ensemble_mlups": round(mlups, 1), "channels": len(chans)}))
+        res[prec + "_mlups"] = mlups
+    ref = res["f64_shifted"][0]
+    rows = []
+    for i, r in enumerate(ratios):
+        row = {"r": r, "steps": steps}
+        for prec in ("f64_shifted", "f32_shifted"):
+            x = res[prec][i]
+            odd_rel = float(np.sqrt((x["u_odd"] ** 2).sum() / (x["u"] ** 2).sum()))
+            row[prec] = {"u": _errs(x["u"], ref["u"]), "n": _errs(x["n"], ref["n"]), "max_u": x["obs"]["max_u"],
+                         "nonfinite": x["obs"]["nonfinite"], "odd_rel": odd_rel}
+            log(json.dumps({"r": r, "precision": prec, "eps_u": "%.3e" % row[prec]["u"]["eps"],
+                            "eps_n": "%.3e" % row[prec]["n"]["eps"], "eps_ux": "%.3e" % row[prec]["u"]["eps_comp"][0],
+                            "odd_rel": "%.2e" % odd_rel, "max_u": "%.4e" % x["obs"]["max_u"]}))
+        rows.append(row)
+    xs = [math.log(rw["r"]) for rw in rows if rw["r"] > ratios[0] and rw["f64_shifted"]["u"]["eps"] > 0]
+    ys = [math.log(rw["f64_shifted"]["u"]["eps"]) for rw in rows if rw["r"] > ratios[0]
+          and rw["f64_shifted"]["u"]["eps"] > 0]
+    slope = float(np.polyfit(xs, ys, 1)[0]) if len(xs) >= 2 else float("nan")
+    best = min(rows, key=lambda rw: rw["f32_shifted"]["u"]["eps"])
+    return {"rows": rows, "fp64_slope": slope, "fp32_best_r": best["r"], "fp32_best_eps_u": best["f32_shifted"]["u"]["eps"],
+            "ensemble_mlups": {"f64_shifted": res["f64_shifted_mlups"], "f32_shifted": res["f32_shifted_mlups"]}}
+
+
 def paper_regime(steps=2_000_000, ratios=(1, 2, 5, 10, 25, 50, 100, 250, 500, 1000), log=print):
     """The Delta t_FD sweep of Sec. III on the paper's own test case
     (inputs.workload_paper): FP64-shifted and FP32-shifted runs of `steps` LBM
@@ -155,9 +227,14 @@ def main(argv=None):
     ap.add_argument("--tube-fd-ratio", type=int, default=5, help="dt_FD/dt_LBM of the tube-drift study")
     ap.add_argument("--paper", action="store_true",
                     help="run the dt_FD sweep on the paper's own 64x64x16 test case instead (--steps per run)")
+    ap.add_argument("--batched", action="store_true",
+                    help="with --paper: run every dt_FD of a precision together as one ensemble")
     args = ap.parse_args(argv)
     if args.paper:
-        res = paper_regime(steps=args.steps, ratios=tuple(args.ratios))
+        if args.batched:
+            res = paper_regime_batched(steps=args.steps, ratios=tuple(args.ratios))
+        else:
+            res = paper_regime(steps=args.steps, ratios=tuple(args.ratios))
         print(json.dumps({k: v for k, v in res.items() if k != "rows"}), flush=True)
         if args.out:
             with open(args.out, "w") as f:

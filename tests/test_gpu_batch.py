@@ -67,6 +67,48 @@ def test_batch_channels_bitwise_equal_single_runs(precision):
             assert np.array_equal(fa[k], fs[k]), (precision, i, k)
 
 
+def _mixed_frank_batch():
+    """Five channels mixing one- and three-constant Frank energies, anchored
+    and free walls, r in {1, 2, 3}, set A and set B."""
+    specs = [(14, 11, 9, 1, True, True, "a"), (17, 8, 10, 3, False, False, "b"), (12, 13, 8, 2, True, False, "b"),
+             (10, 9, 7, 3, True, True, "b"), (15, 10, 9, 2, False, True, "a")]
+    out = []
+    for i, (nx, ny, nz, r, f3, free, m) in enumerate(specs):
+        mat = inputs.set_a() if m == "a" else inputs.set_b()
+        prob = inputs.channel(nx, ny, nz, mat, g=(3e-6 + 1e-6 * i, 0.0, 0.0), K=2e-3, q0=2 * math.pi / 12, W0=1e-4,
+                              fd_ratio=r, free_walls=free)
+        if f3:
+            K11, K22, K33 = inputs.frank_table1(2e-3)
+            prob = prob.with_(frank3=True, K11=K11, K22=K22, K33=K33, K=0.0)
+        n0 = inputs.director_tubes(prob, [(nx / 2.0, ny / 2.0)], min(nx, ny) / 3.0) if i % 2 == 0 else \
+            inputs.director_tilt(prob, seed=30 + i, amplitude=0.2)
+        out.append((prob, n0))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["f32_shifted", "f64_shifted"])
+def test_batch_mixing_three_constant_and_free_wall_channels(precision):
+    """A batch mixing one- and three-constant Frank energies and anchored and
+    free walls: every channel bitwise equal to its single-lattice run."""
+    import torch
+    chans = _mixed_frank_batch()
+    T = 19
+    singles = _lattices(chans, precision)
+    for lat in singles:
+        lat.run(T)
+    lats = _lattices(chans, precision)
+    b = el.Batch(lats)
+    b.step(T)
+    b.moments()
+    b.sync()
+    torch.cuda.synchronize()
+    for i, (a, s) in enumerate(zip(lats, singles)):
+        assert a.step == s.step == T
+        fa, fs = _fields(a), _fields(s)
+        for k in fa:
+            assert np.array_equal(fa[k], fs[k]), (precision, i, k)
+
+
 def test_batch_of_channels_at_different_steps():
     """Channels that have already taken different numbers of steps (so their
     FD updates fall on different batched steps) still match single runs."""
@@ -121,6 +163,31 @@ def test_graph_replay_equals_eager_with_interleaved_work():
             fa, fg = _fields(a), _fields(g)
             for k in fa:
                 assert np.array_equal(fa[k], fg[k]), (rep, i, k)
+
+
+def test_batch_without_a_period_eager_graph_and_single_runs_agree():
+    """Channels whose r have no common period <= 64 (7, 11, 13 and 1): eager
+    steps launch exactly the due tiles, a captured step replays persistent
+    grids over the device-side due list; both equal single runs bitwise."""
+    import torch
+    chans = [(p.with_(fd_ratio=r), n0) for (p, n0), r in zip(_small_batch()[:4], (1, 7, 11, 13))]
+    T = 40
+    singles = _lattices(chans, "f32_shifted")
+    for lat in singles:
+        lat.run(T)
+    eager = el.Batch(_lattices(chans, "f32_shifted"))
+    graph = el.Batch(_lattices(chans, "f32_shifted"))
+    graph.capture()
+    for b in (eager, graph):
+        b.step(T)
+        b.moments()
+        b.sync()
+    torch.cuda.synchronize()
+    for i, (a, g, s) in enumerate(zip(eager.lattices, graph.lattices, singles)):
+        fa, fg, fs = _fields(a), _fields(g), _fields(s)
+        for k in fa:
+            assert np.array_equal(fa[k], fs[k]), ("eager", i, k)
+            assert np.array_equal(fg[k], fs[k]), ("graph", i, k)
 
 
 def test_autotuned_shapes_give_identical_results():

@@ -136,9 +136,12 @@ def test_full_size_tube_channel_one_step_three_constants():
 
 
 def test_three_constants_rejected_where_unsupported():
+    """The y-slab calls keep one-constant stencils only (the ensemble takes
+    three-constant channels: test_gpu_batch)."""
     prob, n0, _ = _c1_frank3()
     p = el.make_params(prob, "f32_shifted")
     assert el.validate(p) == el.EL_OK
     lat = _gpu(prob, n0, "f32_shifted")
-    with pytest.raises(el.ElError):
-        el.Batch([lat])
+    with pytest.raises(el.ElError) as e:
+        lat.fd_halo_pack(0, lat.fd_halo_buffer())
+    assert e.value.status == el.EL_EINVAL
