@@ -135,8 +135,8 @@ typedef struct {
                            homeotropic anchoring), has u = 0, zero stress and no F^LC, and
                            its q are never read; gradients at fluid nodes read those fixed
                            values (Sec. II B).  Observables sum fluid nodes only.  Not
-                           supported by el_init_flow, the ensemble or the y-slab calls
-                           (EL_EINVAL); the LBM then takes the generic node kernel. */
+                           supported by el_init_flow or the y-slab calls (EL_EINVAL); the
+                           LBM then takes the generic node kernel (in the ensemble too). */
 } el_state;
 
 enum { EL_BUF_Q = 0, EL_BUF_VEC3 = 1, EL_BUF_SCRATCH = 2, EL_BUF_HALO = 3, EL_BUF_FD_HALO = 4 };
@@ -429,9 +429,10 @@ typedef struct {
  * architecture) for the process; n_pred and dndt, the predictor-corrector's
  * intermediates, may be overwritten.  Allocates the small device tables of the
  * handle (hipMalloc, outside the hot path).  Channels may mix one- and
- * three-constant Frank energies (EL_FRANK3) and anchored or free walls.
- * EL_EINVAL for a bad channel (el_last_error names it), a channel with
- * obstacles (el_state.solid) or mixed precisions. */
+ * three-constant Frank energies (EL_FRANK3), anchored or free walls, and
+ * obstacles (el_state.solid; the LBM then runs on node tiles for every
+ * channel).  EL_EINVAL for a bad channel (el_last_error names it) or mixed
+ * precisions. */
 int el_batch_create(const el_params* params, el_state* states, int32_t nchan, const el_batch_tuning* tuning,
                     void* stream, el_batch** out);
 

@@ -68,7 +68,9 @@ __device__ __forceinline__ int due_tile(const DueGroup* __restrict__ gr, int ng,
     return 0;
 }
 
-template <typename T, bool SHIFT>
+// MASK: some channel has obstacles (its nodes take the masked node function,
+// as its single-lattice run does; the others the plain one).
+template <typename T, bool SHIFT, bool MASK>
 __global__ void __launch_bounds__(1024) k_batch_lbm(const ChanDesc<T>* __restrict__ ch, const int2* __restrict__ tiles,
                                                    int ntiles, const int* __restrict__ tdev)
 {
@@ -79,7 +81,10 @@ __global__ void __launch_bounds__(1024) k_batch_lbm(const ChanDesc<T>* __restric
         const int k = tl.y + (int)threadIdx.x;
         if (k < c.lbm.g.N) {
             const int par = c.parity0 ^ (t & 1);
-            lbm_node<T, SHIFT>(c.q[par], c.q[par ^ 1], c.F, c.lbm, k);
+            if (MASK && c.lbm.solid)
+                lbm_node<T, SHIFT, true>(c.q[par], c.q[par ^ 1], c.F, c.lbm, k);
+            else
+                lbm_node<T, SHIFT>(c.q[par], c.q[par ^ 1], c.F, c.lbm, k);
         }
     }
 }
@@ -106,7 +111,7 @@ enum { MOM_DUE_IN_STEP = 0, MOM_ALL = 1, MOM_AFTER_PARTIAL = 2 };
 // FD update is due.  MOM_ALL: every channel, outside a step.  MOM_AFTER_PARTIAL:
 // outside a step, channels whose last step was not an FD step (the others
 // already hold the velocity of their last step), as el_run leaves u.
-template <typename T, bool SHIFT>
+template <typename T, bool SHIFT, bool MASK>
 __global__ void __launch_bounds__(1024) k_batch_moments(const ChanDesc<T>* __restrict__ ch,
                                                        const int2* __restrict__ tiles, int ntiles,
                                                        const DueGroup* __restrict__ groups, int ngroups,
@@ -123,7 +128,10 @@ __global__ void __launch_bounds__(1024) k_batch_moments(const ChanDesc<T>* __res
         const int k = tl.y + (int)threadIdx.x;
         if (k < c.lbm.g.N) {
             const int par = c.parity0 ^ ((t + in_step) & 1);
-            moments_node<T, SHIFT>(c.q[par], c.F, c.u, c.lbm, k);
+            if (MASK && c.lbm.solid)
+                moments_node<T, SHIFT, true>(c.q[par], c.F, c.u, c.lbm, k);
+            else
+                moments_node<T, SHIFT>(c.q[par], c.F, c.u, c.lbm, k);
         }
     }
 }
@@ -208,6 +216,7 @@ struct el_batch {
     std::vector<el::DueGroup> h_groups;  // host copy of the group table
     int period = 0;  // lcm of the channels' r when <= MAX_PERIOD (one graph per phase), else 0
     bool frank3 = false;  // some channel has EL_FRANK3
+    bool solid = false;   // some channel has obstacles (node tiles only)
     std::vector<hipGraph_t> graphs;
     std::vector<hipGraphExec_t> execs;
 };
@@ -301,6 +310,8 @@ int build_table(el_batch* b)
         d.sig = sigma_of<T>(s);
         d.lbm = lbm_args<T>(p);
         d.fd = fd_args<T>(p);
+        d.lbm.solid = static_cast<const unsigned char*>(s->solid);
+        d.fd.solid = static_cast<const unsigned char*>(s->solid);
         d.fd_ratio = p->fd_ratio;
         d.frank3 = frank3(p) ? 1 : 0;
         d.frozen = (p->flags & EL_FREEZE_DIRECTOR) ? 1 : 0;
@@ -330,18 +341,26 @@ void launch_lbm(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int 
         hipLaunchKernelGGL((el::k_batch_lbm_rows<T, SHIFT, false>), dim3(ntiles), dim3(block),
                            10 * (size_t)block * sizeof(T), st, static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles,
                            b->d_t);
-    else
-        hipLaunchKernelGGL((el::k_batch_lbm<T, SHIFT>), dim3(grid_of(ntiles, b->cus, bpc)), dim3(block), 0, st,
+    else if (b->solid)
+        hipLaunchKernelGGL((el::k_batch_lbm<T, SHIFT, true>), dim3(grid_of(ntiles, b->cus, bpc)), dim3(block), 0, st,
                            static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles, b->d_t);
+    else
+        hipLaunchKernelGGL((el::k_batch_lbm<T, SHIFT, false>), dim3(grid_of(ntiles, b->cus, bpc)), dim3(block), 0,
+                           st, static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles, b->d_t);
 }
 
 template <typename T, bool SHIFT>
 void launch_moments(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int block, int grid, int mode,
                     int remap)
 {
-    hipLaunchKernelGGL((el::k_batch_moments<T, SHIFT>), dim3(grid), dim3(block), 0, st,
-                       static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles,
-                       static_cast<const el::DueGroup*>(b->d_groups), b->ngroups, b->d_t, mode, remap);
+    if (b->solid)
+        hipLaunchKernelGGL((el::k_batch_moments<T, SHIFT, true>), dim3(grid), dim3(block), 0, st,
+                           static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles,
+                           static_cast<const el::DueGroup*>(b->d_groups), b->ngroups, b->d_t, mode, remap);
+    else
+        hipLaunchKernelGGL((el::k_batch_moments<T, SHIFT, false>), dim3(grid), dim3(block), 0, st,
+                           static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles, ntiles,
+                           static_cast<const el::DueGroup*>(b->d_groups), b->ngroups, b->d_t, mode, remap);
 }
 
 template <typename T, int STAGE>
@@ -457,7 +476,7 @@ int autotune(el_batch* b, hipStream_t st)
     el_batch_tuning tu = b->tuning;
     int2* dt = nullptr;
     for (int blk : lbm_blocks) {
-        const bool rows = rows_fit(b->params, blk, sizeof(T));
+        const bool rows = !b->solid && rows_fit(b->params, blk, sizeof(T));
         for (int bpc : bpcs) {
             if (bpc * blk > 16 * 1024) continue;
             // one block per tile: row tiles when every row fits the block
@@ -511,7 +530,8 @@ int valid_tuning(const el_batch_tuning& t)
 
 int build_tiles(el_batch* b, size_t value_bytes)
 {
-    b->lbm_rows = b->tuning.lbm_blocks_per_cu == 0 && rows_fit(b->params, b->tuning.lbm_block, value_bytes);
+    b->lbm_rows = !b->solid && b->tuning.lbm_blocks_per_cu == 0 &&
+                  rows_fit(b->params, b->tuning.lbm_block, value_bytes);
     const std::vector<int2> lt = b->lbm_rows ? make_row_tiles(b->params, b->tuning.lbm_block)
                                              : make_tiles(b->params, b->tuning.lbm_block);
     int rc = upload_tiles(lt, &b->d_tiles_lbm);
@@ -629,14 +649,16 @@ int el_batch_create(const el_params* params, el_state* states, int32_t nchan, co
         }
         if (params[c].precision != params[0].precision)
             return fail(EL_EINVAL, "channel %d has another precision than channel 0", c);
-        if (states[c].solid) return fail(EL_EINVAL, "channel %d: the ensemble does not support obstacles", c);
     }
     el_batch* b = new el_batch();
     b->nchan = nchan;
     b->precision = params[0].precision;
     b->params.assign(params, params + nchan);
     b->states0.assign(states, states + nchan);
-    for (int c = 0; c < nchan; ++c) b->frank3 = b->frank3 || frank3(&params[c]);
+    for (int c = 0; c < nchan; ++c) {
+        b->frank3 = b->frank3 || frank3(&params[c]);
+        b->solid = b->solid || states[c].solid != nullptr;
+    }
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);

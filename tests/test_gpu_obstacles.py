@@ -98,9 +98,34 @@ def test_mask_layers_reproduce_the_walls_on_the_gpu():
 
 
 def test_obstacles_rejected_where_unsupported():
+    """el_init_flow and the y-slab calls do not take obstacles (the ensemble
+    does: test_obstacle_channels_in_an_ensemble_match_single_runs)."""
     prob, n0, mask = _post_channel()
     lat = _gpu(prob, n0, "f32_shifted", mask)
     with pytest.raises(el.ElError):
-        el.Batch([lat])
-    with pytest.raises(el.ElError):
         lat.init_flow(np.zeros(prob.shape(3)))
+    with pytest.raises(el.ElError):
+        lat.fd_halo_pack(0, lat.fd_halo_buffer())
+
+
+@pytest.mark.parametrize("precision", ["f32_shifted", "f64_shifted"])
+def test_obstacle_channels_in_an_ensemble_match_single_runs(precision):
+    """An ensemble of two obstacle channels (one and three Frank constants) and
+    a plain channel: every channel bitwise equal to its single-lattice run
+    (the ensemble then takes node tiles for all of them)."""
+    import torch
+    chans = [_post_channel(False), _post_channel(True)]
+    plain = inputs.channel(20, 13, 9, inputs.set_b(), g=(4e-6, 0.0, 0.0), K=2e-3, q0=0.3, fd_ratio=3)
+    chans.append((plain, inputs.director_tilt(plain, seed=4, amplitude=0.2), None))
+    T = 21
+    singles = [_gpu(p, n0, precision, m, T) for p, n0, m in chans]
+    lats = [_gpu(p, n0, precision, m) for p, n0, m in chans]
+    b = el.Batch(lats)
+    b.step(T)
+    b.moments()
+    b.sync()
+    torch.cuda.synchronize()
+    for i, (a, s) in enumerate(zip(lats, singles)):
+        assert a.step == s.step == T
+        for f in ("q", "n", "u", "F"):
+            assert np.array_equal(a.get(f), s.get(f)), (precision, i, f)
