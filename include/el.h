@@ -237,8 +237,8 @@ size_t el_buffer_bytes(const el_params* p, int32_t which);
  * el_obs.nonfinite and max_u. */
 int el_validate(const el_params* p);
 
-/* Initialisation (Sec. II D, first step): q = rest state (0 when shifted,
- * w_i otherwise), n = n0 at fluid nodes, n_pred = n0, u = 0, dndt = 0,
+/* Initialisation (Sec. II D, first step): q[0] = q[1] = rest state (0 when
+ * shifted, w_i otherwise), n = n0 at fluid nodes, n_pred = n0, u = 0, dndt = 0,
  * F^LC computed from n0 with u = 0, parity = 0, step = 0.
  * n0: device, 3*N T in the layout above, not modified (may alias s->n). */
 int el_init_lattice(const el_params* p, el_state* s, const void* n0, void* stream);

@@ -243,7 +243,10 @@ int init_impl(const el_params* p, el_state* s, const void* n0, hipStream_t st)
 {
     const int N = geom_of(p).N;
     const int grid = grid_for(N);
+    // both buffers: obstacle nodes are never written by a step, so their q stay
+    // the rest state in either buffer (defined contents for callers that copy q)
     hipLaunchKernelGGL((el::k_rest<T, SHIFT>), dim3(grid), dim3(BLOCK), 0, st, static_cast<T*>(s->q[0]), N);
+    hipLaunchKernelGGL((el::k_rest<T, SHIFT>), dim3(grid), dim3(BLOCK), 0, st, static_cast<T*>(s->q[1]), N);
     hipLaunchKernelGGL((el::k_fd_init<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(n0),
                        static_cast<T*>(s->n), static_cast<T*>(s->n_pred), static_cast<T*>(s->dndt),
                        static_cast<T*>(s->u), static_cast<T*>(s->F), N);
