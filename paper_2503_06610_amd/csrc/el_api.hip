@@ -141,18 +141,25 @@ int launch_lbm_steps(const el_params* p, el_state* s, int nsteps, hipStream_t st
     for (int k = 0; k < nsteps; ++k) {
         const T* qa = static_cast<const T*>(s->q[s->parity]);
         T* qb = static_cast<T*>(s->q[1 - s->parity]);
+        // Odd steps visit the rows last to first (ordinary stores only): the
+        // start of a step then touches what the end of the previous one left
+        // in the Infinity Cache.  Measured, 200 steps, interleaved: 256x256x48
+        // FP32 82.5 -> 79.0 us per step; 128x128x64 FP32 26.7 -> 26.4;
+        // 128x128x64 FP64 49.6 -> 49.5; with streaming stores (256x256x48
+        // FP64) 171.2 -> 172.3, so those keep one order.
+        const int rev = nts ? 0 : (int)(s->step & 1);
         if (rows && threads == a.g.nx && nts)
             hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, true, true>), dim3(nrow), dim3(threads), shmem, st, qa,
-                               qb, static_cast<const T*>(s->F), a, 1);
+                               qb, static_cast<const T*>(s->F), a, 1, rev);
         else if (rows && threads == a.g.nx)
             hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, true, false>), dim3(nrow), dim3(threads), shmem, st, qa,
-                               qb, static_cast<const T*>(s->F), a, 1);
+                               qb, static_cast<const T*>(s->F), a, 1, rev);
         else if (rows && nts)
             hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, false, true>), dim3((nrow + R - 1) / R), dim3(threads),
-                               shmem, st, qa, qb, static_cast<const T*>(s->F), a, R);
+                               shmem, st, qa, qb, static_cast<const T*>(s->F), a, R, rev);
         else if (rows)
             hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, false, false>), dim3((nrow + R - 1) / R), dim3(threads),
-                               shmem, st, qa, qb, static_cast<const T*>(s->F), a, R);
+                               shmem, st, qa, qb, static_cast<const T*>(s->F), a, R, rev);
         else
             hipLaunchKernelGGL((el::k_lbm_push<T, SHIFT>), dim3(grid), dim3(BLOCK), 0, st, qa, qb,
                                static_cast<const T*>(s->F), a);

@@ -238,12 +238,16 @@ __device__ __forceinline__ void lbm_rows(const T* __restrict__ qa, T* __restrict
 
 // Rows of one lattice: block b handles rows b R .. b R + R - 1 (nx <= 1024,
 // blockDim >= R nx; ONE_ROW: R = 1, blockDim = nx); dynamic LDS 10 R nx values.
+// rev != 0 numbers the blocks from the last row block down (the hardware
+// starts the low block indices first), so the step begins where a forward
+// step ended; the results do not depend on the order.
 template <typename T, bool SHIFT, bool ONE_ROW, bool NTS>
 __global__ void __launch_bounds__(1024) k_lbm_push_row(const T* __restrict__ qa, T* __restrict__ qb,
-                                                      const T* __restrict__ Flc, LbmArgs<T> a, int R)
+                                                      const T* __restrict__ Flc, LbmArgs<T> a, int R, int rev)
 {
     extern __shared__ unsigned char lbm_smem[];
-    lbm_rows<T, SHIFT, ONE_ROW, NTS>(qa, qb, Flc, a, (int)blockIdx.x * R, R, reinterpret_cast<T*>(lbm_smem));
+    const int b = rev ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x;
+    lbm_rows<T, SHIFT, ONE_ROW, NTS>(qa, qb, Flc, a, b * R, R, reinterpret_cast<T*>(lbm_smem));
 }
 
 template <typename T, bool SHIFT, bool MASK = false>
