@@ -391,8 +391,8 @@ int el_error_norms_noalloc(const el_params* p, const void* a, const double* ref,
 /* ------------------------------------------------------------------------
  * Batched ensemble: many independent channels of uneven sizes, body forces
  * and FD/LBM step ratios advanced together.  Each step launches the LBM
- * kernel over a work list of (channel, tile) pairs (node tiles, or row tiles
- * of whole x-rows) and the moments and FD kernels over the tiles whose
+ * kernel over a work list of (channel, tile) pairs (tiles of consecutive
+ * nodes, rows cut anywhere) and the moments and FD kernels over the tiles whose
  * channel's finite-difference update of Sec. II D is due ((step + 1) % r ==
  * 0, decided from a device step counter).  When the least common multiple P
  * of the channels' r is at most 64, el_batch_capture records P graphs, one
@@ -404,11 +404,12 @@ int el_error_norms_noalloc(const el_params* p, const void* a, const double* ref,
 typedef struct el_batch el_batch;   /* opaque handle owned by the library */
 
 typedef struct {
-    int32_t lbm_block;          /* threads per block of the LBM kernel (64..1024): nodes per
-                                   node tile, or lbm_block / nx whole rows per row tile */
-    int32_t lbm_blocks_per_cu;  /* 0: one block per tile (row tiles when every channel's
-                                   nx <= lbm_block); 1..64: persistent grid of compute
-                                   units * this blocks looping over node tiles */
+    int32_t lbm_block;          /* threads per block of the LBM kernel (64..1024) = nodes
+                                   per tile */
+    int32_t lbm_blocks_per_cu;  /* 0: one block per tile (x shifts through LDS, unless a
+                                   channel has obstacles or the LDS would exceed 64 KiB);
+                                   1..64: persistent grid of compute units * this blocks
+                                   looping over the tiles */
     int32_t fd_block;           /* the same for the moments and FD kernels */
     int32_t fd_blocks_per_cu;   /* used only when the least common multiple of the
                                    channels' r exceeds 64 (persistent grid; 0 means 8):

@@ -89,19 +89,18 @@ __global__ void __launch_bounds__(1024) k_batch_lbm(const ChanDesc<T>* __restric
     }
 }
 
-// Row tiles: tile = (channel, first row); the block handles
-// R = blockDim / nx whole rows of the channel (every channel has nx <= blockDim).
+// Span tiles: tile = (channel, first node); the block handles the blockDim
+// consecutive nodes of the channel from there (lbm_span).
 template <typename T, bool SHIFT, bool NTS>
-__global__ void __launch_bounds__(1024) k_batch_lbm_rows(const ChanDesc<T>* __restrict__ ch,
+__global__ void __launch_bounds__(1024) k_batch_lbm_span(const ChanDesc<T>* __restrict__ ch,
                                                         const int2* __restrict__ tiles, const int* __restrict__ tdev)
 {
     extern __shared__ unsigned char lbm_smem[];
     const int t = *tdev;
     const int2 tl = tiles[blockIdx.x];
     const ChanDesc<T>& c = ch[tl.x];
-    const int R = max(1, (int)blockDim.x / c.lbm.g.nx);
     const int par = c.parity0 ^ (t & 1);
-    lbm_rows<T, SHIFT, false, NTS>(c.q[par], c.q[par ^ 1], c.F, c.lbm, tl.y, R, reinterpret_cast<T*>(lbm_smem));
+    lbm_span<T, SHIFT, NTS>(c.q[par], c.q[par ^ 1], c.F, c.lbm, tl.y, reinterpret_cast<T*>(lbm_smem));
 }
 
 // Which channels a moments launch covers.
@@ -211,7 +210,7 @@ struct el_batch {
     long long h_t = 0;
     int cus = 0;
     el_batch_tuning tuning{};
-    bool lbm_rows = false;  // LBM tiles are row tiles (one block per tile, whole rows)
+    bool lbm_span = false;  // the LBM runs the span kernel (one block per node tile)
     bool nts = false;       // streaming q stores (all channels' q buffers together > 192 MiB)
     std::vector<el::DueGroup> h_groups;  // host copy of the group table
     int period = 0;  // lcm of the channels' r when <= MAX_PERIOD (one graph per phase), else 0
@@ -227,24 +226,11 @@ using namespace elh;
 std::mutex g_tune_mu;
 std::map<std::string, el_batch_tuning> g_tune_cache;
 
-// Row tiles of blockDim `block` threads: R = block / nx rows per tile.
-std::vector<int2> make_row_tiles(const std::vector<el_params>& params, int block)
+// Whether the span kernel can take every channel with `block` threads (its LDS
+// holds 10 values per thread; obstacles take the node kernel).
+bool spans_fit(const el_batch* b, int block, size_t value_bytes)
 {
-    std::vector<int2> tiles;
-    for (size_t c = 0; c < params.size(); ++c) {
-        const el::Geom g = geom_of(&params[c]);
-        const int R = std::max(1, block / g.nx);
-        for (int r = 0; r < g.ny * g.nzf; r += R) tiles.push_back(make_int2((int)c, r));
-    }
-    return tiles;
-}
-
-// Whether the row kernel can take every channel with `block` threads.
-bool rows_fit(const std::vector<el_params>& params, int block, size_t value_bytes)
-{
-    for (const el_params& p : params)
-        if (p.nx > block) return false;
-    return 10 * (size_t)block * value_bytes <= 65536;
+    return !b->solid && 10 * (size_t)block * value_bytes <= 65536;
 }
 
 std::vector<int2> make_tiles(const std::vector<el_params>& params, int tile)
@@ -329,16 +315,16 @@ int build_table(el_batch* b)
 // bpc == 0: one block per tile; otherwise a persistent grid of cus * bpc blocks.
 int grid_of(int ntiles, int cus, int bpc) { return std::max(1, bpc == 0 ? ntiles : std::min(ntiles, cus * bpc)); }
 
-// rows: tiles are row tiles and the row kernel runs (one block per tile).
+// span: the span kernel runs, one block per node tile.
 template <typename T, bool SHIFT>
-void launch_lbm(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int block, int bpc, bool rows)
+void launch_lbm(el_batch* b, hipStream_t st, const int2* tiles, int ntiles, int block, int bpc, bool span)
 {
-    if (rows && b->nts)
-        hipLaunchKernelGGL((el::k_batch_lbm_rows<T, SHIFT, true>), dim3(ntiles), dim3(block),
+    if (span && b->nts)
+        hipLaunchKernelGGL((el::k_batch_lbm_span<T, SHIFT, true>), dim3(ntiles), dim3(block),
                            10 * (size_t)block * sizeof(T), st, static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles,
                            b->d_t);
-    else if (rows)
-        hipLaunchKernelGGL((el::k_batch_lbm_rows<T, SHIFT, false>), dim3(ntiles), dim3(block),
+    else if (span)
+        hipLaunchKernelGGL((el::k_batch_lbm_span<T, SHIFT, false>), dim3(ntiles), dim3(block),
                            10 * (size_t)block * sizeof(T), st, static_cast<const el::ChanDesc<T>*>(b->d_chan), tiles,
                            b->d_t);
     else if (b->solid)
@@ -396,7 +382,7 @@ template <typename T, bool SHIFT>
 int enqueue_step(el_batch* b, hipStream_t st, long long t, bool exact)
 {
     const el_batch_tuning& tu = b->tuning;
-    launch_lbm<T, SHIFT>(b, st, b->d_tiles_lbm, b->ntiles_lbm, tu.lbm_block, tu.lbm_blocks_per_cu, b->lbm_rows);
+    launch_lbm<T, SHIFT>(b, st, b->d_tiles_lbm, b->ntiles_lbm, tu.lbm_block, tu.lbm_blocks_per_cu, b->lbm_span);
     int grid = 0;
     if (b->period > 0 || exact)
         grid = due_tiles_host(b, t);
@@ -476,16 +462,16 @@ int autotune(el_batch* b, hipStream_t st)
     el_batch_tuning tu = b->tuning;
     int2* dt = nullptr;
     for (int blk : lbm_blocks) {
-        const bool rows = !b->solid && rows_fit(b->params, blk, sizeof(T));
+        // one block per tile: the span kernel where it fits
+        const bool span_ok = spans_fit(b, blk, sizeof(T));
+        const std::vector<int2> tiles = make_tiles(b->params, blk);
+        int rc = upload_tiles(tiles, &dt);
+        if (rc != EL_OK) return rc;
         for (int bpc : bpcs) {
             if (bpc * blk > 16 * 1024) continue;
-            // one block per tile: row tiles when every row fits the block
-            const bool use_rows = rows && bpc == 0;
-            const std::vector<int2> tiles = use_rows ? make_row_tiles(b->params, blk) : make_tiles(b->params, blk);
-            int rc = upload_tiles(tiles, &dt);
-            if (rc != EL_OK) return rc;
+            const bool span = span_ok && bpc == 0;
             const float ms =
-                time_launches(st, [&] { launch_lbm<T, SHIFT>(b, st, dt, (int)tiles.size(), blk, bpc, use_rows); });
+                time_launches(st, [&] { launch_lbm<T, SHIFT>(b, st, dt, (int)tiles.size(), blk, bpc, span); });
             if (ms < best) {
                 best = ms;
                 tu.lbm_block = blk;
@@ -530,10 +516,8 @@ int valid_tuning(const el_batch_tuning& t)
 
 int build_tiles(el_batch* b, size_t value_bytes)
 {
-    b->lbm_rows = !b->solid && b->tuning.lbm_blocks_per_cu == 0 &&
-                  rows_fit(b->params, b->tuning.lbm_block, value_bytes);
-    const std::vector<int2> lt = b->lbm_rows ? make_row_tiles(b->params, b->tuning.lbm_block)
-                                             : make_tiles(b->params, b->tuning.lbm_block);
+    b->lbm_span = b->tuning.lbm_blocks_per_cu == 0 && spans_fit(b, b->tuning.lbm_block, value_bytes);
+    const std::vector<int2> lt = make_tiles(b->params, b->tuning.lbm_block);
     int rc = upload_tiles(lt, &b->d_tiles_lbm);
     if (rc != EL_OK) return rc;
     b->ntiles_lbm = (int)lt.size();

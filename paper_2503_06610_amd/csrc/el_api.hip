@@ -115,6 +115,7 @@ int launch_lbm_steps(const el_params* p, el_state* s, int nsteps, hipStream_t st
 {
     el::LbmArgs<T> a = lbm_args<T>(p);
     const int grid = grid_for(a.g.N);
+    constexpr int SPAN = 256;
     if (s->solid) {
         // obstacles: the generic node kernel with the destination check
         a.solid = static_cast<const unsigned char*>(s->solid);
@@ -127,42 +128,44 @@ int launch_lbm_steps(const el_params* p, el_state* s, int nsteps, hipStream_t st
         }
         return check_launch("LBM step kernel");
     }
-    // whole-row blocks with the x shifts through LDS: one row per block when a
-    // row is a whole number of wavefronts, else as many rows as fit in 256
-    // threads (several rows per block when nx is a multiple of 64 measured
-    // slower: 128x128x64 FP32 27.5 us per step with one row, 29.7-30.7 us with
-    // 2-8 rows)
-    const int R = (a.g.nx % 64 == 0) ? 1 : std::max(1, 256 / a.g.nx);
-    const bool rows = a.g.nx <= 1024 && 10 * (size_t)R * a.g.nx * sizeof(T) <= 65536;
-    const int threads = ((R * a.g.nx + 63) / 64) * 64;
+    // The x shifts go through LDS.  One row per block when a row is a whole
+    // number of wavefronts (nx a multiple of 64, up to 1024; several rows per
+    // block measured slower: 128x128x64 FP32 27.5 us per step with one row,
+    // 29.7-30.7 us with 2-8 rows).  Other row lengths take spans of 256
+    // consecutive nodes, rows cut anywhere.  Measured against whole rows
+    // packed into 256-thread blocks (FP32, 200 steps, interleaved; us per
+    // step): 129x97x34 19.8 -> 16.2, 200x200x34 51.0 -> 41.0, 100x100x34
+    // 13.6 -> 13.2, 160x160x34 26.8 -> 25.6, 72x150x34 14.5 -> 14.5: packed
+    // rows leave lanes idle and start anywhere inside a cache line.
+    const bool one_row = a.g.nx % 64 == 0 && a.g.nx <= 1024 && 10 * (size_t)a.g.nx * sizeof(T) <= 65536;
+    const int threads = one_row ? a.g.nx : SPAN;
     const int nrow = a.g.ny * a.g.nzf;
-    const size_t shmem = rows ? 10 * (size_t)R * a.g.nx * sizeof(T) : 0;
+    const int grid_rows = one_row ? nrow : (a.g.N + SPAN - 1) / SPAN;
+    const size_t shmem = 10 * (size_t)threads * sizeof(T);
     const bool nts = streaming_stores(19 * (size_t)a.g.N * sizeof(T));
     for (int k = 0; k < nsteps; ++k) {
         const T* qa = static_cast<const T*>(s->q[s->parity]);
         T* qb = static_cast<T*>(s->q[1 - s->parity]);
-        // Odd steps visit the rows last to first (ordinary stores only): the
+        const T* F = static_cast<const T*>(s->F);
+        // Odd steps visit the blocks last to first (ordinary stores only): the
         // start of a step then touches what the end of the previous one left
         // in the Infinity Cache.  Measured, 200 steps, interleaved: 256x256x48
         // FP32 82.5 -> 79.0 us per step; 128x128x64 FP32 26.7 -> 26.4;
         // 128x128x64 FP64 49.6 -> 49.5; with streaming stores (256x256x48
         // FP64) 171.2 -> 172.3, so those keep one order.
         const int rev = nts ? 0 : (int)(s->step & 1);
-        if (rows && threads == a.g.nx && nts)
-            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, true, true>), dim3(nrow), dim3(threads), shmem, st, qa,
-                               qb, static_cast<const T*>(s->F), a, 1, rev);
-        else if (rows && threads == a.g.nx)
-            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, true, false>), dim3(nrow), dim3(threads), shmem, st, qa,
-                               qb, static_cast<const T*>(s->F), a, 1, rev);
-        else if (rows && nts)
-            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, false, true>), dim3((nrow + R - 1) / R), dim3(threads),
-                               shmem, st, qa, qb, static_cast<const T*>(s->F), a, R, rev);
-        else if (rows)
-            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, false, false>), dim3((nrow + R - 1) / R), dim3(threads),
-                               shmem, st, qa, qb, static_cast<const T*>(s->F), a, R, rev);
+        if (one_row && nts)
+            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, true>), dim3(grid_rows), dim3(threads), shmem, st, qa,
+                               qb, F, a, rev);
+        else if (one_row)
+            hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, false>), dim3(grid_rows), dim3(threads), shmem, st, qa,
+                               qb, F, a, rev);
+        else if (nts)
+            hipLaunchKernelGGL((el::k_lbm_push_span<T, SHIFT, true>), dim3(grid_rows), dim3(threads), shmem, st,
+                               qa, qb, F, a, rev);
         else
-            hipLaunchKernelGGL((el::k_lbm_push<T, SHIFT>), dim3(grid), dim3(BLOCK), 0, st, qa, qb,
-                               static_cast<const T*>(s->F), a);
+            hipLaunchKernelGGL((el::k_lbm_push_span<T, SHIFT, false>), dim3(grid_rows), dim3(threads), shmem, st,
+                               qa, qb, F, a, rev);
         s->parity = 1 - s->parity;
         s->step += 1;
     }

@@ -173,81 +173,156 @@ __device__ __forceinline__ void lbm_node(const T* __restrict__ qa, T* __restrict
     }
 }
 
-// Row variant: a block handles R whole x-rows (y, z) = row0 .. row0 + R - 1,
-// thread (row rl, column x) = threadIdx.x = rl nx + x (R nx <= blockDim.x;
-// the rest idle).  Populations moving in x are passed through LDS
-// (lds: [10][R nx], the directions with e_x != 0) to the thread owning their
-// destination column, so every store writes whole rows; the arithmetic is
-// lbm_collide's.  Every thread of the block must call this (barrier).
-// ONE_ROW: R = 1 and blockDim = nx (no idle lanes, no division).  NTS:
-// streaming stores (see q_store).
-template <typename T, bool SHIFT, bool ONE_ROW = false, bool NTS = false>
-__device__ __forceinline__ void lbm_rows(const T* __restrict__ qa, T* __restrict__ qb, const T* __restrict__ Flc,
-                                         const LbmArgs<T>& a, int row0, int R, T* lds)
+// Neighbour row offsets of row (y, z) and which z walls it touches.
+struct RowNbrs {
+    int ys[3], zs[3];
+    bool wall_m, wall_p;
+};
+
+__device__ __forceinline__ RowNbrs row_nbrs(const Geom& g, int y, int z)
 {
-    const Geom& g = a.g;
-    const int rl = ONE_ROW ? 0 : (int)threadIdx.x / g.nx;
-    const int x = (int)threadIdx.x - rl * g.nx;
-    const int r = row0 + rl;
-    const bool active = rl < R && r < g.ny * g.nzf;
-    const int span = R * g.nx;
-    const int base = rl * g.nx;
-    const size_t N = (size_t)g.N;
-    // slot of each direction with e_x != 0 in the LDS staging area
-    constexpr int SLOT[19] = {-1, 0, 1, -1, -1, -1, -1, 2, 3, 4, 5, 6, 7, 8, 9, -1, -1, -1, -1};
-    T post[19];
-    int k = 0;
-    if (active) {
-        k = x + g.nx * r;
-        lbm_collide<T, SHIFT>(qa, Flc, a, k, post);
-#pragma unroll
-        for (int i = 0; i < 19; ++i)
-            if (SLOT[i] >= 0) lds[SLOT[i] * span + base + x] = post[i];
-    }
-    __syncthreads();
-    if (!active) return;
-    const int y = r % g.ny;
-    const int z = r / g.ny;
+    RowNbrs n;
     const int row = g.nx, plane = g.nx * g.ny;
-    const int ys[3] = {((y == 0) ? g.ny - 1 : y - 1) * row, y * row, ((y == g.ny - 1) ? 0 : y + 1) * row};
+    n.ys[0] = ((y == 0) ? g.ny - 1 : y - 1) * row;
+    n.ys[1] = y * row;
+    n.ys[2] = ((y == g.ny - 1) ? 0 : y + 1) * row;
     int zm = z - 1, zp = z + 1;
-    bool wall_m = false, wall_p = false;
+    n.wall_m = n.wall_p = false;
     if (g.periodic_z) {
         if (zm < 0) zm = g.nzf - 1;
         if (zp == g.nzf) zp = 0;
     } else {
-        wall_m = zm < 0;
-        wall_p = zp == g.nzf;
+        n.wall_m = zm < 0;
+        n.wall_p = zp == g.nzf;
     }
-    const int zs[3] = {zm * plane, z * plane, zp * plane};
+    n.zs[0] = zm * plane;
+    n.zs[1] = z * plane;
+    n.zs[2] = zp * plane;
+    return n;
+}
+
+// LDS slot of each direction with e_x != 0 (the populations that move in x).
+__host__ __device__ constexpr int XSLOT(int i)
+{
+    return (i == 1 || i == 2) ? i - 1 : ((i >= 7 && i <= 14) ? i - 5 : -1);
+}
+
+// Row variant: the block (blockDim = nx) handles the whole x-row
+// (y, z) = row, thread x = threadIdx.x.  Populations moving in x are passed
+// through LDS (lds: [10][nx], the directions with e_x != 0) to the thread
+// owning their destination column, so every store writes a whole row; the
+// arithmetic is lbm_collide's.  NTS: streaming stores (see q_store).
+template <typename T, bool SHIFT, bool NTS = false>
+__device__ __forceinline__ void lbm_row(const T* __restrict__ qa, T* __restrict__ qb, const T* __restrict__ Flc,
+                                        const LbmArgs<T>& a, int r, T* lds)
+{
+    const Geom& g = a.g;
+    const int x = (int)threadIdx.x;
+    const size_t N = (size_t)g.N;
+    T post[19];
+    const int k = x + g.nx * r;
+    lbm_collide<T, SHIFT>(qa, Flc, a, k, post);
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+        if (XSLOT(i) >= 0) lds[XSLOT(i) * g.nx + x] = post[i];
+    __syncthreads();
+    const RowNbrs nb = row_nbrs(g, r % g.ny, r / g.ny);
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
-        const bool to_wall = (EZ(i) == 1 && wall_p) || (EZ(i) == -1 && wall_m);
+        const bool to_wall = (EZ(i) == 1 && nb.wall_p) || (EZ(i) == -1 && nb.wall_m);
+        const int dst = x + nb.ys[EY(i) + 1] + nb.zs[EZ(i) + 1];
         if (to_wall) {
             q_store<NTS>(qb + OPP(i) * N + k, post[i]);  // bounce-back: own value, own node
-        } else if (SLOT[i] < 0) {
-            q_store<NTS>(qb + i * N + x + ys[EY(i) + 1] + zs[EZ(i) + 1], post[i]);
+        } else if (XSLOT(i) < 0) {
+            q_store<NTS>(qb + i * N + dst, post[i]);
         } else {
             // the population arriving at column x came from column x - e_x
             int xs = x - EX(i);
             xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
-            q_store<NTS>(qb + i * N + x + ys[EY(i) + 1] + zs[EZ(i) + 1], lds[SLOT[i] * span + base + xs]);
+            q_store<NTS>(qb + i * N + dst, lds[XSLOT(i) * g.nx + xs]);
         }
     }
 }
 
-// Rows of one lattice: block b handles rows b R .. b R + R - 1 (nx <= 1024,
-// blockDim >= R nx; ONE_ROW: R = 1, blockDim = nx); dynamic LDS 10 R nx values.
-// rev != 0 numbers the blocks from the last row block down (the hardware
-// starts the low block indices first), so the step begins where a forward
-// step ended; the results do not depend on the order.
-template <typename T, bool SHIFT, bool ONE_ROW, bool NTS>
+// Span variant: the block handles the S = blockDim consecutive nodes
+// k0 .. k0 + S - 1 of the linear index, whatever rows they belong to (rows of
+// any length, cut anywhere), so no lane idles but in a lattice's last span and
+// every load of a wavefront is one aligned run.  As in lbm_row, a population
+// moving in x passes through LDS (lds: [10][S]) to the thread of the column it
+// arrives at, which stores it in that direction's contiguous run; where the
+// source column lies outside the span (the rows the span cuts), the source's
+// own thread stores it instead, so every (node, direction) is written once.
+// Every thread of the block must call this (barrier).
+template <typename T, bool SHIFT, bool NTS = false>
+__device__ __forceinline__ void lbm_span(const T* __restrict__ qa, T* __restrict__ qb, const T* __restrict__ Flc,
+                                         const LbmArgs<T>& a, int k0, T* lds)
+{
+    const Geom& g = a.g;
+    const int S = (int)blockDim.x;
+    const int j = (int)threadIdx.x;
+    const int k = k0 + j;
+    const int kend = min(k0 + S, g.N);
+    const bool active = k < g.N;
+    const size_t N = (size_t)g.N;
+    T post[19];
+    if (active) {
+        lbm_collide<T, SHIFT>(qa, Flc, a, k, post);
+#pragma unroll
+        for (int i = 0; i < 19; ++i)
+            if (XSLOT(i) >= 0) lds[XSLOT(i) * S + j] = post[i];
+    }
+    __syncthreads();
+    if (!active) return;
+    const int r = k / g.nx;
+    const int x = k - r * g.nx;
+    const int row0 = k - x;  // linear index of the row's first node
+    const RowNbrs nb = row_nbrs(g, r % g.ny, r / g.ny);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const bool to_wall = (EZ(i) == 1 && nb.wall_p) || (EZ(i) == -1 && nb.wall_m);
+        const int off = nb.ys[EY(i) + 1] + nb.zs[EZ(i) + 1];
+        if (to_wall) {
+            q_store<NTS>(qb + OPP(i) * N + k, post[i]);
+        } else if (XSLOT(i) < 0) {
+            q_store<NTS>(qb + i * N + x + off, post[i]);
+        } else {
+            // arriving at column x from column x - e_x of the same row
+            int xs = x - EX(i);
+            xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
+            const int src = row0 + xs;
+            if (src >= k0 && src < kend) q_store<NTS>(qb + i * N + x + off, lds[XSLOT(i) * S + (src - k0)]);
+            // leaving for column x + e_x: stored here when that column's
+            // thread belongs to another span
+            int xd = x + EX(i);
+            xd = xd < 0 ? xd + g.nx : (xd >= g.nx ? xd - g.nx : xd);
+            const int dst = row0 + xd;
+            if (dst < k0 || dst >= kend) q_store<NTS>(qb + i * N + xd + off, post[i]);
+        }
+    }
+}
+
+// One row per block (blockDim = nx, nx <= 1024); dynamic LDS 10 nx values.
+// rev != 0 numbers the blocks from the last row down (the hardware starts the
+// low block indices first), so the step begins where a forward step ended;
+// the results do not depend on the order.
+template <typename T, bool SHIFT, bool NTS>
 __global__ void __launch_bounds__(1024) k_lbm_push_row(const T* __restrict__ qa, T* __restrict__ qb,
-                                                      const T* __restrict__ Flc, LbmArgs<T> a, int R, int rev)
+                                                      const T* __restrict__ Flc, LbmArgs<T> a, int rev)
 {
     extern __shared__ unsigned char lbm_smem[];
     const int b = rev ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x;
-    lbm_rows<T, SHIFT, ONE_ROW, NTS>(qa, qb, Flc, a, b * R, R, reinterpret_cast<T*>(lbm_smem));
+    lbm_row<T, SHIFT, NTS>(qa, qb, Flc, a, b, reinterpret_cast<T*>(lbm_smem));
+}
+
+// Spans of blockDim consecutive nodes; dynamic LDS 10 blockDim values; rev as
+// in k_lbm_push_row.
+template <typename T, bool SHIFT, bool NTS>
+__global__ void __launch_bounds__(1024) k_lbm_push_span(const T* __restrict__ qa, T* __restrict__ qb,
+                                                       const T* __restrict__ Flc, LbmArgs<T> a, int rev)
+{
+    extern __shared__ unsigned char lbm_smem[];
+    const int b = rev ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x;
+    lbm_span<T, SHIFT, NTS>(qa, qb, Flc, a, b * (int)blockDim.x, reinterpret_cast<T*>(lbm_smem));
 }
 
 template <typename T, bool SHIFT, bool MASK = false>

@@ -294,10 +294,12 @@ def test_capture_on_null_stream_is_rejected():
     assert b.lattices[0].step == 2
 
 
-def test_row_kernel_matches_generic_kernel():
-    """The single-lattice path takes the LDS row-shift LBM kernel; the batch
-    uses the generic push (node tiles) or the row kernel on row tiles.  All
-    must agree bitwise (same collision code, only the data movement differs)."""
+def test_span_kernel_matches_generic_kernel():
+    """The single-lattice path takes the LDS row-shift LBM kernel (nx a
+    multiple of 64) or the span kernel; the batch uses the generic push
+    (persistent grid) or the span kernel on its tiles, here with spans shorter
+    and longer than the rows.  All must agree bitwise (same collision code,
+    only the data movement differs)."""
     import torch
     mat = inputs.set_a()
     chans = []
@@ -308,7 +310,7 @@ def test_row_kernel_matches_generic_kernel():
     for lat in singles:
         lat.run(17)
     lats = _lattices(chans, "f32_shifted")
-    for tuning in ((256, 4, 256, 4), (256, 0, 256, 0)):  # node tiles; row tiles (every nx <= 256)
+    for tuning in ((256, 4, 256, 4), (256, 0, 256, 0), (64, 0, 128, 0), (1024, 0, 256, 0)):  # generic; spans
         lats = _lattices(chans, "f32_shifted")
         b = el.Batch(lats, tuning=tuning)
         b.step(17)

@@ -101,11 +101,12 @@ def test_ragged_lattice_all_terms_fp64():
 
 @pytest.mark.parametrize("nx,ny", [(300, 4), (37, 11), (64, 5), (300, 100)])
 def test_row_shapes_match_oracle(nx, ny):
-    """The LBM row kernel's block shapes: several short rows per block (37),
-    one row of a whole number of wavefronts (64), one row with idle lanes
-    (300 of 320 threads); 300x100 planes are large enough for the FD kernels
-    to visit them in y-strips of 13 rows (the last one ragged).  FP64 against
-    the oracle, FP32-shifted against FP64 on the GPU."""
+    """The LBM kernels' block shapes: 256-node spans over short rows, cut
+    anywhere (37), one row of a whole number of wavefronts per block (64),
+    rows longer than a span, whose x-moving populations cross span ends
+    (300); 300x100 planes are large enough for the FD kernels to visit them
+    in y-strips of 13 rows (the last one ragged).  FP64 against the oracle,
+    FP32-shifted against FP64 on the GPU."""
     prob = inputs.channel(nx, ny, 7, inputs.set_a(), g=(2e-6, 1e-6, 0.0), K=2e-3, q0=2 * math.pi / 12,
                           fd_ratio=2)
     n0 = inputs.director_tilt(prob, seed=nx, amplitude=0.3)
