@@ -34,6 +34,11 @@
  *   - Layout: structure of arrays over FLUID nodes only, x fastest:
  *       element (c, x, y, zf) of a field with C components lives at
  *       c*N + x + nx*(y + ny*zf),  N = nx*ny*nzf,
+ *     except q, whose 19 directions are spaced qs = N rounded up to a
+ *     multiple of EL_Q_ALIGN values apart (element (i, x, y, zf) at
+ *     i*qs + x + nx*(y + ny*zf)), so each direction's array starts on a
+ *     256-byte boundary; the qs - N values after each direction are padding
+ *     (set by el_init_lattice, not read by any call),
  *     where zf = z - 1 and nzf = nz - 2 with solid walls at z = 0 and
  *     z = nz - 1 (halfway bounce-back, wall midway between the last fluid
  *     and the solid layer), or zf = z and nzf = nz with EL_PERIODIC_Z.
@@ -117,7 +122,7 @@ typedef struct {
 
 /* Caller-owned device buffers of one lattice (sizes from el_buffer_bytes). */
 typedef struct {
-    void* q[2];         /* 19*N T each: distributions, ping-pong */
+    void* q[2];         /* 19*qs T each: distributions, ping-pong */
     void* n;            /* 3*N T: director */
     void* n_pred;       /* 3*N T: predictor n^P */
     void* dndt;         /* 3*N T: (d_t n)_old of the predictor-corrector */
@@ -140,6 +145,9 @@ typedef struct {
 } el_state;
 
 enum { EL_BUF_Q = 0, EL_BUF_VEC3 = 1, EL_BUF_SCRATCH = 2, EL_BUF_HALO = 3, EL_BUF_FD_HALO = 4 };
+
+/* Values per direction of q are rounded up to a multiple of this (the stride qs). */
+#define EL_Q_ALIGN 64
 
 /* Skyrmion tubes followed by the observables (Sec. III B follows one tube
  * carried by the flow and a system of many).  A node with tube weight

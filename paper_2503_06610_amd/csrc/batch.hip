@@ -576,7 +576,7 @@ int create_impl(el_batch* b, const el_batch_tuning* tuning, hipStream_t st)
     b->period = period_of(b->params);
     {
         size_t qbytes = 0;
-        for (const el_params& p : b->params) qbytes += 19 * (size_t)geom_of(&p).N * sizeof(T);
+        for (const el_params& p : b->params) qbytes += 19 * (size_t)geom_of(&p).qs * sizeof(T);
         b->nts = streaming_stores(qbytes);
     }
     int rc = build_table<T>(b);

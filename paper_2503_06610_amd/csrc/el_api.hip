@@ -142,7 +142,7 @@ int launch_lbm_steps(const el_params* p, el_state* s, int nsteps, hipStream_t st
     const int nrow = a.g.ny * a.g.nzf;
     const int grid_rows = one_row ? nrow : (a.g.N + SPAN - 1) / SPAN;
     const size_t shmem = 10 * (size_t)threads * sizeof(T);
-    const bool nts = streaming_stores(19 * (size_t)a.g.N * sizeof(T));
+    const bool nts = streaming_stores(19 * (size_t)a.g.qs * sizeof(T));
     for (int k = 0; k < nsteps; ++k) {
         const T* qa = static_cast<const T*>(s->q[s->parity]);
         T* qb = static_cast<T*>(s->q[1 - s->parity]);
@@ -252,11 +252,12 @@ template <typename T, bool SHIFT>
 int init_impl(const el_params* p, el_state* s, const void* n0, hipStream_t st)
 {
     const int N = geom_of(p).N;
+    const int qs = geom_of(p).qs;
     const int grid = grid_for(N);
     // both buffers: obstacle nodes are never written by a step, so their q stay
     // the rest state in either buffer (defined contents for callers that copy q)
-    hipLaunchKernelGGL((el::k_rest<T, SHIFT>), dim3(grid), dim3(BLOCK), 0, st, static_cast<T*>(s->q[0]), N);
-    hipLaunchKernelGGL((el::k_rest<T, SHIFT>), dim3(grid), dim3(BLOCK), 0, st, static_cast<T*>(s->q[1]), N);
+    hipLaunchKernelGGL((el::k_rest<T, SHIFT>), dim3(grid_for(qs)), dim3(BLOCK), 0, st, static_cast<T*>(s->q[0]), qs);
+    hipLaunchKernelGGL((el::k_rest<T, SHIFT>), dim3(grid_for(qs)), dim3(BLOCK), 0, st, static_cast<T*>(s->q[1]), qs);
     hipLaunchKernelGGL((el::k_fd_init<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(n0),
                        static_cast<T*>(s->n), static_cast<T*>(s->n_pred), static_cast<T*>(s->dndt),
                        static_cast<T*>(s->u), static_cast<T*>(s->F), N);
@@ -473,7 +474,7 @@ size_t el_buffer_bytes(const el_params* p, int32_t which)
     const size_t N = (size_t)geom_of(p).N;
     const size_t ts = is_f64(p) ? sizeof(double) : sizeof(float);
     switch (which) {
-    case EL_BUF_Q: return 19 * N * ts;
+    case EL_BUF_Q: return 19 * (size_t)geom_of(p).qs * ts;
     case EL_BUF_VEC3: return 3 * N * ts;
     case EL_BUF_SCRATCH: return REDUCE_BYTES + 9 * N * ts;
     case EL_BUF_HALO: return 2 * 5 * (size_t)p->nx * (size_t)nzf_of(p) * ts;

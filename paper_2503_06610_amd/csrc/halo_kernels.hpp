@@ -37,9 +37,9 @@ __global__ void __launch_bounds__(256) k_halo_pack(const T* __restrict__ q, T* _
     const int r = i - d * face;
     const int z = r / g.nx;
     const int x = r - z * g.nx;
-    const size_t N = (size_t)g.N;
-    out[i] = q[HALO_UP(d) * N + x + (size_t)g.nx * g.ny * z];
-    out[5 * face + i] = q[HALO_DN(d) * N + x + g.nx * ((size_t)(g.ny - 1) + (size_t)g.ny * z)];
+    const size_t QS = (size_t)g.qs;
+    out[i] = q[HALO_UP(d) * QS + x + (size_t)g.nx * g.ny * z];
+    out[5 * face + i] = q[HALO_DN(d) * QS + x + g.nx * ((size_t)(g.ny - 1) + (size_t)g.ny * z)];
 }
 
 template <typename T>
@@ -53,11 +53,11 @@ __global__ void __launch_bounds__(256) k_halo_unpack(T* __restrict__ q, const T*
     const int r = i - d * face;
     const int z = r / g.nx;
     const int x = r - z * g.nx;
-    const size_t N = (size_t)g.N;
+    const size_t QS = (size_t)g.qs;
     const int zu = z - EZ(HALO_UP(d)), zd = z - EZ(HALO_DN(d));
-    if (g.periodic_z || (zu >= 0 && zu < g.nzf)) q[HALO_UP(d) * N + x + (size_t)g.nx * g.ny * z] = lower[i];
+    if (g.periodic_z || (zu >= 0 && zu < g.nzf)) q[HALO_UP(d) * QS + x + (size_t)g.nx * g.ny * z] = lower[i];
     if (g.periodic_z || (zd >= 0 && zd < g.nzf))
-        q[HALO_DN(d) * N + x + g.nx * ((size_t)(g.ny - 1) + (size_t)g.ny * z)] = upper[5 * face + i];
+        q[HALO_DN(d) * QS + x + g.nx * ((size_t)(g.ny - 1) + (size_t)g.ny * z)] = upper[5 * face + i];
 }
 
 }  // namespace el

@@ -17,6 +17,8 @@
 #include "lbm_kernels.hpp"
 #include "reduce_kernels.hpp"
 
+static_assert(el::Q_ALIGN == EL_Q_ALIGN, "q stride alignment differs from the header");
+
 namespace elh {
 
 // Records the detail of a failure for el_last_error() and returns code.
@@ -50,6 +52,7 @@ inline el::Geom geom_of(const el_params* p)
     g.nzf = nzf_of(p);
     g.periodic_z = periodic_z(p) ? 1 : 0;
     g.N = p->nx * p->ny * g.nzf;
+    g.qs = (g.N + el::Q_ALIGN - 1) / el::Q_ALIGN * el::Q_ALIGN;
     g.free_walls = (p->flags & EL_FREE_WALLS) ? 1 : 0;
     return g;
 }

@@ -87,10 +87,10 @@ template <typename T, bool SHIFT>
 __device__ __forceinline__ void lbm_collide(const T* __restrict__ qa, const T* __restrict__ Flc, const LbmArgs<T>& a,
                                             int k, T (&post)[19])
 {
-    const size_t N = (size_t)a.g.N;
+    const size_t N = (size_t)a.g.N, QS = (size_t)a.g.qs;
     T q[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) q[i] = q_load(qa + i * N + k);
+    for (int i = 0; i < 19; ++i) q[i] = q_load(qa + i * QS + k);
 
     T rho, drho, jx, jy, jz;
     node_moments<T, SHIFT>(q, rho, drho, jx, jy, jz);
@@ -144,7 +144,7 @@ __device__ __forceinline__ void lbm_node(const T* __restrict__ qa, T* __restrict
     const int t = k / g.nx;
     const int y = t % g.ny;
     const int z = t / g.ny;
-    const size_t N = (size_t)g.N;
+    const size_t QS = (size_t)g.qs;
     T post[19];
     lbm_collide<T, SHIFT>(qa, Flc, a, k, post);
 
@@ -166,9 +166,9 @@ __device__ __forceinline__ void lbm_node(const T* __restrict__ qa, T* __restrict
         const bool to_wall = (EZ(i) == 1 && wall_p) || (EZ(i) == -1 && wall_m);
         const int d = xs[EX(i) + 1] + ys[EY(i) + 1] + zs[EZ(i) + 1];
         if (to_wall || (MASK && i != 0 && a.solid[d])) {
-            qb[OPP(i) * N + k] = post[i];
+            qb[OPP(i) * QS + k] = post[i];
         } else {
-            qb[i * N + d] = post[i];
+            qb[i * QS + d] = post[i];
         }
     }
 }
@@ -218,7 +218,7 @@ __device__ __forceinline__ void lbm_row(const T* __restrict__ qa, T* __restrict_
 {
     const Geom& g = a.g;
     const int x = (int)threadIdx.x;
-    const size_t N = (size_t)g.N;
+    const size_t QS = (size_t)g.qs;
     T post[19];
     const int k = x + g.nx * r;
     lbm_collide<T, SHIFT>(qa, Flc, a, k, post);
@@ -232,14 +232,14 @@ __device__ __forceinline__ void lbm_row(const T* __restrict__ qa, T* __restrict_
         const bool to_wall = (EZ(i) == 1 && nb.wall_p) || (EZ(i) == -1 && nb.wall_m);
         const int dst = x + nb.ys[EY(i) + 1] + nb.zs[EZ(i) + 1];
         if (to_wall) {
-            q_store<NTS>(qb + OPP(i) * N + k, post[i]);  // bounce-back: own value, own node
+            q_store<NTS>(qb + OPP(i) * QS + k, post[i]);  // bounce-back: own value, own node
         } else if (XSLOT(i) < 0) {
-            q_store<NTS>(qb + i * N + dst, post[i]);
+            q_store<NTS>(qb + i * QS + dst, post[i]);
         } else {
             // the population arriving at column x came from column x - e_x
             int xs = x - EX(i);
             xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
-            q_store<NTS>(qb + i * N + dst, lds[XSLOT(i) * g.nx + xs]);
+            q_store<NTS>(qb + i * QS + dst, lds[XSLOT(i) * g.nx + xs]);
         }
     }
 }
@@ -263,7 +263,7 @@ __device__ __forceinline__ void lbm_span(const T* __restrict__ qa, T* __restrict
     const int k = k0 + j;
     const int kend = min(k0 + S, g.N);
     const bool active = k < g.N;
-    const size_t N = (size_t)g.N;
+    const size_t QS = (size_t)g.qs;
     T post[19];
     if (active) {
         lbm_collide<T, SHIFT>(qa, Flc, a, k, post);
@@ -282,21 +282,21 @@ __device__ __forceinline__ void lbm_span(const T* __restrict__ qa, T* __restrict
         const bool to_wall = (EZ(i) == 1 && nb.wall_p) || (EZ(i) == -1 && nb.wall_m);
         const int off = nb.ys[EY(i) + 1] + nb.zs[EZ(i) + 1];
         if (to_wall) {
-            q_store<NTS>(qb + OPP(i) * N + k, post[i]);
+            q_store<NTS>(qb + OPP(i) * QS + k, post[i]);
         } else if (XSLOT(i) < 0) {
-            q_store<NTS>(qb + i * N + x + off, post[i]);
+            q_store<NTS>(qb + i * QS + x + off, post[i]);
         } else {
             // arriving at column x from column x - e_x of the same row
             int xs = x - EX(i);
             xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
             const int src = row0 + xs;
-            if (src >= k0 && src < kend) q_store<NTS>(qb + i * N + x + off, lds[XSLOT(i) * S + (src - k0)]);
+            if (src >= k0 && src < kend) q_store<NTS>(qb + i * QS + x + off, lds[XSLOT(i) * S + (src - k0)]);
             // leaving for column x + e_x: stored here when that column's
             // thread belongs to another span
             int xd = x + EX(i);
             xd = xd < 0 ? xd + g.nx : (xd >= g.nx ? xd - g.nx : xd);
             const int dst = row0 + xd;
-            if (dst < k0 || dst >= kend) q_store<NTS>(qb + i * N + xd + off, post[i]);
+            if (dst < k0 || dst >= kend) q_store<NTS>(qb + i * QS + xd + off, post[i]);
         }
     }
 }
@@ -349,7 +349,7 @@ __device__ __forceinline__ void moments_node(const T* __restrict__ q_in, const T
     }
     T q[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) q[i] = q_in[i * N + k];
+    for (int i = 0; i < 19; ++i) q[i] = q_in[i * (size_t)a.g.qs + k];
     T rho, drho, jx, jy, jz;
     node_moments<T, SHIFT>(q, rho, drho, jx, jy, jz);
     T Fx = rho * a.gx, Fy = rho * a.gy, Fz = rho * a.gz;
@@ -383,14 +383,16 @@ __global__ void __launch_bounds__(256) k_fill(T* __restrict__ p, T v, int n)
     if (k < n) p[k] = v;
 }
 
-// Rest state: q = 0 (shifted) or q_i = w_i (plain).
+// Rest state: q = 0 (shifted) or q_i = w_i (plain), over all qs values of
+// each direction (the padding after the N nodes too, so the buffer holds no
+// undefined values).
 template <typename T, bool SHIFT>
-__global__ void __launch_bounds__(256) k_rest(T* __restrict__ q, int N)
+__global__ void __launch_bounds__(256) k_rest(T* __restrict__ q, int qs)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N) return;
+    if (k >= qs) return;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) q[(size_t)i * N + k] = SHIFT ? T(0) : WGT<T>(i);
+    for (int i = 0; i < 19; ++i) q[(size_t)i * qs + k] = SHIFT ? T(0) : WGT<T>(i);
 }
 
 // Equilibrium at rho = 1 and velocity u0 minus its checkerboard components
@@ -414,7 +416,7 @@ __global__ void __launch_bounds__(256) k_equilibrium(T* __restrict__ q, const T*
     for (int i = 0; i < 19; ++i) {
         const T eu = T(EX(i)) * ux + T(EY(i)) * uy + T(EZ(i)) * uz;
         const T poly = LIN<T>(i) * eu + WGT<T>(i) * (T(4.5) * eu * eu - T(1.5) * uu);
-        q[i * n + k] = SHIFT ? poly : WGT<T>(i) + poly;
+        q[i * (size_t)g.qs + k] = SHIFT ? poly : WGT<T>(i) + poly;
     }
 }
 

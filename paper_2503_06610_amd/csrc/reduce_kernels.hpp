@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_obs_partial(const T* __restrict
         bool bad = false;
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-            const double qi = (double)q[i * N + k];
+            const double qi = (double)q[i * (size_t)a.g.qs + k];
             bad |= !isfinite(qi);
             s += qi;
             jx += EX(i) * qi;

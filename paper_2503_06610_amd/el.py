@@ -22,6 +22,7 @@ EL_PERIODIC_Z, EL_NO_COUPLING, EL_NO_RENORM_PREDICTOR, EL_ALLOW_UNSTABLE, EL_FRE
 EL_FRANK3, EL_FREE_WALLS = 128, 256
 EL_FORCE_ONE_PASS, EL_FORCE_TWO_PASS = 32, 64
 EL_BUF_Q, EL_BUF_VEC3, EL_BUF_SCRATCH, EL_BUF_HALO, EL_BUF_FD_HALO = 0, 1, 2, 3, 4
+EL_Q_ALIGN = 64  # values per direction of q are padded to a multiple of this (include/el.h)
 
 PRECISIONS = {"f64": EL_F64, "f64_shifted": EL_F64_SHIFTED, "f32": EL_F32, "f32_shifted": EL_F32_SHIFTED}
 
@@ -241,7 +242,9 @@ class Lattice:
         self.dtype = torch.float64 if precision.startswith("f64") else torch.float32
         self.N = prob.fluid_nodes
         dev = torch.device(device)
-        self.q = [torch.empty((19,) + prob.shape(1)[1:], dtype=self.dtype, device=dev) for _ in range(2)]
+        # q: 19 direction arrays of N values, each padded to qs (a multiple of EL_Q_ALIGN)
+        self.qs = -(-self.N // EL_Q_ALIGN) * EL_Q_ALIGN
+        self.q = [torch.empty((19, self.qs), dtype=self.dtype, device=dev) for _ in range(2)]
         mk = lambda: torch.zeros(prob.shape(3), dtype=self.dtype, device=dev)
         self.n, self.n_pred, self.dndt, self.u, self.F = mk(), mk(), mk(), mk(), mk()
         nscratch = buffer_bytes(self.params, EL_BUF_SCRATCH)
@@ -388,17 +391,21 @@ class Lattice:
                                     C.c_void_p(lower.data_ptr()), C.c_void_p(upper.data_ptr()), _stream_ptr(stream)),
                "el_fd_stage")
 
+    def _field(self, name: str):
+        if name == "q":  # the N values of each direction, without the padding
+            return self.q_current()[:, :self.N].view((19,) + self.prob.shape(1)[1:])
+        return {"n": self.n, "nP": self.n_pred, "u": self.u, "F": self.F}[name]
+
     def get(self, name: str) -> np.ndarray:
-        """Host copy (float64) of a field: q, n, nP, u, F."""
+        """Host copy (float64) of a field: q ([19][nzf][ny][nx]), n, nP, u, F."""
         import torch
         torch.cuda.synchronize()
-        t = {"q": self.q_current(), "n": self.n, "nP": self.n_pred, "u": self.u, "F": self.F}[name]
-        return t.detach().to("cpu", torch.float64).numpy()
+        return self._field(name).detach().to("cpu", torch.float64).numpy()
 
     def set(self, name: str, arr):
         """Overwrite a field from host data (tests and warm starts)."""
         import torch
-        t = {"q": self.q_current(), "n": self.n, "nP": self.n_pred, "u": self.u, "F": self.F}[name]
+        t = self._field(name)
         t.copy_(torch.as_tensor(np.ascontiguousarray(arr)).reshape(t.shape).to(t.dtype))
 
 

@@ -144,12 +144,17 @@ def test_validate_rejects_high_mach_and_overflowing_lattice():
     assert el.validate(el.make_params(big, "f32")) == el.EL_EINVAL
 
 
-def test_buffer_bytes():
+@pytest.mark.parametrize("ragged", [False, True])
+def test_buffer_bytes(ragged):
     prob = inputs.workload_c1()[0]
+    if ragged:  # N = 13 * 7 * 9 = 819, padded to 832 values per direction of q
+        prob = prob.with_(nx=13, ny=7, nz=11)
     N = prob.fluid_nodes
     for prec, ts in (("f64", 8), ("f32_shifted", 4)):
         p = el.make_params(prob, prec)
-        assert el.buffer_bytes(p, el.EL_BUF_Q) == 19 * N * ts
+        qs = -(-N // 64) * 64  # each direction padded to a multiple of 64 values
+        assert qs % el.EL_Q_ALIGN == 0 and qs - N < 64
+        assert el.buffer_bytes(p, el.EL_BUF_Q) == 19 * qs * ts
         assert el.buffer_bytes(p, el.EL_BUF_VEC3) == 3 * N * ts
         assert el.buffer_bytes(p, el.EL_BUF_SCRATCH) == 131072 + 9 * N * ts
         assert el.buffer_bytes(p, el.EL_BUF_HALO) == 2 * 5 * prob.nx * prob.nzf * ts
