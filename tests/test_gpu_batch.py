@@ -299,11 +299,14 @@ def test_span_kernel_matches_generic_kernel():
     multiple of 64) or the span kernel; the batch uses the generic push
     (persistent grid) or the span kernel on its tiles, here with spans shorter
     and longer than the rows.  All must agree bitwise (same collision code,
-    only the data movement differs)."""
+    only the data movement differs).  The 37x11x9 channel's q padding (2849
+    values per direction, padded to 2880) holds NaN in the batch, which no
+    kernel may read."""
     import torch
     mat = inputs.set_a()
     chans = []
-    for i, (nx, ny, nz, r) in enumerate([(64, 9, 10, 1), (128, 5, 7, 3), (192, 3, 6, 2), (100, 4, 6, 2)]):
+    for i, (nx, ny, nz, r) in enumerate([(64, 9, 10, 1), (128, 5, 7, 3), (192, 3, 6, 2), (100, 4, 6, 2),
+                                         (37, 11, 9, 2)]):
         prob = inputs.channel(nx, ny, nz, mat, g=(2e-6, 1e-7, 0.0), K=1e-3, q0=2 * math.pi / 16, fd_ratio=r)
         chans.append((prob, inputs.director_tilt(prob, seed=30 + i, amplitude=0.3)))
     singles = _lattices(chans, "f32_shifted")
@@ -312,6 +315,10 @@ def test_span_kernel_matches_generic_kernel():
     lats = _lattices(chans, "f32_shifted")
     for tuning in ((256, 4, 256, 4), (256, 0, 256, 0), (64, 0, 128, 0), (1024, 0, 256, 0)):  # generic; spans
         lats = _lattices(chans, "f32_shifted")
+        assert lats[-1].qs > lats[-1].N
+        for lat in lats:
+            for q in lat.q:
+                q[:, lat.N:] = float("nan")
         b = el.Batch(lats, tuning=tuning)
         b.step(17)
         b.moments()

@@ -498,3 +498,32 @@ def test_stream_copy_copies_exactly(nbytes):
     torch.cuda.synchronize()
     assert torch.equal(dst[:nbytes], src)
     assert int(dst[nbytes:].count_nonzero()) == 0
+
+
+def test_q_padding_is_never_read():
+    """q's direction arrays are padded to a multiple of 64 values; no call may
+    read the padding.  NaN written into it (both buffers) must leave the state
+    after LBM steps, FD steps, a warm start and the observables bitwise what
+    a lattice with the padding as initialised gives."""
+    import torch
+    prob = inputs.channel(13, 7, 11, inputs.set_a(), g=(2e-6, 1e-6, 0.0), K=2e-3, q0=2 * math.pi / 12,
+                          fd_ratio=3)  # N = 13 * 7 * 9 = 819, padded to 832
+    n0 = inputs.director_tilt(prob, seed=17, amplitude=0.3)
+    lats = []
+    for poison in (False, True):
+        lat = el.Lattice(prob, "f32_shifted")
+        lat.init_lattice(n0)
+        assert lat.qs == 832 and lat.qs > lat.N
+        if poison:
+            for q in lat.q:
+                q[:, lat.N:] = float("nan")
+        lat.run(10)
+        lat.init_flow(lat.u.clone())
+        lat.run(8)
+        lats.append(lat)
+    torch.cuda.synchronize()
+    a, b = lats
+    for name in ("q", "n", "u", "F"):
+        assert np.array_equal(a.get(name), b.get(name)), name
+    oa, ob = a.observables(), b.observables()
+    assert ob["nonfinite"] == 0 and oa["mass"] == ob["mass"] and np.array_equal(oa["mom"], ob["mom"])
