@@ -36,6 +36,7 @@ METRIC = "coupled MLUPS FP32-shifted vs FP64 at <=1e-4 rel-L2 velocity error; % 
 HBM_PEAK_GBS = 8000.0
 OBS_EVERY = 100  # FP64 observables inside the timed loop, every 100 steps
 EVENT_EVERY = 10  # LBM / FD launch groups timed with HIP events: every 10th
+PHASE_STEPS = 4000  # untimed steps for the per-phase kernel times after the timed run
 GATE_STEPS = 20000  # the precision study's stated length
 ROOFLINE_LAUNCHES = 200
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "lbm_step_traffic.json")
@@ -50,33 +51,57 @@ def lbm_source_hash() -> str:
 
 
 def timed_run(prob, n0, precision, steps, warmup):
-    """W untimed steps, then `steps` timed hybrid steps; returns timings and
-    the final fields (host copies)."""
+    """W untimed steps, then `steps` timed hybrid steps through el_run in blocks
+    of OBS_EVERY steps, each followed by the FP64 observables on the device;
+    then, untimed, the per-phase kernel times (phase_times).  Returns timings
+    and the final fields (host copies)."""
     import torch
     from paper_2503_06610_amd import el
 
-    stream = torch.cuda.current_stream()
     lat = el.Lattice(prob, precision)
     lat.init_lattice(n0)
     lat.run(warmup)
-    r = prob.fd_ratio
-    # every multiple of r and of OBS_EVERY ends a launch group
-    nint = steps // r + steps // OBS_EVERY + 2
     from paper_2503_06610_amd.el import OBS_DOUBLES
     obs_ring = torch.zeros((steps // OBS_EVERY + 1, OBS_DOUBLES), dtype=torch.float64, device=lat.n.device)
     nobs = 0
-    lbm_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nint)]
-    fd_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nint)]
-    lbm_counts = []
-    nfd = 0
-    nlbm = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
-    k = 0
     while done < steps:
-        n = min(r - (lat.step % r), OBS_EVERY - (lat.step % OBS_EVERY), steps - done)
-        # HIP events around every EVENT_EVERY-th launch group only (events add gaps)
+        n = min(OBS_EVERY - (lat.step % OBS_EVERY), steps - done)
+        lat.run(n)
+        done += n
+        if lat.step % OBS_EVERY == 0:
+            # FP64 observables on the device (no host synchronisation)
+            lat.observables_to(obs_ring[nobs].data_ptr())
+            nobs += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    from paper_2503_06610_amd.el import el_obs
+    ring = obs_ring[:nobs].cpu().numpy()
+    ring_obs = [el_obs.from_buffer_copy(ring[i].tobytes()) for i in range(nobs)]
+    out = {"wall_s": wall, "u": lat.get("u"), "n": lat.get("n"), "obs": lat.observables(),
+           "timed_obs": {"count": nobs, "nonfinite": int(sum(o.nonfinite for o in ring_obs)),
+                         "max_u": max((o.max_u for o in ring_obs), default=0.0)}}
+    out.update(phase_times(lat, min(steps, PHASE_STEPS)))
+    return out
+
+
+def phase_times(lat, steps):
+    """Kernel time of the LBM step and of one FD step (moments, predictor,
+    corrector, stress, divergence: el_step_director as called on its own),
+    from `steps` further untimed steps taken as separate calls, with HIP
+    events around every EVENT_EVERY-th launch group."""
+    import torch
+    stream = torch.cuda.current_stream()
+    r = lat.prob.fd_ratio
+    nint = steps // r + 2
+    lbm_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nint)]
+    fd_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nint)]
+    lbm_counts = []
+    nfd = nlbm = done = k = 0
+    while done < steps:
+        n = min(r - (lat.step % r), steps - done)
         sample = k % EVENT_EVERY == 0
         if sample:
             lbm_ev[nlbm][0].record(stream)
@@ -94,26 +119,13 @@ def timed_run(prob, n0, precision, steps, warmup):
             if sample:
                 fd_ev[nfd][1].record(stream)
                 nfd += 1
-        elif done == steps:
-            lat.moments()
-        if lat.step % OBS_EVERY == 0:
-            # FP64 observables on the device (no host synchronisation)
-            lat.observables_to(obs_ring[nobs].data_ptr())
-            nobs += 1
         k += 1
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     lbm_ms = sum(lbm_ev[i][0].elapsed_time(lbm_ev[i][1]) for i in range(nlbm))
     fd_ms = sum(fd_ev[i][0].elapsed_time(fd_ev[i][1]) for i in range(nfd))
-    from paper_2503_06610_amd.el import el_obs
-    ring = obs_ring[:nobs].cpu().numpy()
-    ring_obs = [el_obs.from_buffer_copy(ring[i].tobytes()) for i in range(nobs)]
-    out = {"wall_s": wall, "lbm_kernel_ms_avg": lbm_ms / sum(lbm_counts), "fd_ms_avg": fd_ms / max(nfd, 1),
-           "n_fd": nfd, "timed_groups": {"lbm": nlbm, "fd": nfd, "every": EVENT_EVERY},
-           "timed_lbm_launches": sum(lbm_counts), "u": lat.get("u"), "n": lat.get("n"), "obs": lat.observables(),
-           "timed_obs": {"count": nobs, "nonfinite": int(sum(o.nonfinite for o in ring_obs)),
-                         "max_u": max((o.max_u for o in ring_obs), default=0.0)}}
-    return out
+    return {"lbm_kernel_ms_avg": lbm_ms / max(sum(lbm_counts), 1), "fd_ms_avg": fd_ms / max(nfd, 1), "n_fd": nfd,
+            "timed_groups": {"lbm": nlbm, "fd": nfd, "every": EVENT_EVERY},
+            "timed_lbm_launches": sum(lbm_counts)}
 
 
 def precision_gate(prob, n0, steps=GATE_STEPS):
@@ -363,7 +375,8 @@ def main():
     roofline_headline = {"achieved": round(bytes_per_launch / lbm_s / 1e9, 1), "unit": "GB/s",
                          "frac": round(bytes_per_launch / lbm_s / 1e9 / HBM_PEAK_GBS, 4),
                          "avg_launch_us": round(lbm_s * 1e6, 3), "timed_launches": res32["timed_lbm_launches"],
-                         "note": "MALL-resident working set (2 x 77 MB q buffers)"}
+                         "note": "MALL-resident working set (2 x 77 MB q buffers); HIP events around every "
+                                 f"{EVENT_EVERY}th LBM launch group of {PHASE_STEPS} steps after the timed run"}
     # whole-step algorithmic bytes s*(41 + 15/r) per fluid-node update
     step_bytes = 4 * (41 + 15.0 / prob.fd_ratio)
     step_frac = mlups * 1e6 * step_bytes / (HBM_PEAK_GBS * 1e9)
@@ -379,7 +392,9 @@ def main():
         "roofline": roofline,
         "roofline_headline_workload": roofline_headline,
         "step_roofline": {"bytes_per_update": step_bytes, "frac": round(step_frac, 4),
-                          "fd_step_us": round(res32["fd_ms_avg"] * 1e3, 2)},
+                          "fd_step_us": round(res32["fd_ms_avg"] * 1e3, 2),
+                          "fd_step_note": "moments + el_step_director called on their own (el_run leaves the "
+                                          "stress divergence to the next LBM step)"},
         "precision_check": check,
         "observables": {"mass": res32["obs"]["mass"], "max_u": res32["obs"]["max_u"],
                         "max_unit_dev": res32["obs"]["max_unit_dev"], "nonfinite": res32["obs"]["nonfinite"],

@@ -295,6 +295,11 @@ int el_force(const el_params* p, el_state* s, void* stream);
 /* The hybrid loop of Sec. II D for T more LBM steps: after every LBM step
  * whose counter t satisfies t % r == 0, the moments, the predictor-corrector
  * and the new force.  u is left holding the velocity of the last step.
+ * Where the force takes two passes (stress, then its divergence) and there
+ * are no obstacles, the divergence is formed by the first LBM step after the
+ * FD step instead of a pass of its own (the same arithmetic: F^LC, u, q and n
+ * are bitwise those of the separate calls; the scratch buffer holds the
+ * stress between the two, and F^LC is formed before el_run returns).
  * Kernel launches only (no allocation, copy, memset or synchronisation), so
  * a caller may capture it into a graph; the host-side counter s->step and
  * parity then advance at capture, not at replay, and are the caller's to

@@ -110,10 +110,13 @@ using namespace elh;
 
 
 // --------------------------------------------------------------------------
+// sigf_first: the first step forms F^LC from the stress in scratch (the
+// divergence an FD step left to it, see el_run) and stores it to s->F.
 template <typename T, bool SHIFT>
-int launch_lbm_steps(const el_params* p, el_state* s, int nsteps, hipStream_t st)
+int launch_lbm_steps(const el_params* p, el_state* s, int nsteps, hipStream_t st, bool sigf_first = false)
 {
     el::LbmArgs<T> a = lbm_args<T>(p);
+    if (sigf_first && s->solid) return fail(EL_EINVAL, "internal: stress-fed LBM step with obstacles");
     const int grid = grid_for(a.g.N);
     constexpr int SPAN = 256;
     if (s->solid) {
@@ -154,7 +157,23 @@ int launch_lbm_steps(const el_params* p, el_state* s, int nsteps, hipStream_t st
         // 128x128x64 FP64 49.6 -> 49.5; with streaming stores (256x256x48
         // FP64) 171.2 -> 172.3, so those keep one order.
         const int rev = nts ? 0 : (int)(s->step & 1);
-        if (one_row && nts)
+        if (k == 0 && sigf_first) {
+            el::LbmArgs<T> as = a;
+            as.sig = sigma_of<T>(s);
+            as.Fout = static_cast<T*>(s->F);
+            if (one_row && nts)
+                hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, true, true>), dim3(grid_rows), dim3(threads), shmem,
+                                   st, qa, qb, F, as, rev);
+            else if (one_row)
+                hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, false, true>), dim3(grid_rows), dim3(threads), shmem,
+                                   st, qa, qb, F, as, rev);
+            else if (nts)
+                hipLaunchKernelGGL((el::k_lbm_push_span<T, SHIFT, true, true>), dim3(grid_rows), dim3(threads), shmem,
+                                   st, qa, qb, F, as, rev);
+            else
+                hipLaunchKernelGGL((el::k_lbm_push_span<T, SHIFT, false, true>), dim3(grid_rows), dim3(threads),
+                                   shmem, st, qa, qb, F, as, rev);
+        } else if (one_row && nts)
             hipLaunchKernelGGL((el::k_lbm_push_row<T, SHIFT, true>), dim3(grid_rows), dim3(threads), shmem, st, qa,
                                qb, F, a, rev);
         else if (one_row)
@@ -189,8 +208,11 @@ int launch_moments(const el_params* p, el_state* s, hipStream_t st)
     return check_launch("k_moments");
 }
 
+// deferred != nullptr: where the force takes the two passes, only the stress
+// is written and *deferred is set; the next LBM step (el_run) then forms F^LC
+// from it.
 template <typename T>
-int launch_force(const el_params* p, el_state* s, hipStream_t st)
+int launch_force(const el_params* p, el_state* s, hipStream_t st, bool* deferred = nullptr)
 {
     el::FdArgs<T> a = fd_args<T>(p);
     a.solid = static_cast<const unsigned char*>(s->solid);
@@ -216,17 +238,31 @@ int launch_force(const el_params* p, el_state* s, hipStream_t st)
     else
         hipLaunchKernelGGL((el::k_fd_stress<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
                            static_cast<const T*>(s->u), sig, a, fd_strip(a.g));
+    if (deferred && !s->solid) {
+        *deferred = true;
+        return check_launch("stress kernel");
+    }
     hipLaunchKernelGGL((el::k_fd_divergence<T>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(sig),
                        static_cast<T*>(s->F), a, fd_strip(a.g));
     return check_launch("force kernels");
 }
 
+// F^LC from the stress an FD step left in scratch (the second force pass).
 template <typename T>
-int launch_director(const el_params* p, el_state* s, hipStream_t st)
+int launch_divergence(const el_params* p, el_state* s, hipStream_t st)
+{
+    el::FdArgs<T> a = fd_args<T>(p);
+    hipLaunchKernelGGL((el::k_fd_divergence<T>), dim3(grid_for(a.g.N)), dim3(BLOCK), 0, st,
+                       static_cast<const T*>(sigma_of<T>(s)), static_cast<T*>(s->F), a, fd_strip(a.g));
+    return check_launch("k_fd_divergence");
+}
+
+template <typename T>
+int launch_director(const el_params* p, el_state* s, hipStream_t st, bool* deferred = nullptr)
 {
     el::FdArgs<T> a = fd_args<T>(p);
     a.solid = static_cast<const unsigned char*>(s->solid);
-    if (p->flags & EL_FREEZE_DIRECTOR) return launch_force<T>(p, s, st);
+    if (p->flags & EL_FREEZE_DIRECTOR) return launch_force<T>(p, s, st, deferred);
     const int grid = grid_for(a.g.N);
     if (frank3(p)) {
         hipLaunchKernelGGL((el::k_fd_predictor<T, true>), dim3(grid), dim3(BLOCK), 0, st, static_cast<const T*>(s->n),
@@ -245,7 +281,7 @@ int launch_director(const el_params* p, el_state* s, hipStream_t st)
     }
     int rc = check_launch("director kernels");
     if (rc != EL_OK) return rc;
-    return launch_force<T>(p, s, st);
+    return launch_force<T>(p, s, st, deferred);
 }
 
 template <typename T, bool SHIFT>
@@ -336,6 +372,15 @@ int error_impl(const el_params* p, const void* a, const double* ref, int ncomp, 
     case EL_F64_SHIFTED: { using T = double; constexpr bool SH = true; return CALL; } \
     case EL_F32: { using T = float; constexpr bool SH = false; return CALL; } \
     default: { using T = float; constexpr bool SH = true; return CALL; } \
+    }
+
+// The same dispatch, storing the result in rc instead of returning it.
+#define EL_DISPATCH_RC(p, rc, CALL)                            \
+    switch ((p)->precision) {                                  \
+    case EL_F64: { using T = double; constexpr bool SH = false; rc = CALL; break; } \
+    case EL_F64_SHIFTED: { using T = double; constexpr bool SH = true; rc = CALL; break; } \
+    case EL_F32: { using T = float; constexpr bool SH = false; rc = CALL; break; } \
+    default: { using T = float; constexpr bool SH = true; rc = CALL; break; } \
     }
 
 }  // namespace
@@ -564,17 +609,27 @@ int el_run(const el_params* p, el_state* s, int64_t T, void* stream)
     if ((rc = state_checks(p, s)) != EL_OK) return rc;
     if (T < 0) return fail(EL_EINVAL, "T = %lld", (long long)T);
     const int r = p->fd_ratio;
+    hipStream_t st = static_cast<hipStream_t>(stream);
     int64_t left = T;
+    // pending: the last FD step left F^LC as the stress in scratch, and the
+    // next LBM step forms it (the divergence's stencil then costs no pass of
+    // its own; the force and the state are bitwise those of el_step_director)
+    bool pending = false;
     while (left > 0) {
         // LBM steps up to the next multiple of r (or the end)
         int64_t to_fd = r - (s->step % r);
         const int n = (int)(left < to_fd ? left : to_fd);
-        if ((rc = el_step_lbm(p, s, n, 0, stream)) != EL_OK) return rc;
+        EL_DISPATCH_RC(p, rc, (launch_lbm_steps<T, SH>(p, s, n, st, pending)));
+        if (rc != EL_OK) return rc;
+        pending = false;
         left -= n;
         if ((rc = el_moments(p, s, stream)) != EL_OK) return rc;
-        if (s->step % r == 0)
-            if ((rc = el_step_director(p, s, stream)) != EL_OK) return rc;
+        if (s->step % r == 0) {
+            rc = is_f64(p) ? launch_director<double>(p, s, st, &pending) : launch_director<float>(p, s, st, &pending);
+            if (rc != EL_OK) return rc;
+        }
     }
+    if (pending) return is_f64(p) ? launch_divergence<double>(p, s, st) : launch_divergence<float>(p, s, st);
     return EL_OK;
 }
 

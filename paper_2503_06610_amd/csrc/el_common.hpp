@@ -90,6 +90,32 @@ __device__ inline Nbr make_nbr(const Geom& g, int x, int y, int z)
     return n;
 }
 
+// F^LC_i = sum_b d_b sigma_ib at node (x, y, z) by central differences, with
+// zero stress at a wall across z (Sec. II B force).  sig: [9][N], component
+// i * 3 + b.  Shared by the divergence kernel and the LBM step that forms the
+// force from the stress on its way, so both give the same bits.
+template <typename T>
+__device__ __forceinline__ void sigma_divergence(const T* __restrict__ sig, const Geom& g, int x, int y, int z,
+                                                 T (&F)[3])
+{
+    const size_t N = (size_t)g.N;
+    const Nbr nb = make_nbr(g, x, y, z);
+    const int plus[3] = {nb.xp, nb.yp, nb.zp};
+    const int minus[3] = {nb.xm, nb.ym, nb.zm};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        T div = T(0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const T* s = sig + (i * 3 + b) * N;
+            const T sp = (b == 2 && nb.wall_zp) ? T(0) : s[plus[b]];
+            const T sm = (b == 2 && nb.wall_zm) ? T(0) : s[minus[b]];
+            div += T(0.5) * (sp - sm);
+        }
+        F[i] = div;
+    }
+}
+
 // The workgroups of a launch go to the chip's eight XCDs (each with its own
 // L2) round-robin by linear block index.  xcd_remap renumbers a block so that
 // each XCD receives one contiguous range of logical blocks: the rows and

@@ -487,21 +487,10 @@ __device__ __forceinline__ void divergence_node(const T* __restrict__ sig, T* __
     }
     int x, y, z;
     node_coords(a.g, k, x, y, z);
-    const Nbr nb = make_nbr(a.g, x, y, z);
-    const int plus[3] = {nb.xp, nb.yp, nb.zp};
-    const int minus[3] = {nb.xm, nb.ym, nb.zm};
+    T f[3];
+    sigma_divergence(sig, a.g, x, y, z, f);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        T div = T(0);
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const T* s = sig + (i * 3 + b) * N;
-            const T sp = (b == 2 && nb.wall_zp) ? T(0) : s[plus[b]];
-            const T sm = (b == 2 && nb.wall_zm) ? T(0) : s[minus[b]];
-            div += T(0.5) * (sp - sm);
-        }
-        F[i * N + k] = div;
-    }
+    for (int i = 0; i < 3; ++i) F[i * N + k] = f[i];
 }
 
 template <typename T, bool F3 = false>

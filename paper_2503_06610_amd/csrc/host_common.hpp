@@ -114,6 +114,8 @@ el::LbmArgs<T> lbm_args(const el_params* p)
     a.gz = T(p->g[2]);
     a.coupling = coupling(p) ? 1 : 0;
     a.solid = nullptr;
+    a.sig = nullptr;
+    a.Fout = nullptr;
     return a;
 }
 

@@ -55,6 +55,8 @@ struct LbmArgs {
     T gx, gy, gz;  // body acceleration (force density rho g)
     int coupling;  // 0: F^LC is treated as zero and not read
     const unsigned char* solid;  // obstacle mask (1 = solid node inside the channel), or nullptr
+    const T* sig;  // SIGF kernels: the stress [9][N] whose divergence is F^LC ...
+    T* Fout;       // ... written here ([3][N]) as the step forms it
 };
 
 // Density and momentum of one node: rho - 1 = sum q (shifted) or rho = sum f,
@@ -83,7 +85,9 @@ __device__ inline void node_moments(const T (&q)[19], T& rho, T& drho, T& jx, T&
 // F = rho g + F^LC, BGK relaxation toward the (shifted) equilibrium and the
 // Guo source.  Shared by every LBM kernel, so all of them perform the same
 // arithmetic.
-template <typename T, bool SHIFT>
+// SIGF: F^LC is not read from Flc but formed from the stress a.sig (the
+// divergence the FD step would otherwise finish with) and stored to a.Fout.
+template <typename T, bool SHIFT, bool SIGF = false>
 __device__ __forceinline__ void lbm_collide(const T* __restrict__ qa, const T* __restrict__ Flc, const LbmArgs<T>& a,
                                             int k, T (&post)[19])
 {
@@ -96,9 +100,21 @@ __device__ __forceinline__ void lbm_collide(const T* __restrict__ qa, const T* _
     node_moments<T, SHIFT>(q, rho, drho, jx, jy, jz);
     T Fx = rho * a.gx, Fy = rho * a.gy, Fz = rho * a.gz;
     if (a.coupling) {
-        Fx += Flc[k];
-        Fy += Flc[N + k];
-        Fz += Flc[2 * N + k];
+        if constexpr (SIGF) {
+            const int x = k % a.g.nx, t = k / a.g.nx;
+            T f[3];
+            sigma_divergence(a.sig, a.g, x, t % a.g.ny, t / a.g.ny, f);
+            a.Fout[k] = f[0];
+            a.Fout[N + k] = f[1];
+            a.Fout[2 * N + k] = f[2];
+            Fx += f[0];
+            Fy += f[1];
+            Fz += f[2];
+        } else {
+            Fx += Flc[k];
+            Fy += Flc[N + k];
+            Fz += Flc[2 * N + k];
+        }
     }
     // momentum rho u = j + F/2; the equilibrium's linear term is taken from it
     // directly, so its first moment is rho u without the rounding of
@@ -212,7 +228,7 @@ __host__ __device__ constexpr int XSLOT(int i)
 // through LDS (lds: [10][nx], the directions with e_x != 0) to the thread
 // owning their destination column, so every store writes a whole row; the
 // arithmetic is lbm_collide's.  NTS: streaming stores (see q_store).
-template <typename T, bool SHIFT, bool NTS = false>
+template <typename T, bool SHIFT, bool NTS = false, bool SIGF = false>
 __device__ __forceinline__ void lbm_row(const T* __restrict__ qa, T* __restrict__ qb, const T* __restrict__ Flc,
                                         const LbmArgs<T>& a, int r, T* lds)
 {
@@ -221,7 +237,7 @@ __device__ __forceinline__ void lbm_row(const T* __restrict__ qa, T* __restrict_
     const size_t QS = (size_t)g.qs;
     T post[19];
     const int k = x + g.nx * r;
-    lbm_collide<T, SHIFT>(qa, Flc, a, k, post);
+    lbm_collide<T, SHIFT, SIGF>(qa, Flc, a, k, post);
 #pragma unroll
     for (int i = 0; i < 19; ++i)
         if (XSLOT(i) >= 0) lds[XSLOT(i) * g.nx + x] = post[i];
@@ -253,7 +269,7 @@ __device__ __forceinline__ void lbm_row(const T* __restrict__ qa, T* __restrict_
 // source column lies outside the span (the rows the span cuts), the source's
 // own thread stores it instead, so every (node, direction) is written once.
 // Every thread of the block must call this (barrier).
-template <typename T, bool SHIFT, bool NTS = false>
+template <typename T, bool SHIFT, bool NTS = false, bool SIGF = false>
 __device__ __forceinline__ void lbm_span(const T* __restrict__ qa, T* __restrict__ qb, const T* __restrict__ Flc,
                                          const LbmArgs<T>& a, int k0, T* lds)
 {
@@ -266,7 +282,7 @@ __device__ __forceinline__ void lbm_span(const T* __restrict__ qa, T* __restrict
     const size_t QS = (size_t)g.qs;
     T post[19];
     if (active) {
-        lbm_collide<T, SHIFT>(qa, Flc, a, k, post);
+        lbm_collide<T, SHIFT, SIGF>(qa, Flc, a, k, post);
 #pragma unroll
         for (int i = 0; i < 19; ++i)
             if (XSLOT(i) >= 0) lds[XSLOT(i) * S + j] = post[i];
@@ -305,24 +321,24 @@ __device__ __forceinline__ void lbm_span(const T* __restrict__ qa, T* __restrict
 // rev != 0 numbers the blocks from the last row down (the hardware starts the
 // low block indices first), so the step begins where a forward step ended;
 // the results do not depend on the order.
-template <typename T, bool SHIFT, bool NTS>
+template <typename T, bool SHIFT, bool NTS, bool SIGF = false>
 __global__ void __launch_bounds__(1024) k_lbm_push_row(const T* __restrict__ qa, T* __restrict__ qb,
                                                       const T* __restrict__ Flc, LbmArgs<T> a, int rev)
 {
     extern __shared__ unsigned char lbm_smem[];
     const int b = rev ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x;
-    lbm_row<T, SHIFT, NTS>(qa, qb, Flc, a, b, reinterpret_cast<T*>(lbm_smem));
+    lbm_row<T, SHIFT, NTS, SIGF>(qa, qb, Flc, a, b, reinterpret_cast<T*>(lbm_smem));
 }
 
 // Spans of blockDim consecutive nodes; dynamic LDS 10 blockDim values; rev as
 // in k_lbm_push_row.
-template <typename T, bool SHIFT, bool NTS>
+template <typename T, bool SHIFT, bool NTS, bool SIGF = false>
 __global__ void __launch_bounds__(1024) k_lbm_push_span(const T* __restrict__ qa, T* __restrict__ qb,
                                                        const T* __restrict__ Flc, LbmArgs<T> a, int rev)
 {
     extern __shared__ unsigned char lbm_smem[];
     const int b = rev ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x;
-    lbm_span<T, SHIFT, NTS>(qa, qb, Flc, a, b * (int)blockDim.x, reinterpret_cast<T*>(lbm_smem));
+    lbm_span<T, SHIFT, NTS, SIGF>(qa, qb, Flc, a, b * (int)blockDim.x, reinterpret_cast<T*>(lbm_smem));
 }
 
 template <typename T, bool SHIFT, bool MASK = false>
