@@ -20,6 +20,7 @@ constexpr int OBS_NSUM = OBS_NBASE + 5 * OBS_NT;  // + per tube: w, w cos x, w s
 constexpr int OBS_NMAX = 3;     // max |u|, max ||n| - 1|, nonfinite
 constexpr int OBS_NQ = OBS_NSUM + OBS_NMAX;
 constexpr int OBS_MAX_BLOCKS = 256;  // partial rows of the observables: 256 * 50 doubles
+constexpr int OBS_BATCH = 4;         // nodes whose loads a thread issues together
 constexpr int ERR_NQ = 10;      // up to 4 + 2*3 sums
 
 __device__ inline double wave_sum(double v)
@@ -115,61 +116,86 @@ __global__ void __launch_bounds__(RED_THREADS) k_obs_partial(const T* __restrict
     for (int j = 0; j < OBS_NQ; ++j) v[j] = 0.0;
     const size_t N = (size_t)a.g.N;
     const double two_pi = 6.283185307179586476925286766559;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < a.g.N; k += gridDim.x * blockDim.x) {
-        if (a.solid && a.solid[k]) continue;  // fluid nodes only
-        double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-        bool bad = false;
+    // A thread visits nodes k0, k0 + stride, ... in that order; the values of
+    // OBS_BATCH consecutive ones are loaded before any is summed, so their
+    // loads are in flight together (one wave per SIMD has nothing else to hide
+    // the latency with).
+    const int stride = gridDim.x * blockDim.x;
+    for (int k0 = blockIdx.x * blockDim.x + threadIdx.x; k0 < a.g.N; k0 += OBS_BATCH * stride) {
+        T qv[OBS_BATCH][19], fv[OBS_BATCH][3], uv[OBS_BATCH][3], nv[OBS_BATCH][3];
+        bool skip[OBS_BATCH];
 #pragma unroll
-        for (int i = 0; i < 19; ++i) {
-            const double qi = (double)q[i * (size_t)a.g.qs + k];
-            bad |= !isfinite(qi);
-            s += qi;
-            jx += EX(i) * qi;
-            jy += EY(i) * qi;
-            jz += EZ(i) * qi;
-        }
-        const double rho = a.shifted ? 1.0 + s : s;
-        double F[3] = {rho * a.gx, rho * a.gy, rho * a.gz};
-        double uu = 0.0, nn = 0.0, nz = 0.0;
+        for (int b = 0; b < OBS_BATCH; ++b) {
+            const int k = k0 + b * stride;
+            skip[b] = k >= a.g.N || (a.solid && a.solid[k]);  // fluid nodes only
+            if (skip[b]) continue;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double fl = a.coupling ? (double)Flc[c * N + k] : 0.0;
-            const double uc = (double)u[c * N + k];
-            const double nc = (double)n[c * N + k];
-            bad |= !isfinite(fl) || !isfinite(uc) || !isfinite(nc);
-            F[c] += fl;
-            uu += uc * uc;
-            nn += nc * nc;
-            if (c == 2) nz = nc;
-        }
-        v[0] += rho;
-        v[1] += jx;
-        v[2] += jy;
-        v[3] += jz;
-        v[4] += F[0];
-        v[5] += F[1];
-        v[6] += F[2];
-        const double w = fmax(0.0, -nz);
-        if (w > 0.0 && ntubes > 0) {
-            const int x = k % a.g.nx;
-            const int y = (k / a.g.nx) % a.g.ny;
-            const int tube = nearest_tube((double)x, (double)y, a.g.nx, a.g.ny, ntubes, seed);
-            const double cx = cos(two_pi * x / a.g.nx), sx = sin(two_pi * x / a.g.nx);
-            const double cy = cos(two_pi * y / a.g.ny), sy = sin(two_pi * y / a.g.ny);
-            // unrolled selection keeps the per-tube sums in registers
+            for (int i = 0; i < 19; ++i) qv[b][i] = q[i * (size_t)a.g.qs + k];
 #pragma unroll
-            for (int t = 0; t < OBS_NT; ++t)
-                if (t == tube) {
-                    v[OBS_NBASE + 5 * t + 0] += w;
-                    v[OBS_NBASE + 5 * t + 1] += w * cx;
-                    v[OBS_NBASE + 5 * t + 2] += w * sx;
-                    v[OBS_NBASE + 5 * t + 3] += w * cy;
-                    v[OBS_NBASE + 5 * t + 4] += w * sy;
-                }
+            for (int c = 0; c < 3; ++c) {
+                fv[b][c] = a.coupling ? Flc[c * N + k] : T(0);
+                uv[b][c] = u[c * N + k];
+                nv[b][c] = n[c * N + k];
+            }
         }
-        v[OBS_NSUM + 0] = fmax(v[OBS_NSUM + 0], sqrt(uu));
-        v[OBS_NSUM + 1] = fmax(v[OBS_NSUM + 1], fabs(sqrt(nn) - 1.0));
-        if (bad) v[OBS_NSUM + 2] = 1.0;
+#pragma unroll
+        for (int b = 0; b < OBS_BATCH; ++b) {
+            if (skip[b]) continue;
+            const int k = k0 + b * stride;
+            double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+            bool bad = false;
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                const double qi = (double)qv[b][i];
+                bad |= !isfinite(qi);
+                s += qi;
+                jx += EX(i) * qi;
+                jy += EY(i) * qi;
+                jz += EZ(i) * qi;
+            }
+            const double rho = a.shifted ? 1.0 + s : s;
+            double F[3] = {rho * a.gx, rho * a.gy, rho * a.gz};
+            double uu = 0.0, nn = 0.0, nz = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double fl = (double)fv[b][c];
+                const double uc = (double)uv[b][c];
+                const double nc = (double)nv[b][c];
+                bad |= !isfinite(fl) || !isfinite(uc) || !isfinite(nc);
+                F[c] += fl;
+                uu += uc * uc;
+                nn += nc * nc;
+                if (c == 2) nz = nc;
+            }
+            v[0] += rho;
+            v[1] += jx;
+            v[2] += jy;
+            v[3] += jz;
+            v[4] += F[0];
+            v[5] += F[1];
+            v[6] += F[2];
+            const double w = fmax(0.0, -nz);
+            if (w > 0.0 && ntubes > 0) {
+                const int x = k % a.g.nx;
+                const int y = (k / a.g.nx) % a.g.ny;
+                const int tube = nearest_tube((double)x, (double)y, a.g.nx, a.g.ny, ntubes, seed);
+                const double cx = cos(two_pi * x / a.g.nx), sx = sin(two_pi * x / a.g.nx);
+                const double cy = cos(two_pi * y / a.g.ny), sy = sin(two_pi * y / a.g.ny);
+                // unrolled selection keeps the per-tube sums in registers
+#pragma unroll
+                for (int t = 0; t < OBS_NT; ++t)
+                    if (t == tube) {
+                        v[OBS_NBASE + 5 * t + 0] += w;
+                        v[OBS_NBASE + 5 * t + 1] += w * cx;
+                        v[OBS_NBASE + 5 * t + 2] += w * sx;
+                        v[OBS_NBASE + 5 * t + 3] += w * cy;
+                        v[OBS_NBASE + 5 * t + 4] += w * sy;
+                    }
+            }
+            v[OBS_NSUM + 0] = fmax(v[OBS_NSUM + 0], sqrt(uu));
+            v[OBS_NSUM + 1] = fmax(v[OBS_NSUM + 1], fabs(sqrt(nn) - 1.0));
+            if (bad) v[OBS_NSUM + 2] = 1.0;
+        }
     }
     block_reduce<OBS_NQ, OBS_NSUM>(v, lds);
     if (threadIdx.x == 0)
