@@ -222,47 +222,62 @@ static __global__ void __launch_bounds__(RED_THREADS) k_obs_final(const double* 
             v[j] = (j < OBS_NSUM) ? v[j] + partial[b * OBS_NQ + j] : fmax(v[j], partial[b * OBS_NQ + j]);
     block_reduce<OBS_NQ, OBS_NSUM>(v, lds);
     if (threadIdx.x == 0) {
+        // Thread 0 writes the results straight to the destinations; every
+        // per-tube loop is unrolled, so nothing goes through private memory.
         const double two_pi = 6.283185307179586476925286766559;
         int nt = drift ? drift->ntubes : ts.ntubes;
         if (nt < 1 || nt > EL_MAX_TUBES) nt = 0;
-        el_obs o;
-        o.mass = v[0];
-        o.mom[0] = v[1];
-        o.mom[1] = v[2];
-        o.mom[2] = v[3];
-        o.mom_phys[0] = v[1] + 0.5 * v[4];
-        o.mom_phys[1] = v[2] + 0.5 * v[5];
-        o.mom_phys[2] = v[3] + 0.5 * v[6];
-        o.max_u = v[OBS_NSUM + 0];
-        o.max_unit_dev = v[OBS_NSUM + 1];
-        o.nonfinite = v[OBS_NSUM + 2] > 0.0 ? 1 : 0;
-        o.ntubes = nt;
+        double cxs[EL_MAX_TUBES], cys[EL_MAX_TUBES];
+#pragma unroll
         for (int t = 0; t < EL_MAX_TUBES; ++t) {
             const double* tv = v + OBS_NBASE + 5 * t;
-            o.tube_weight[t] = tv[0];
-            for (int j = 0; j < 4; ++j) o.tube_cs[t][j] = tv[1 + j];
-            const double s0 = t < nt ? (drift ? drift->seed[t][0] : ts.s[t][0]) : 0.0;
-            const double s1 = t < nt ? (drift ? drift->seed[t][1] : ts.s[t][1]) : 0.0;
             if (tv[0] > 0.0) {
                 double cx = atan2(tv[2], tv[1]) * nx / two_pi;
                 double cy = atan2(tv[4], tv[3]) * ny / two_pi;
                 if (cx < 0) cx += nx;
                 if (cy < 0) cy += ny;
-                o.tube_centroid[t][0] = cx;
-                o.tube_centroid[t][1] = cy;
-            } else {
-                o.tube_centroid[t][0] = s0;
-                o.tube_centroid[t][1] = s1;
+                cxs[t] = cx;
+                cys[t] = cy;
+            } else {  // no weight: the tube keeps its seed
+                cxs[t] = t < nt ? (drift ? drift->seed[t][0] : ts.s[t][0]) : 0.0;
+                cys[t] = t < nt ? (drift ? drift->seed[t][1] : ts.s[t][1]) : 0.0;
             }
         }
-        if (out) *out = o;
+        el_obs* const dsts[2] = {out, drift ? &drift->obs : nullptr};
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            el_obs* o = dsts[d];
+            if (!o) continue;
+            o->mass = v[0];
+            o->mom[0] = v[1];
+            o->mom[1] = v[2];
+            o->mom[2] = v[3];
+            o->mom_phys[0] = v[1] + 0.5 * v[4];
+            o->mom_phys[1] = v[2] + 0.5 * v[5];
+            o->mom_phys[2] = v[3] + 0.5 * v[6];
+            o->max_u = v[OBS_NSUM + 0];
+            o->max_unit_dev = v[OBS_NSUM + 1];
+            o->nonfinite = v[OBS_NSUM + 2] > 0.0 ? 1 : 0;
+            o->ntubes = nt;
+#pragma unroll
+            for (int t = 0; t < EL_MAX_TUBES; ++t) {
+                o->tube_weight[t] = v[OBS_NBASE + 5 * t];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) o->tube_cs[t][j] = v[OBS_NBASE + 5 * t + 1 + j];
+                o->tube_centroid[t][0] = cxs[t];
+                o->tube_centroid[t][1] = cys[t];
+            }
+        }
         if (drift) {
-            drift->obs = o;
             const double L[2] = {(double)nx, (double)ny};
-            for (int t = 0; t < nt; ++t) {
-                const double c[2] = {o.tube_centroid[t][0], o.tube_centroid[t][1]};
+            const bool first = drift->ncalls == 0;
+#pragma unroll
+            for (int t = 0; t < EL_MAX_TUBES; ++t) {
+                if (t >= nt) continue;
+                const double c[2] = {cxs[t], cys[t]};
+#pragma unroll
                 for (int a = 0; a < 2; ++a) {
-                    if (drift->ncalls == 0) {
+                    if (first) {
                         drift->origin[t][a] = c[a];
                         drift->unwrapped[t][a] = c[a];
                         drift->displacement[t][a] = 0.0;
@@ -270,15 +285,15 @@ static __global__ void __launch_bounds__(RED_THREADS) k_obs_final(const double* 
                         // minimum-image change of the centroid since the last call
                         double last = fmod(drift->unwrapped[t][a], L[a]);
                         if (last < 0) last += L[a];
-                        double d = c[a] - last;
-                        d -= L[a] * floor(d / L[a] + 0.5);
-                        drift->unwrapped[t][a] += d;
+                        double dd = c[a] - last;
+                        dd -= L[a] * floor(dd / L[a] + 0.5);
+                        drift->unwrapped[t][a] += dd;
                         drift->displacement[t][a] = drift->unwrapped[t][a] - drift->origin[t][a];
                     }
                     drift->seed[t][a] = c[a];
                 }
             }
-            if (drift->ncalls == 0) drift->step0 = step;
+            if (first) drift->step0 = step;
             drift->step = step;
             drift->ncalls += 1;
         }
