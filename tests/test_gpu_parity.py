@@ -527,3 +527,26 @@ def test_q_padding_is_never_read():
         assert np.array_equal(a.get(name), b.get(name)), name
     oa, ob = a.observables(), b.observables()
     assert ob["nonfinite"] == 0 and oa["mass"] == ob["mass"] and np.array_equal(oa["mom"], ob["mom"])
+
+
+def test_streaming_store_span_kernel_matches_generic_kernel():
+    """A lattice whose q buffers exceed 320 MiB stores with streaming stores;
+    with nx not a multiple of 64 it takes the span kernel, and el_run forms
+    F^LC inside its LBM steps.  An all-fluid obstacle mask sends the same
+    lattice through the generic node kernel and the separate divergence pass:
+    the fields must agree bitwise (FP64-shifted, 200 x 200 x 56 fluid nodes,
+    2.24 M; 19 x 2,240,000 x 8 B = 340 MB per q buffer)."""
+    import torch
+    prob = inputs.channel(200, 200, 58, inputs.set_a(), g=(2e-6, 1e-6, 0.0), K=2e-3, q0=2 * math.pi / 12,
+                          fd_ratio=3)
+    n0 = inputs.director_tilt(prob, seed=23, amplitude=0.3)
+    plain = el.Lattice(prob, "f64_shifted", force_kernel="two_pass")  # two passes: el_run defers the second
+    plain.init_lattice(n0)
+    plain.run(7)
+    generic = el.Lattice(prob, "f64_shifted", solid=np.zeros(prob.shape(1)[1:], dtype=np.uint8))
+    generic.init_lattice(n0)
+    generic.run(7)
+    torch.cuda.synchronize()
+    assert 19 * plain.qs * 8 > 320 * 2 ** 20
+    for name in ("q", "n", "u", "F"):
+        assert np.array_equal(plain.get(name), generic.get(name)), name
