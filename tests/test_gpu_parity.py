@@ -120,17 +120,24 @@ def test_row_shapes_match_oracle(nx, ny):
     assert rel_l2(lat32.get("u"), lat.get("u")) < 1e-4
 
 
-def test_step_calls_compose_to_run():
+@pytest.mark.parametrize("nx,ny,nz,r,T", [(20, 9, 10, 1, 12), (128, 128, 64, 10, 25), (64, 6, 8, 3, 9)])
+def test_step_calls_compose_to_run(nx, ny, nz, r, T):
     """el_step_lbm / el_moments / el_step_director in the order of the hybrid
-    loop give bitwise the same state as el_run."""
+    loop give bitwise the same state as el_run, which forms F^LC inside the LBM
+    step after each FD step: on spans (nx = 20) and on whole rows (nx = 64,
+    128, the headline channel), ending inside an FD interval and on one."""
     prob, n0, _ = inputs.workload_c1()
-    prob = prob.with_(nx=20, ny=9, nz=10, fd_ratio=1)
-    a = _gpu(prob, n0 := inputs.director_tilt(prob, seed=5), "f32_shifted", 12)
+    prob = prob.with_(nx=nx, ny=ny, nz=nz, fd_ratio=r, K=1e-3)
+    a = _gpu(prob, n0 := inputs.director_tilt(prob, seed=5), "f32_shifted", T)
     b = el.Lattice(prob, "f32_shifted")
     b.init_lattice(n0)
-    for _ in range(12):
-        b.step_lbm(1, write_u=True)
-        b.step_director()
+    done = 0
+    while done < T:
+        n = min(r - b.step % r, T - done)
+        b.step_lbm(n, write_u=True)
+        done += n
+        if b.step % r == 0:
+            b.step_director()
     for name in ("q", "n", "u", "F"):
         assert np.array_equal(a.get(name), b.get(name)), name
 
