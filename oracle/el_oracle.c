@@ -10,8 +10,8 @@
  * Compiled with -O2 -ffp-contract=off.  The optional OpenMP pragmas only split
  * independent z-planes; every value is independent of the thread count.
  *
- * Readings of points the paper leaves open (each one is a choice, listed with
- * its reason in the design notes of the repository):
+ * Readings of points the paper leaves open (each one is a choice of
+ * reading, made where the paper is silent or ambiguous):
  *   R1  the finite-difference force carries alpha4' as given; alpha4 itself
  *       is informational.
  *   R3  the Laplacian in h is the compact 3-point stencil per axis; first
