@@ -36,7 +36,8 @@ int basic_checks(const el_params* p)
     if (p->nx < 3 || p->ny < 3 || (periodic_z(p) ? p->nz < 3 : p->nz < 4))
         return fail(EL_EINVAL, "lattice %dx%dx%d too small", p->nx, p->ny, p->nz);
     const long long N = (long long)p->nx * p->ny * nzf_of(p);
-    if (N * 19 >= (1LL << 31)) return fail(EL_EINVAL, "lattice of %lld fluid nodes exceeds 32-bit offsets", N);
+    const long long qs = (N + EL_Q_ALIGN - 1) / EL_Q_ALIGN * EL_Q_ALIGN;
+    if (qs * 19 >= (1LL << 31)) return fail(EL_EINVAL, "lattice of %lld fluid nodes exceeds 32-bit offsets", N);
     if (!(p->tau > 0.5)) return fail(EL_EINVAL, "tau = %g must exceed 1/2", p->tau);
     if (p->fd_ratio < 1) return fail(EL_EINVAL, "fd_ratio = %d must be >= 1", p->fd_ratio);
     const double gamma1 = p->alpha[2] - p->alpha[1];
