@@ -220,7 +220,7 @@ const char* el_last_error(void);
 size_t el_buffer_bytes(const el_params* p, int32_t which);
 
 /* Checks the parameters.  EL_EINVAL: sizes (nx, ny >= 3; nz >= 4, or >= 3
- * with EL_PERIODIC_Z), tau <= 1/2, r < 1, gamma1 = alpha3 - alpha2 <= 0 with
+ * with EL_PERIODIC_Z; 19 qs < 2^31, the offsets being 32-bit), tau <= 1/2, r < 1, gamma1 = alpha3 - alpha2 <= 0 with
  * coupling, unknown precision or flags, both force-kernel flags, EL_FRANK3
  * with a negative or non-finite K11, K22 or K33.  EL_EUNSTABLE (unless
  * EL_ALLOW_UNSTABLE): r * 12 K / gamma1 > 2 (the explicit Heun step on the
