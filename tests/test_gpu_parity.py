@@ -557,3 +557,33 @@ def test_streaming_store_span_kernel_matches_generic_kernel():
     assert 19 * plain.qs * 8 > 320 * 2 ** 20
     for name in ("q", "n", "u", "F"):
         assert np.array_equal(plain.get(name), generic.get(name)), name
+
+
+@pytest.mark.parametrize("variant", ["frank3", "frozen"])
+def test_el_run_forms_the_force_like_separate_calls(variant):
+    """el_run leaves the stress divergence to the LBM step after each FD step
+    also for the three-constant stress and for a frozen director (the FD step
+    only refreshes F^LC): bitwise the same state as the separate calls."""
+    import torch
+    prob, n0, _ = inputs.workload_c3_frank3(r=3)
+    prob = prob.with_(nx=40, ny=24, nz=12)
+    n0 = inputs.director_tilt(prob, seed=9, amplitude=0.3)
+    frozen = variant == "frozen"
+    if frozen:
+        prob = prob.with_(frank3=False, K=5e-3)
+    T, r = 14, prob.fd_ratio
+    a = el.Lattice(prob, "f32_shifted", freeze_director=frozen)
+    a.init_lattice(n0)
+    a.run(T)
+    b = el.Lattice(prob, "f32_shifted", freeze_director=frozen)
+    b.init_lattice(n0)
+    done = 0
+    while done < T:
+        n = min(r - b.step % r, T - done)
+        b.step_lbm(n, write_u=True)
+        done += n
+        if b.step % r == 0:
+            b.step_director()
+    torch.cuda.synchronize()
+    for name in ("q", "n", "u", "F"):
+        assert np.array_equal(a.get(name), b.get(name)), name
