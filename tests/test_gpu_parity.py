@@ -99,12 +99,13 @@ def test_ragged_lattice_all_terms_fp64():
         assert rel_l2(lat.get("F"), o.get("F")) < 1e-10
 
 
-@pytest.mark.parametrize("nx,ny", [(300, 4), (37, 11), (64, 5), (300, 100)])
+@pytest.mark.parametrize("nx,ny", [(300, 4), (37, 11), (64, 5), (300, 100), (1100, 3)])
 def test_row_shapes_match_oracle(nx, ny):
     """The LBM kernels' block shapes: 256-node spans over short rows, cut
     anywhere (37), one row of a whole number of wavefronts per block (64),
     rows longer than a span, whose x-moving populations cross span ends
-    (300); 300x100 planes are large enough for the FD kernels to visit them
+    (300; 1100, more than four spans and longer than a block can hold);
+    300x100 planes are large enough for the FD kernels to visit them
     in y-strips of 13 rows (the last one ragged).  FP64 against the oracle,
     FP32-shifted against FP64 on the GPU."""
     prob = inputs.channel(nx, ny, 7, inputs.set_a(), g=(2e-6, 1e-6, 0.0), K=2e-3, q0=2 * math.pi / 12,
