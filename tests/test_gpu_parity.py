@@ -119,6 +119,14 @@ def test_row_shapes_match_oracle(nx, ny):
     assert rel_l2(lat.get("n"), o.get("n")) < 1e-12
     lat32 = _gpu(prob, n0, "f32_shifted", 9)
     assert rel_l2(lat32.get("u"), lat.get("u")) < 1e-4
+    # the unshifted distribution through the same kernels (FP64 exact to
+    # rounding; FP32 loses about max|q|/|u| ulps in the moments)
+    lat64p = _gpu(prob, n0, "f64", 9)
+    lat32p = _gpu(prob, n0, "f32", 9)
+    e64p, e32p = rel_l2(lat64p.get("u"), lat.get("u")), rel_l2(lat32p.get("u"), lat.get("u"))
+    _say(f"rows {nx}x{ny}: unshifted f64 {e64p:.2e}, f32 {e32p:.2e}")
+    # measured 4.7e-14 to 4.9e-14 and 2.5e-5 to 2.6e-5 on these five shapes
+    assert e64p < 1e-12 and e32p < 3e-4
 
 
 @pytest.mark.parametrize("nx,ny,nz,r,T", [(20, 9, 10, 1, 12), (128, 128, 64, 10, 25), (64, 6, 8, 3, 9)])
